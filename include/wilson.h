@@ -1,0 +1,212 @@
+/*
+ * wilson.h -- C ABI of the MI355X (gfx950) Wilson-operator library.
+ *
+ * The library applies the Wilson hopping term of Eq. (1) of the paper
+ * (Sec. 2),
+ *
+ *   (H phi)(x) = sum_{mu=0..3} [ U_mu(x) (1 - gamma_mu) phi(x + mu)
+ *                              + U_mu(x - mu)^+ (1 + gamma_mu) phi(x - mu) ],
+ *
+ * in the half-spinor form of Eq. (2), and solves with it.  Everything runs on
+ * one GPU with hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2; direction
+ *   mu = 0, 1, 2, 3 is x, y, z, t; lexicographic site index
+ *   lex = x + Lx (y + Ly (z + Lz t)); parity (x + y + z + t) mod 2; V sites,
+ *   Vh = V / 2 per parity.
+ * Gamma matrices: chiral basis, gamma_mu = [[0, A_mu], [A_mu^+, 0]] with
+ *   A = (-i sigma_1, -i sigma_2, -i sigma_3, -1) for mu = x, y, z, t;
+ *   gamma_5 = diag(1, 1, -1, -1).
+ * Boundary phases: phases[2 mu], phases[2 mu + 1] = (re, im) of z_mu.  A
+ *   forward hop that wraps in direction mu (x_mu = L_mu - 1 -> 0) is multiplied
+ *   by z_mu, a backward hop that wraps (x_mu = 0 -> L_mu - 1) by conj(z_mu).
+ *   Periodic = (1, 0), antiperiodic = (-1, 0).
+ * Canonical fields (what a user hands in and gets back), FP64, complex
+ *   interleaved (re, im), array-of-structures:
+ *     gauge        [lex][mu 4][row 3][col 3]                 (V * 72 doubles)
+ *     spinor FULL  [rhs][lex][spin 4][colour 3]              (nrhs * V * 24 doubles)
+ *     spinor EVEN / ODD  [rhs][i][spin 4][colour 3], i = 0 .. Vh-1 the sites of
+ *                  that parity in increasing lex order (i = lex >> 1).
+ * Internal fields: the layout the kernels use (site-major structure of
+ *   arrays, right-hand side innermost).  Their size comes from
+ *   wl_spinor_bytes(); their content is only meaningful to this library.  A
+ *   FULL internal field is the EVEN half followed by the ODD half.
+ *
+ * Ownership: the caller allocates every field buffer passed to an entry point
+ * (device memory, e.g. torch.empty(..., device="cuda")) and keeps ownership;
+ * the library never frees caller memory.  A wl_ctx owns its gauge-field copies
+ * and its solver workspace.
+ *
+ * Streams: every call is enqueued asynchronously on the given HIP stream
+ * (0 = the null stream) unless stated otherwise.  Calls on one context are not
+ * thread-safe.
+ *
+ * Errors: every function returns a wl_status; none throws or aborts.  A
+ * negative status means nothing was enqueued (argument errors) or a HIP call
+ * failed; wl_last_error() then returns a message (thread-local).  Positive
+ * statuses come from solvers that ran: the result is filled in and the info
+ * struct says how far they got.
+ */
+#ifndef WILSON_H
+#define WILSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WL_OK = 0,
+    WL_NOT_CONVERGED = 1,   /* solver hit maxiter; x and info are filled in            */
+    WL_BREAKDOWN = 2,       /* NaN/Inf or non-positive <p, A p>; x holds the last iterate */
+    WL_ERR_ARG = -1,        /* bad argument (null / aliased / misaligned pointer, enum) */
+    WL_ERR_DIMS = -2,       /* odd, zero or too large extents                          */
+    WL_ERR_HIP = -3,        /* a HIP runtime call failed                               */
+    WL_ERR_NOMEM = -4,      /* device allocation failed                                */
+    WL_ERR_UNSUPPORTED = -5 /* valid but unsupported combination                       */
+} wl_status;
+
+/* Storage precision of internal spinor and link fields.  Arithmetic is FP64 for
+ * WL_F64 and FP32 for all others.  The 16-bit formats store each spinor point
+ * scaled by its own FP32 norm s = max |component| (s = 0 stores zeros). */
+typedef enum { WL_F64 = 0, WL_F32 = 1, WL_F16N = 2, WL_BF16N = 3 } wl_prec;
+
+typedef enum { WL_EVEN = 0, WL_ODD = 1, WL_FULL = 2 } wl_subset;
+
+/* Operators M of the solver:
+ *   WL_OP_D     D = 1 - kappa H on the full lattice
+ *   WL_OP_DHAT  D_hat = 1 - kappa^2 H_eo H_oe on the even sites (Schur complement) */
+typedef enum { WL_OP_D = 0, WL_OP_DHAT = 1 } wl_op;
+
+typedef struct wl_ctx wl_ctx;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on the current HIP device.
+ *   dims      : {Lx, Ly, Lz, Lt}, all even, >= 2, V <= 2^28.
+ *   phases    : 8 doubles, boundary phases z_mu as (re, im).
+ *   gauge_host: canonical FP64 gauge field in HOST memory (V * 72 doubles); it is
+ *               uploaded and converted once; the caller's buffer is not kept.
+ * The FP64 18-real link copy is built here; other link formats are built on
+ * first use (or by wl_ctx_prepare_links).  Synchronous. */
+wl_status wl_ctx_create(const int dims[4], const double phases[8],
+                        const double *gauge_host, wl_ctx **out);
+wl_status wl_ctx_destroy(wl_ctx *ctx);
+
+/* Build the link copy used by kernels of storage precision `prec` with
+ * `recon` = 18 (all 9 complex entries) or 12 (two rows; the third is rebuilt
+ * as the complex conjugate of their cross product).  Synchronous. */
+wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
+
+/* Bytes of an internal spinor field of `nrhs` right-hand sides. */
+wl_status wl_spinor_bytes(const wl_ctx *ctx, wl_subset subset, wl_prec prec,
+                          int nrhs, size_t *bytes);
+
+/* canonical FP64 (device) -> internal (device), and back.  For the 16-bit
+ * formats pack computes the per-point norm and rounds to nearest even. */
+wl_status wl_pack_spinor(const wl_ctx *ctx, void *dst_internal, const double *src_canonical,
+                         wl_subset subset, wl_prec prec, int nrhs, void *stream);
+wl_status wl_unpack_spinor(const wl_ctx *ctx, double *dst_canonical, const void *src_internal,
+                           wl_subset subset, wl_prec prec, int nrhs, void *stream);
+
+/* internal -> internal with a change of storage precision. */
+wl_status wl_convert_spinor(const wl_ctx *ctx, void *dst, wl_prec dst_prec, const void *src,
+                            wl_prec src_prec, wl_subset subset, int nrhs, void *stream);
+
+/* ---------------------------------------------------------------- operators */
+
+/* out = H in  (Eq. (1)), evaluated through the half-spinor form of Eq. (2).
+ *   out_subset = WL_EVEN : out (even field) = H_eo in (in: odd field)
+ *   out_subset = WL_ODD  : out (odd field)  = H_oe in (in: even field)
+ *   out_subset = WL_FULL : out (full field) = H in    (in: full field)
+ * prec/recon select the storage of spinors and links; out and in must not
+ * overlap. */
+wl_status wl_dslash_apply(const wl_ctx *ctx, void *out, const void *in, wl_subset out_subset,
+                          wl_prec prec, int recon, int nrhs, void *stream);
+
+/* out = H^+ in: Eq. (1) with (1 + gamma_mu) on the forward and (1 - gamma_mu)
+ * on the backward neighbour (H^+ = gamma_5 H gamma_5).  Arguments as above. */
+wl_status wl_dslash_dagger_apply(const wl_ctx *ctx, void *out, const void *in,
+                                 wl_subset out_subset, wl_prec prec, int recon, int nrhs,
+                                 void *stream);
+
+/* out = M in or M^+ in for op = WL_OP_D (FULL fields) or WL_OP_DHAT (EVEN
+ * fields).  Uses a context-owned odd-parity temporary for WL_OP_DHAT. */
+wl_status wl_dirac_apply(wl_ctx *ctx, void *out, const void *in, wl_op op, int dagger,
+                         double kappa, wl_prec prec, int recon, int nrhs, void *stream);
+
+/* Even/odd helpers for solving D x = b through D_hat:
+ *   wl_eo_prepare     : bhat_e = b_e + kappa H_eo b_o
+ *   wl_eo_reconstruct : x_o    = b_o + kappa H_oe x_e
+ * All fields are half (EVEN or ODD) internal fields of precision prec. */
+wl_status wl_eo_prepare(const wl_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o,
+                        double kappa, wl_prec prec, int recon, int nrhs, void *stream);
+wl_status wl_eo_reconstruct(const wl_ctx *ctx, void *x_o, const void *x_e, const void *b_o,
+                            double kappa, wl_prec prec, int recon, int nrhs, void *stream);
+
+/* ---------------------------------------------------------------- BLAS-1 */
+
+/* y = a x + y on internal fields (real a).  */
+wl_status wl_blas_axpy(const wl_ctx *ctx, double a, const void *x, void *y, wl_subset subset,
+                       wl_prec prec, int nrhs, void *stream);
+/* result[2] (host) = <x, y> = sum conj(x) y, accumulated in FP64 in a fixed
+ * order (bitwise reproducible).  Synchronises the stream. */
+wl_status wl_blas_dot(const wl_ctx *ctx, const void *x, const void *y, wl_subset subset,
+                      wl_prec prec, int nrhs, double result[2], void *stream);
+/* *result (host) = ||x||^2, FP64, fixed order.  Synchronises the stream. */
+wl_status wl_blas_norm2(const wl_ctx *ctx, const void *x, wl_subset subset, wl_prec prec,
+                        int nrhs, double *result, void *stream);
+
+/* ---------------------------------------------------------------- solvers */
+
+typedef struct {
+    double tol;          /* stop when ||b - A x|| <= tol ||b|| (A = M^+ M)            */
+    int maxiter;         /* total iteration cap (all restarts)                        */
+    int check_every;     /* iterations enqueued between host-side convergence reads  */
+    int max_restarts;    /* true-residual restarts after the iterated residual converged */
+    wl_prec prec;        /* storage of the inner iteration (WL_F64 = plain FP64 CG)   */
+    int recon;           /* 18 or 12                                                  */
+    int reliable_every;  /* mixed precision: FP64 residual refresh every this many iters */
+    double reliable_delta; /* mixed precision: also refresh when ||r|| < delta * max ||r|| */
+    int use_graph;       /* capture the iteration block in a hipGraph and replay it    */
+} wl_solver_params;
+
+typedef struct {
+    int iters;            /* iterations performed (all restarts)       */
+    int restarts;         /* true-residual restarts                    */
+    int reliable_updates; /* FP64 residual refreshes (mixed precision) */
+    double rel_resid;     /* final iterated relative residual          */
+    double true_rel_resid;/* final ||b - A x|| / ||b|| recomputed in FP64 */
+    double seconds;       /* wall time of the solve                    */
+} wl_solver_info;
+
+/* Fill in defaults: tol 1e-10, maxiter 100000, check_every 25, max_restarts 5,
+ * prec WL_F64, recon 18, reliable_every 100, reliable_delta 0.1, no graph. */
+void wl_solver_params_default(wl_solver_params *p);
+
+/* Conjugate gradient on the normal equations M^+ M x = b, M = D or D_hat.
+ *   x : in: initial guess, out: solution (internal FP64 field of the op's subset)
+ *   b : right-hand side (internal FP64 field), not modified
+ *   nrhs right-hand sides are solved as independent systems sharing every
+ *   operator application; each stops on its own residual.
+ * Synchronous: returns when done.  info may be NULL (else nrhs entries). */
+wl_status wl_cg_solve(wl_ctx *ctx, void *x, const void *b, wl_op op, double kappa, int nrhs,
+                      const wl_solver_params *params, wl_solver_info *info, void *stream);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *wl_last_error(void);
+
+/* Library version string. */
+const char *wl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WILSON_H */

@@ -1,0 +1,905 @@
+// C ABI of the Wilson library: context, field conversion, operators, BLAS and
+// the conjugate-gradient driver.  All arithmetic happens in the kernels of
+// wl_dslash.hip and wl_blas.hip; this file validates arguments, owns device
+// memory and enqueues launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wilson.h"
+#include "wl_blas.h"
+#include "wl_dslash.h"
+
+using namespace wl;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static wl_status fail(wl_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(call)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(WL_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ context
+namespace {
+enum Slot {
+    S_TMP_OP = 0,  // odd temporary of wl_dirac_apply
+    S_R, S_P, S_Q, S_S, S_TMP,           // solver fields in the inner precision
+    S_RHI, S_THI, S_TMPHI,               // FP64 fields for true residuals
+    S_PARTIALS, S_SCAL, S_BNORM, S_FLAG,
+    S_NSLOTS
+};
+}
+
+struct wl_ctx {
+    int dims[4];
+    double phases[8];
+    long V, Vh;
+    int device;
+    Geom g;
+    void *gauge[4][2] = {};  // [prec][recon == 12]
+    size_t slab[4][2] = {};
+    void *buf[S_NSLOTS] = {};
+    size_t buf_bytes[S_NSLOTS] = {};
+    void *host_pinned = nullptr;
+    size_t host_pinned_bytes = 0;
+    LaunchCfg cfg;
+};
+
+static bool prec_ok(int p) { return p >= WL_F64 && p <= WL_BF16N; }
+static bool recon_ok(int prec, int r) {
+    if (r != 12 && r != 18) return false;
+    if ((prec == WL_F16N || prec == WL_BF16N) && r != 12) return false;
+    return true;
+}
+
+static size_t half_bytes(const wl_ctx *c, int prec, int nrhs) {
+    return spinor_point_bytes(prec) * (size_t)c->Vh * (size_t)nrhs;
+}
+
+static wl_status ensure_buf(wl_ctx *c, int slot, size_t bytes) {
+    if (c->buf_bytes[slot] >= bytes) return WL_OK;
+    if (c->buf[slot]) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(c->buf[slot]));
+        c->buf[slot] = nullptr;
+        c->buf_bytes[slot] = 0;
+    }
+    hipError_t e = hipMalloc(&c->buf[slot], bytes);
+    if (e != hipSuccess) {
+        c->buf[slot] = nullptr;
+        (void)hipGetLastError();
+        return fail(WL_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->buf_bytes[slot] = bytes;
+    return WL_OK;
+}
+
+static wl_status ensure_pinned(wl_ctx *c, size_t bytes) {
+    if (c->host_pinned_bytes >= bytes) return WL_OK;
+    if (c->host_pinned) HIP_TRY(hipHostFree(c->host_pinned));
+    c->host_pinned = nullptr;
+    c->host_pinned_bytes = 0;
+    HIP_TRY(hipHostMalloc(&c->host_pinned, bytes, hipHostMallocDefault));
+    c->host_pinned_bytes = bytes;
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ small kernels (layout conversion)
+// canonical FP64 spinor <-> internal, one thread per internal point
+template <int SP>
+__global__ void __launch_bounds__(256) k_pack(Geom g, void *dst, size_t half_bytes, const double *src, int subset,
+                                              int nrhs) {
+    using T = typename SpinorIO<SP>::real;
+    const int h = blockIdx.y;
+    const long n = (long)g.vh * nrhs;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n) return;
+    const int i = (int)(gid / nrhs), rhs = (int)(gid - (long)i * nrhs);
+    const int par = subset == WL_FULL ? h : subset;
+    long idx, nsite;
+    if (subset == WL_FULL) {
+        int c[4];
+        eo_coords(g, i, par, c);
+        idx = c[0] + (long)g.L[0] * (c[1] + (long)g.L[1] * (c[2] + (long)g.L[2] * c[3]));
+        nsite = 2L * g.vh;
+    } else {
+        idx = i;
+        nsite = g.vh;
+    }
+    const double *s = src + ((long)rhs * nsite + idx) * 24;
+    cpx<T> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = {(T)s[2 * k], (T)s[2 * k + 1]};
+    SpinorIO<SP>::store((char *)dst + h * half_bytes, n, gid, v);
+}
+
+template <int SP>
+__global__ void __launch_bounds__(256) k_unpack(Geom g, double *dst, const void *src, size_t half_bytes, int subset,
+                                                int nrhs) {
+    using T = typename SpinorIO<SP>::real;
+    const int h = blockIdx.y;
+    const long n = (long)g.vh * nrhs;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n) return;
+    const int i = (int)(gid / nrhs), rhs = (int)(gid - (long)i * nrhs);
+    const int par = subset == WL_FULL ? h : subset;
+    long idx, nsite;
+    if (subset == WL_FULL) {
+        int c[4];
+        eo_coords(g, i, par, c);
+        idx = c[0] + (long)g.L[0] * (c[1] + (long)g.L[1] * (c[2] + (long)g.L[2] * c[3]));
+        nsite = 2L * g.vh;
+    } else {
+        idx = i;
+        nsite = g.vh;
+    }
+    cpx<T> v[12];
+    SpinorIO<SP>::load((const char *)src + h * half_bytes, n, gid, v);
+    double *d = dst + ((long)rhs * nsite + idx) * 24;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        d[2 * k] = (double)v[k].re;
+        d[2 * k + 1] = (double)v[k].im;
+    }
+}
+
+// FP64 18-real internal links -> another link format, one thread per (slab, site)
+template <int GP, int R>
+__global__ void __launch_bounds__(256) k_link_convert(void *dst, size_t dslab, const void *src, size_t sslab,
+                                                      int vh) {
+    using T = typename LinkIO<GP, R>::real;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int slab = blockIdx.y;
+    if (i >= vh) return;
+    cpx<double> u[9];
+    LinkIO<WL_F64, 18>::load((const char *)src + slab * sslab, vh, i, u);
+    cpx<T> w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = {(T)u[k].re, (T)u[k].im};
+    LinkIO<GP, R>::store((char *)dst + slab * dslab, vh, i, w);
+}
+
+template <template <int> class K, typename... A>
+static hipError_t launch_prec(int prec, dim3 grid, hipStream_t s, A... args) {
+    switch (prec) {
+    case WL_F64: hipLaunchKernelGGL(K<WL_F64>::fn, grid, dim3(256), 0, s, args...); break;
+    case WL_F32: hipLaunchKernelGGL(K<WL_F32>::fn, grid, dim3(256), 0, s, args...); break;
+    case WL_F16N: hipLaunchKernelGGL(K<WL_F16N>::fn, grid, dim3(256), 0, s, args...); break;
+    case WL_BF16N: hipLaunchKernelGGL(K<WL_BF16N>::fn, grid, dim3(256), 0, s, args...); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template <int SP> struct PackK { static constexpr auto fn = k_pack<SP>; };
+template <int SP> struct UnpackK { static constexpr auto fn = k_unpack<SP>; };
+
+// ------------------------------------------------------------------ validation helpers
+static wl_status check_field_args(const wl_ctx *c, int subset, int prec, int nrhs) {
+    if (!c) return fail(WL_ERR_ARG, "null context");
+    if (subset < WL_EVEN || subset > WL_FULL) return fail(WL_ERR_ARG, "bad subset %d", subset);
+    if (!prec_ok(prec)) return fail(WL_ERR_ARG, "bad precision %d", prec);
+    if (nrhs < 1 || nrhs > 64) return fail(WL_ERR_ARG, "nrhs %d outside [1, 64]", nrhs);
+    return WL_OK;
+}
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+static wl_status get_links(wl_ctx *c, int prec, int recon, const void **ptr, size_t *slab);
+
+// ------------------------------------------------------------------ context API
+extern "C" const char *wl_last_error(void) { return g_err.c_str(); }
+extern "C" const char *wl_version(void) { return "wilson-gfx950 0.1"; }
+
+extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], const double *gauge_host,
+                                   wl_ctx **out) {
+    g_err.clear();
+    if (!dims || !phases || !gauge_host || !out) return fail(WL_ERR_ARG, "null argument");
+    *out = nullptr;
+    long V = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (dims[m] < 2 || dims[m] % 2 || dims[m] > 4096)
+            return fail(WL_ERR_DIMS, "extent %d of direction %d must be even and in [2, 4096]", dims[m], m);
+        V *= dims[m];
+        if (V > (1L << 28)) return fail(WL_ERR_DIMS, "volume exceeds 2^28 sites");
+    }
+    for (int k = 0; k < 8; ++k)
+        if (!std::isfinite(phases[k])) return fail(WL_ERR_ARG, "non-finite boundary phase");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(WL_ERR_HIP, "no HIP device available (%s)", hipGetErrorString(e));
+    }
+    wl_ctx *c = new wl_ctx();
+    std::memcpy(c->dims, dims, sizeof c->dims);
+    std::memcpy(c->phases, phases, sizeof c->phases);
+    c->V = V;
+    c->Vh = V / 2;
+    HIP_TRY(hipGetDevice(&c->device));
+    Geom &g = c->g;
+    for (int m = 0; m < 4; ++m) g.L[m] = dims[m];
+    g.lxh = dims[0] / 2;
+    g.vh = (int)c->Vh;
+    g.sy = g.lxh;
+    g.sz = g.lxh * dims[1];
+    g.st = g.lxh * dims[1] * dims[2];
+    g.phase_mask = 0;
+    for (int m = 0; m < 4; ++m) {
+        g.zr[m] = phases[2 * m];
+        g.zi[m] = phases[2 * m + 1];
+        if (!(phases[2 * m] == 1.0 && phases[2 * m + 1] == 0.0)) g.phase_mask |= 1 << m;
+    }
+    // host packing of the canonical FP64 gauge field into the FP64 18-real internal layout
+    const size_t slab = LinkIO<WL_F64, 18>::bytes_per_link * (size_t)c->Vh;
+    std::vector<double> host(slab / sizeof(double) * 8);
+    for (long lex = 0; lex < V; ++lex) {
+        long r = lex;
+        const int x = (int)(r % dims[0]);
+        r /= dims[0];
+        const int y = (int)(r % dims[1]);
+        r /= dims[1];
+        const int z = (int)(r % dims[2]);
+        const int t = (int)(r / dims[2]);
+        const int par = (x + y + z + t) & 1;
+        const long i = lex >> 1;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int k = 0; k < 9; ++k) {
+                const double *src = gauge_host + ((lex * 4 + mu) * 9 + k) * 2;
+                double *dst = host.data() + (((size_t)(par * 4 + mu) * 9 + k) * c->Vh + i) * 2;
+                dst[0] = src[0];
+                dst[1] = src[1];
+            }
+    }
+    void *d = nullptr;
+    e = hipMalloc(&d, slab * 8);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(WL_ERR_NOMEM, "hipMalloc of gauge field failed: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(d, host.data(), slab * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        delete c;
+        return fail(WL_ERR_HIP, "gauge upload failed: %s", hipGetErrorString(e));
+    }
+    c->gauge[WL_F64][0] = d;
+    c->slab[WL_F64][0] = slab;
+    *out = c;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ctx_destroy(wl_ctx *c) {
+    if (!c) return WL_OK;
+    (void)hipDeviceSynchronize();
+    for (int p = 0; p < 4; ++p)
+        for (int r = 0; r < 2; ++r)
+            if (c->gauge[p][r]) (void)hipFree(c->gauge[p][r]);
+    for (int s = 0; s < S_NSLOTS; ++s)
+        if (c->buf[s]) (void)hipFree(c->buf[s]);
+    if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    delete c;
+    return WL_OK;
+}
+
+static wl_status get_links(wl_ctx *c, int prec, int recon, const void **ptr, size_t *slab) {
+    if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "link format prec %d / recon %d not supported", prec, recon);
+    const int ri = recon == 12 ? 1 : 0;
+    if (!c->gauge[prec][ri]) {
+        const size_t sl = link_bytes(prec, recon) * (size_t)c->Vh;
+        void *d = nullptr;
+        hipError_t e = hipMalloc(&d, sl * 8);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(WL_ERR_NOMEM, "hipMalloc of link copy failed: %s", hipGetErrorString(e));
+        }
+        dim3 grid((unsigned)((c->Vh + 255) / 256), 8);
+        const void *src = c->gauge[WL_F64][0];
+        const size_t ss = c->slab[WL_F64][0];
+        const int vh = (int)c->Vh;
+        if (prec == WL_F64 && recon == 12) hipLaunchKernelGGL((k_link_convert<WL_F64, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
+        else if (prec == WL_F32 && recon == 18) hipLaunchKernelGGL((k_link_convert<WL_F32, 18>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
+        else if (prec == WL_F32 && recon == 12) hipLaunchKernelGGL((k_link_convert<WL_F32, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
+        else if (prec == WL_F16N) hipLaunchKernelGGL((k_link_convert<WL_F16N, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
+        else if (prec == WL_BF16N) hipLaunchKernelGGL((k_link_convert<WL_BF16N, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipDeviceSynchronize());
+        c->gauge[prec][ri] = d;
+        c->slab[prec][ri] = sl;
+    }
+    *ptr = c->gauge[prec][ri];
+    *slab = c->slab[prec][ri];
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ctx_prepare_links(wl_ctx *c, wl_prec prec, int recon) {
+    g_err.clear();
+    if (!c) return fail(WL_ERR_ARG, "null context");
+    if (!prec_ok(prec)) return fail(WL_ERR_ARG, "bad precision %d", (int)prec);
+    const void *p;
+    size_t s;
+    return get_links(c, prec, recon, &p, &s);
+}
+
+extern "C" wl_status wl_spinor_bytes(const wl_ctx *c, wl_subset subset, wl_prec prec, int nrhs, size_t *bytes) {
+    g_err.clear();
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!bytes) return fail(WL_ERR_ARG, "null output");
+    *bytes = half_bytes(c, prec, nrhs) * (subset == WL_FULL ? 2 : 1);
+    return WL_OK;
+}
+
+extern "C" wl_status wl_pack_spinor(const wl_ctx *c, void *dst, const double *src, wl_subset subset, wl_prec prec,
+                                    int nrhs, void *stream) {
+    g_err.clear();
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!dst || !src) return fail(WL_ERR_ARG, "null field pointer");
+    if (!aligned16(dst) || !aligned16(src)) return fail(WL_ERR_ARG, "field pointers must be 16-byte aligned");
+    const int nh = subset == WL_FULL ? 2 : 1;
+    const size_t hb = half_bytes(c, prec, nrhs);
+    if (overlap(dst, hb * nh, src, (size_t)c->Vh * nh * nrhs * 24 * 8)) return fail(WL_ERR_ARG, "dst and src overlap");
+    dim3 grid((unsigned)((c->Vh * nrhs + 255) / 256), nh);
+    HIP_TRY((launch_prec<PackK>(prec, grid, (hipStream_t)stream, c->g, dst, hb, src, (int)subset, nrhs)));
+    return WL_OK;
+}
+
+extern "C" wl_status wl_unpack_spinor(const wl_ctx *c, double *dst, const void *src, wl_subset subset, wl_prec prec,
+                                      int nrhs, void *stream) {
+    g_err.clear();
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!dst || !src) return fail(WL_ERR_ARG, "null field pointer");
+    if (!aligned16(dst) || !aligned16(src)) return fail(WL_ERR_ARG, "field pointers must be 16-byte aligned");
+    const int nh = subset == WL_FULL ? 2 : 1;
+    const size_t hb = half_bytes(c, prec, nrhs);
+    if (overlap(dst, (size_t)c->Vh * nh * nrhs * 24 * 8, src, hb * nh)) return fail(WL_ERR_ARG, "dst and src overlap");
+    dim3 grid((unsigned)((c->Vh * nrhs + 255) / 256), nh);
+    HIP_TRY((launch_prec<UnpackK>(prec, grid, (hipStream_t)stream, c->g, dst, src, hb, (int)subset, nrhs)));
+    return WL_OK;
+}
+
+static VecArgs vec_args(const wl_ctx *c, int prec, int nrhs) {
+    VecArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = c->Vh * (long)nrhs;
+    a.nrhs = nrhs;
+    (void)prec;
+    return a;
+}
+static void set_vec(VecArgs &a, int k, const void *base, size_t hb) {
+    a.v[k][0] = (void *)base;
+    a.v[k][1] = (char *)base + hb;
+}
+
+extern "C" wl_status wl_convert_spinor(const wl_ctx *c, void *dst, wl_prec dprec, const void *src, wl_prec sprec,
+                                       wl_subset subset, int nrhs, void *stream) {
+    g_err.clear();
+    wl_status st = check_field_args(c, subset, sprec, nrhs);
+    if (st) return st;
+    if (!prec_ok(dprec)) return fail(WL_ERR_ARG, "bad precision %d", (int)dprec);
+    if (!dst || !src || !aligned16(dst) || !aligned16(src)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    const int nh = subset == WL_FULL ? 2 : 1;
+    if (overlap(dst, half_bytes(c, dprec, nrhs) * nh, src, half_bytes(c, sprec, nrhs) * nh))
+        return fail(WL_ERR_ARG, "dst and src overlap");
+    VecArgs a = vec_args(c, sprec, nrhs);
+    set_vec(a, 0, src, half_bytes(c, sprec, nrhs));
+    set_vec(a, 1, dst, half_bytes(c, dprec, nrhs));
+    HIP_TRY(blas_convert(dprec, sprec, false, a, nh, (hipStream_t)stream));
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ operators
+// Enqueue out = a x + b H in (or H^+) for one output subset.
+static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, void *out, const void *in,
+                          const void *x, int out_subset, int nrhs, double a, double b, double *partials,
+                          long part_stride, const int *flag, hipStream_t s, long *nblk_out = nullptr) {
+    const void *gauge;
+    size_t slab;
+    wl_status st = get_links(c, prec, recon, &gauge, &slab);
+    if (st) return st;
+    const size_t hb = half_bytes(c, prec, nrhs);
+    HopArgs h;
+    std::memset(&h, 0, sizeof h);
+    h.g = c->g;
+    h.gauge = gauge;
+    h.slab_bytes = slab;
+    h.nrhs = nrhs;
+    h.npts = c->Vh * (long)nrhs;
+    h.a = a;
+    h.b = b;
+    h.partials = partials;
+    h.part_stride = part_stride;
+    h.flag = flag;
+    int np = 1;
+    if (out_subset == WL_FULL) {
+        h.out[0] = out;
+        h.out[1] = (char *)out + hb;
+        h.in[0] = in;
+        h.in[1] = (const char *)in + hb;
+        if (x) {
+            h.x[0] = x;
+            h.x[1] = (const char *)x + hb;
+        }
+        h.out_par0 = 0;
+        np = 2;
+    } else {
+        const int p = out_subset;
+        h.out[p] = out;
+        h.in[1 - p] = in;
+        h.x[p] = x;
+        h.out_par0 = p;
+    }
+    HIP_TRY(launch_hop(prec, recon, dag, epi, h, np, c->cfg, s));
+    if (nblk_out) *nblk_out = hop_blocks(h.npts, c->cfg.block) * np;
+    return WL_OK;
+}
+
+static wl_status dslash_common(const wl_ctx *cc, void *out, const void *in, wl_subset subset, wl_prec prec, int recon,
+                               int nrhs, void *stream, bool dag) {
+    g_err.clear();
+    wl_ctx *c = const_cast<wl_ctx *>(cc);
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", prec, recon);
+    if (!out || !in || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    const size_t bytes = half_bytes(c, prec, nrhs) * (subset == WL_FULL ? 2 : 1);
+    if (overlap(out, bytes, in, bytes)) return fail(WL_ERR_ARG, "out and in overlap");
+    return hop_core(c, prec, recon, dag, 0, out, in, nullptr, subset, nrhs, 0.0, 1.0, nullptr, 0, nullptr,
+                    (hipStream_t)stream);
+}
+
+extern "C" wl_status wl_dslash_apply(const wl_ctx *c, void *out, const void *in, wl_subset subset, wl_prec prec,
+                                     int recon, int nrhs, void *stream) {
+    return dslash_common(c, out, in, subset, prec, recon, nrhs, stream, false);
+}
+extern "C" wl_status wl_dslash_dagger_apply(const wl_ctx *c, void *out, const void *in, wl_subset subset,
+                                            wl_prec prec, int recon, int nrhs, void *stream) {
+    return dslash_common(c, out, in, subset, prec, recon, nrhs, stream, true);
+}
+
+// out = M in (M^+ if dag); tmp: odd half temporary for DHAT.  Norm partials of
+// out if partials != null.
+static wl_status apply_m(wl_ctx *c, int op, bool dag, double kappa, int prec, int recon, int nrhs, void *out,
+                         const void *in, void *tmp, double *partials, long stride, const int *flag, hipStream_t s,
+                         long *nblk) {
+    const int epi = EPI_XPAY | (partials ? EPI_NORM : 0);
+    if (op == WL_OP_D)
+        return hop_core(c, prec, recon, dag, epi, out, in, in, WL_FULL, nrhs, 1.0, -kappa, partials, stride, flag, s,
+                        nblk);
+    wl_status st = hop_core(c, prec, recon, dag, 0, tmp, in, nullptr, WL_ODD, nrhs, 0.0, 1.0, nullptr, 0, flag, s);
+    if (st) return st;
+    return hop_core(c, prec, recon, dag, epi, out, tmp, in, WL_EVEN, nrhs, 1.0, -kappa * kappa, partials, stride,
+                    flag, s, nblk);
+}
+
+extern "C" wl_status wl_dirac_apply(wl_ctx *c, void *out, const void *in, wl_op op, int dagger, double kappa,
+                                    wl_prec prec, int recon, int nrhs, void *stream) {
+    g_err.clear();
+    if (op != WL_OP_D && op != WL_OP_DHAT) return fail(WL_ERR_ARG, "bad operator %d", (int)op);
+    const int subset = op == WL_OP_D ? WL_FULL : WL_EVEN;
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", prec, recon);
+    if (!out || !in || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    if (!std::isfinite(kappa)) return fail(WL_ERR_ARG, "non-finite kappa");
+    const size_t hb = half_bytes(c, prec, nrhs);
+    const size_t bytes = hb * (op == WL_OP_D ? 2 : 1);
+    if (overlap(out, bytes, in, bytes)) return fail(WL_ERR_ARG, "out and in overlap");
+    void *tmp = nullptr;
+    if (op == WL_OP_DHAT) {
+        st = ensure_buf(c, S_TMP_OP, hb);
+        if (st) return st;
+        tmp = c->buf[S_TMP_OP];
+    }
+    return apply_m(c, op, dagger != 0, kappa, prec, recon, nrhs, out, in, tmp, nullptr, 0, nullptr,
+                   (hipStream_t)stream, nullptr);
+}
+
+static wl_status eo_helper(const wl_ctx *cc, void *out, const void *a_in, const void *hop_in, int out_subset,
+                           double kappa, wl_prec prec, int recon, int nrhs, void *stream) {
+    g_err.clear();
+    wl_ctx *c = const_cast<wl_ctx *>(cc);
+    wl_status st = check_field_args(c, out_subset, prec, nrhs);
+    if (st) return st;
+    if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", prec, recon);
+    if (!out || !a_in || !hop_in || !aligned16(out) || !aligned16(a_in) || !aligned16(hop_in))
+        return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    if (!std::isfinite(kappa)) return fail(WL_ERR_ARG, "non-finite kappa");
+    const size_t hb = half_bytes(c, prec, nrhs);
+    if (overlap(out, hb, hop_in, hb)) return fail(WL_ERR_ARG, "output overlaps the hopping input");
+    return hop_core(c, prec, recon, false, EPI_XPAY, out, hop_in, a_in, out_subset, nrhs, 1.0, kappa, nullptr, 0,
+                    nullptr, (hipStream_t)stream);
+}
+
+extern "C" wl_status wl_eo_prepare(const wl_ctx *c, void *bhat_e, const void *b_e, const void *b_o, double kappa,
+                                   wl_prec prec, int recon, int nrhs, void *stream) {
+    return eo_helper(c, bhat_e, b_e, b_o, WL_EVEN, kappa, prec, recon, nrhs, stream);
+}
+extern "C" wl_status wl_eo_reconstruct(const wl_ctx *c, void *x_o, const void *x_e, const void *b_o, double kappa,
+                                       wl_prec prec, int recon, int nrhs, void *stream) {
+    return eo_helper(c, x_o, b_o, x_e, WL_ODD, kappa, prec, recon, nrhs, stream);
+}
+
+// ------------------------------------------------------------------ BLAS API
+static long part_stride_for(const wl_ctx *c, int nrhs) {
+    const long n = c->Vh * (long)nrhs;
+    const long hb = hop_blocks(n, 64) * 2;  // the smallest block size any kernel may use
+    const long bb = blas_blocks(n) * 2;
+    return std::max(hb, bb);
+}
+
+extern "C" wl_status wl_blas_axpy(const wl_ctx *c, double a, const void *x, void *y, wl_subset subset, wl_prec prec,
+                                  int nrhs, void *stream) {
+    g_err.clear();
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!x || !y || !aligned16(x) || !aligned16(y)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    if (!std::isfinite(a)) return fail(WL_ERR_ARG, "non-finite scalar");
+    VecArgs v = vec_args(c, prec, nrhs);
+    const size_t hb = half_bytes(c, prec, nrhs);
+    set_vec(v, 0, x, hb);
+    set_vec(v, 1, y, hb);
+    v.a = a;
+    v.b = 1.0;
+    HIP_TRY(blas_axpby(prec, v, subset == WL_FULL ? 2 : 1, false, (hipStream_t)stream));
+    return WL_OK;
+}
+
+static wl_status reduce_to_host(wl_ctx *c, int nvals, long stride, long nblk, double *out, hipStream_t s) {
+    wl_status st = ensure_buf(c, S_SCAL, std::max<size_t>(c->buf_bytes[S_SCAL], 64 * sizeof(double) * 2));
+    if (st) return st;
+    double *d = (double *)c->buf[S_SCAL];
+    HIP_TRY(reduce_partials((const double *)c->buf[S_PARTIALS], stride, nblk, nvals, d, s));
+    HIP_TRY(hipMemcpyAsync(out, d, nvals * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return WL_OK;
+}
+
+extern "C" wl_status wl_blas_dot(const wl_ctx *cc, const void *x, const void *y, wl_subset subset, wl_prec prec,
+                                 int nrhs, double result[2], void *stream) {
+    g_err.clear();
+    wl_ctx *c = const_cast<wl_ctx *>(cc);
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!x || !y || !result || !aligned16(x) || !aligned16(y)) return fail(WL_ERR_ARG, "null or misaligned pointer");
+    const long stride = part_stride_for(c, nrhs);
+    st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * nrhs * stride);
+    if (st) return st;
+    VecArgs v = vec_args(c, prec, nrhs);
+    const size_t hb = half_bytes(c, prec, nrhs);
+    set_vec(v, 0, x, hb);
+    set_vec(v, 1, y, hb);
+    v.partials = (double *)c->buf[S_PARTIALS];
+    v.part_stride = stride;
+    const int nh = subset == WL_FULL ? 2 : 1;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(blas_dot(prec, v, nh, s));
+    std::vector<double> vals(2 * nrhs);
+    st = reduce_to_host(c, 2 * nrhs, stride, blas_blocks(v.n) * nh, vals.data(), s);
+    if (st) return st;
+    // result holds (re, im) for rhs 0; callers with nrhs > 1 get the sum over rhs
+    double re = 0, im = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        re += vals[r];
+        im += vals[nrhs + r];
+    }
+    result[0] = re;
+    result[1] = im;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_blas_norm2(const wl_ctx *cc, const void *x, wl_subset subset, wl_prec prec, int nrhs,
+                                   double *result, void *stream) {
+    g_err.clear();
+    wl_ctx *c = const_cast<wl_ctx *>(cc);
+    wl_status st = check_field_args(c, subset, prec, nrhs);
+    if (st) return st;
+    if (!x || !result || !aligned16(x)) return fail(WL_ERR_ARG, "null or misaligned pointer");
+    const long stride = part_stride_for(c, nrhs);
+    st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * nrhs * stride);
+    if (st) return st;
+    VecArgs v = vec_args(c, prec, nrhs);
+    set_vec(v, 0, x, half_bytes(c, prec, nrhs));
+    v.partials = (double *)c->buf[S_PARTIALS];
+    v.part_stride = stride;
+    const int nh = subset == WL_FULL ? 2 : 1;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(blas_norm2(prec, v, nh, s));
+    std::vector<double> vals(nrhs);
+    st = reduce_to_host(c, nrhs, stride, blas_blocks(v.n) * nh, vals.data(), s);
+    if (st) return st;
+    double t = 0;
+    for (double q : vals) t += q;
+    *result = t;
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ CG
+extern "C" void wl_solver_params_default(wl_solver_params *p) {
+    if (!p) return;
+    p->tol = 1e-10;
+    p->maxiter = 100000;
+    p->check_every = 25;
+    p->max_restarts = 5;
+    p->prec = WL_F64;
+    p->recon = 18;
+    p->reliable_every = 100;
+    p->reliable_delta = 0.1;
+    p->use_graph = 0;
+}
+
+namespace {
+struct CGRun {
+    wl_ctx *c;
+    int op, nrhs, prec, recon, nh;
+    double kappa;
+    hipStream_t s;
+    size_t hb_lo, hb_hi;
+    void *x, *r, *p, *q, *sv, *tmp;  // inner precision (x is FP64)
+    const void *b;
+    void *rhi, *thi, *tmphi;
+    double *partials;
+    long stride;
+    CGScalars *sc;
+    double *bnorm2;
+    int *done;
+    long nblk_blas;
+};
+}  // namespace
+
+// t = A x = M^+ M x in FP64; r_hi = b - t; partials of ||r_hi||^2
+static wl_status true_residual(CGRun &R) {
+    wl_status st = apply_m(R.c, R.op, false, R.kappa, WL_F64, 18, R.nrhs, R.thi, R.x, R.tmphi, nullptr, 0, nullptr,
+                           R.s, nullptr);
+    if (st) return st;
+    st = apply_m(R.c, R.op, true, R.kappa, WL_F64, 18, R.nrhs, R.rhi, R.thi, R.tmphi, nullptr, 0, nullptr, R.s,
+                 nullptr);
+    if (st) return st;
+    VecArgs v = vec_args(R.c, WL_F64, R.nrhs);
+    set_vec(v, 0, R.b, R.hb_hi);
+    set_vec(v, 1, R.rhi, R.hb_hi);
+    set_vec(v, 2, R.rhi, R.hb_hi);
+    v.partials = R.partials;
+    v.part_stride = R.stride;
+    HIP_TRY(blas_residual(WL_F64, v, R.nh, R.s));
+    return WL_OK;
+}
+
+// r_lo = r_hi ; p = r_lo
+static wl_status load_residual(CGRun &R) {
+    VecArgs v = vec_args(R.c, R.prec, R.nrhs);
+    if (R.prec != WL_F64) {
+        set_vec(v, 0, R.rhi, R.hb_hi);
+        set_vec(v, 1, R.r, R.hb_lo);
+        HIP_TRY(blas_convert(R.prec, WL_F64, false, v, R.nh, R.s));
+    }
+    set_vec(v, 0, R.r, R.hb_lo);
+    set_vec(v, 1, R.p, R.hb_lo);
+    HIP_TRY(blas_convert(R.prec, R.prec, false, v, R.nh, R.s));
+    return WL_OK;
+}
+
+static wl_status cg_iteration(CGRun &R, bool reliable) {
+    long nblk = 0;
+    wl_status st = apply_m(R.c, R.op, false, R.kappa, R.prec, R.recon, R.nrhs, R.q, R.p, R.tmp, R.partials, R.stride,
+                           R.done, R.s, &nblk);
+    if (st) return st;
+    HIP_TRY(cg_alpha(R.sc, R.nrhs, R.partials, R.stride, nblk, R.done, R.s));
+    st = apply_m(R.c, R.op, true, R.kappa, R.prec, R.recon, R.nrhs, R.sv, R.q, R.tmp, nullptr, 0, R.done, R.s,
+                 nullptr);
+    if (st) return st;
+    VecArgs v = vec_args(R.c, R.prec, R.nrhs);
+    set_vec(v, 0, R.x, R.hb_hi);
+    set_vec(v, 1, R.p, R.hb_lo);
+    set_vec(v, 2, R.r, R.hb_lo);
+    set_vec(v, 3, R.sv, R.hb_lo);
+    v.partials = R.partials;
+    v.part_stride = R.stride;
+    v.sc = R.sc;
+    v.flag = R.done;
+    HIP_TRY(cg_update_xr(R.prec, WL_F64, v, R.nh, R.s));
+    if (reliable) {
+        // replace the iterated residual by the FP64 one before the step length of p is formed
+        st = true_residual(R);
+        if (st) return st;
+        VecArgs w = vec_args(R.c, R.prec, R.nrhs);
+        set_vec(w, 0, R.rhi, R.hb_hi);
+        set_vec(w, 1, R.r, R.hb_lo);
+        w.flag = R.done;
+        HIP_TRY(blas_convert(R.prec, WL_F64, false, w, R.nh, R.s));
+    }
+    HIP_TRY(cg_beta(R.sc, R.nrhs, R.partials, R.stride, R.nblk_blas, R.done, reliable ? 1 : 0, R.s));
+    VecArgs u = vec_args(R.c, R.prec, R.nrhs);
+    set_vec(u, 0, R.r, R.hb_lo);
+    set_vec(u, 1, R.p, R.hb_lo);
+    u.sc = R.sc;
+    u.flag = R.done;
+    HIP_TRY(cg_update_p(R.prec, u, R.nh, R.s));
+    return WL_OK;
+}
+
+extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, double kappa, int nrhs,
+                                 const wl_solver_params *params, wl_solver_info *info, void *stream) {
+    g_err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (op != WL_OP_D && op != WL_OP_DHAT) return fail(WL_ERR_ARG, "bad operator %d", (int)op);
+    const int subset = op == WL_OP_D ? WL_FULL : WL_EVEN;
+    wl_status st = check_field_args(c, subset, WL_F64, nrhs);
+    if (st) return st;
+    wl_solver_params P;
+    wl_solver_params_default(&P);
+    if (params) P = *params;
+    if (!prec_ok(P.prec)) return fail(WL_ERR_ARG, "bad inner precision %d", (int)P.prec);
+    if (!recon_ok(P.prec, P.recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", P.prec, P.recon);
+    if (!(P.tol >= 0.0) || !std::isfinite(kappa)) return fail(WL_ERR_ARG, "bad tolerance or kappa");
+    if (P.maxiter < 0 || P.check_every < 1 || P.max_restarts < 0) return fail(WL_ERR_ARG, "bad iteration limits");
+    if (!x || !b || !aligned16(x) || !aligned16(b)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    const int nh = subset == WL_FULL ? 2 : 1;
+    CGRun R;
+    std::memset(&R, 0, sizeof R);
+    R.c = c;
+    R.op = op;
+    R.nrhs = nrhs;
+    R.prec = P.prec;
+    R.recon = P.recon;
+    R.nh = nh;
+    R.kappa = kappa;
+    R.s = (hipStream_t)stream;
+    R.hb_lo = half_bytes(c, P.prec, nrhs);
+    R.hb_hi = half_bytes(c, WL_F64, nrhs);
+    if (overlap(x, R.hb_hi * nh, b, R.hb_hi * nh)) return fail(WL_ERR_ARG, "x and b overlap");
+    R.x = x;
+    R.b = b;
+    R.stride = part_stride_for(c, nrhs);
+    const size_t flo = R.hb_lo * nh, fhi = R.hb_hi * nh;
+    if ((st = ensure_buf(c, S_R, flo)) || (st = ensure_buf(c, S_P, flo)) || (st = ensure_buf(c, S_Q, flo)) ||
+        (st = ensure_buf(c, S_S, flo)) || (st = ensure_buf(c, S_TMP, R.hb_lo)) || (st = ensure_buf(c, S_RHI, fhi)) ||
+        (st = ensure_buf(c, S_THI, fhi)) || (st = ensure_buf(c, S_TMPHI, R.hb_hi)) ||
+        (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * nrhs * R.stride)) ||
+        (st = ensure_buf(c, S_SCAL, std::max<size_t>(sizeof(CGScalars) * nrhs, 64 * sizeof(double) * 2))) ||
+        (st = ensure_buf(c, S_BNORM, sizeof(double) * 2 * nrhs)) || (st = ensure_buf(c, S_FLAG, 64)) ||
+        (st = ensure_pinned(c, sizeof(CGScalars) * nrhs + 64)))
+        return st;
+    R.r = c->buf[S_R];
+    R.p = c->buf[S_P];
+    R.q = c->buf[S_Q];
+    R.sv = c->buf[S_S];
+    R.tmp = c->buf[S_TMP];
+    R.rhi = c->buf[S_RHI];
+    R.thi = c->buf[S_THI];
+    R.tmphi = c->buf[S_TMPHI];
+    R.partials = (double *)c->buf[S_PARTIALS];
+    R.sc = (CGScalars *)c->buf[S_SCAL];
+    R.bnorm2 = (double *)c->buf[S_BNORM];
+    R.done = (int *)c->buf[S_FLAG];
+    R.nblk_blas = blas_blocks(c->Vh * (long)nrhs) * nh;
+    if (P.prec == WL_F64) R.r = R.rhi;  // FP64 CG iterates directly on the FP64 residual
+    const bool mixed = P.prec != WL_F64;
+
+    // ||b||^2 per rhs
+    {
+        VecArgs v = vec_args(c, WL_F64, nrhs);
+        set_vec(v, 0, b, R.hb_hi);
+        v.partials = R.partials;
+        v.part_stride = R.stride;
+        HIP_TRY(blas_norm2(WL_F64, v, nh, R.s));
+        HIP_TRY(reduce_partials(R.partials, R.stride, R.nblk_blas, nrhs, R.bnorm2, R.s));
+    }
+    std::vector<CGScalars> hsc(nrhs);
+    std::vector<int> total_iters(nrhs, 0), reliable(nrhs, 0);
+    int restarts = 0;
+    int remaining = P.maxiter;
+    wl_status result = WL_OK;
+    std::vector<double> true_rel(nrhs, 0.0), iter_rel(nrhs, 0.0);
+    std::vector<double> hb2(nrhs);
+    HIP_TRY(hipMemcpyAsync(hb2.data(), R.bnorm2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, R.s));
+    for (;;) {
+        // (re)start from the FP64 residual of the current x
+        st = true_residual(R);
+        if (st) return st;
+        HIP_TRY(cg_init(R.sc, nrhs, R.partials, R.stride, R.nblk_blas, R.bnorm2, P.tol, remaining, R.done, R.s));
+        st = load_residual(R);
+        if (st) return st;
+        int since_reliable = 0, k = 0;
+        for (;;) {
+            for (int j = 0; j < P.check_every; ++j, ++k) {
+                bool ru = false;
+                if (mixed && P.reliable_every > 0 && ++since_reliable >= P.reliable_every) {
+                    ru = true;
+                    since_reliable = 0;
+                    for (int r = 0; r < nrhs; ++r) reliable[r]++;
+                }
+                st = cg_iteration(R, ru);
+                if (st) return st;
+            }
+            HIP_TRY(hipMemcpyAsync(c->host_pinned, R.sc, sizeof(CGScalars) * nrhs, hipMemcpyDeviceToHost, R.s));
+            HIP_TRY(hipStreamSynchronize(R.s));
+            std::memcpy(hsc.data(), c->host_pinned, sizeof(CGScalars) * nrhs);
+            bool any = false, need_ru = false;
+            for (int r = 0; r < nrhs; ++r) {
+                any |= hsc[r].active != 0;
+                if (mixed && hsc[r].active && hsc[r].rho < P.reliable_delta * P.reliable_delta * hsc[r].rho_max)
+                    need_ru = true;
+            }
+            if (!any) break;
+            if (need_ru) {
+                // an FP64 refresh forced by the residual drop, carried by the next iteration
+                st = cg_iteration(R, true);
+                if (st) return st;
+                since_reliable = 0;
+                for (int r = 0; r < nrhs; ++r) reliable[r]++;
+            }
+        }
+        int maxit = 0;
+        bool breakdown = false;
+        for (int r = 0; r < nrhs; ++r) {
+            total_iters[r] += hsc[r].iter;
+            maxit = std::max(maxit, hsc[r].iter);
+            iter_rel[r] = hb2[r] > 0 ? std::sqrt(hsc[r].rho / hb2[r]) : 0.0;
+            breakdown |= hsc[r].status == WL_BREAKDOWN;
+        }
+        remaining -= maxit;
+        // FP64 true residual of the result
+        st = true_residual(R);
+        if (st) return st;
+        std::vector<double> rr(nrhs);
+        HIP_TRY(reduce_partials(R.partials, R.stride, R.nblk_blas, nrhs, R.bnorm2 + nrhs, R.s));
+        HIP_TRY(hipMemcpyAsync(rr.data(), R.bnorm2 + nrhs, sizeof(double) * nrhs, hipMemcpyDeviceToHost, R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+        bool all_ok = true;
+        for (int r = 0; r < nrhs; ++r) {
+            true_rel[r] = hb2[r] > 0 ? std::sqrt(rr[r] / hb2[r]) : 0.0;
+            if (!(true_rel[r] <= P.tol)) all_ok = false;
+        }
+        if (breakdown) {
+            result = WL_BREAKDOWN;
+            break;
+        }
+        if (all_ok) {
+            result = WL_OK;
+            break;
+        }
+        if (remaining <= 0 || restarts >= P.max_restarts) {
+            result = WL_NOT_CONVERGED;
+            break;
+        }
+        ++restarts;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int r = 0; r < nrhs; ++r) {
+            info[r].iters = total_iters[r];
+            info[r].restarts = restarts;
+            info[r].reliable_updates = reliable[r];
+            info[r].rel_resid = iter_rel[r];
+            info[r].true_rel_resid = true_rel[r];
+            info[r].seconds = secs;
+        }
+    if (result == WL_BREAKDOWN) fail(WL_BREAKDOWN, "CG breakdown (NaN/Inf or non-positive <p, A p>)");
+    else if (result == WL_NOT_CONVERGED) fail(WL_NOT_CONVERGED, "CG did not reach the tolerance");
+    return result;
+}

@@ -1,0 +1,67 @@
+// BLAS-1 and solver-scalar kernels on internal spinor fields.
+#pragma once
+
+#include "wl_common.h"
+
+namespace wl {
+
+// Device-resident scalars of one right-hand side of a CG solve.
+struct CGScalars {
+    double rho;      // ||r||^2 of the current iterate
+    double pap;      // <p, A p>
+    double alpha;
+    double beta;
+    double target;   // tol^2 ||b||^2
+    double rho_max;  // largest ||r||^2 since the last reliable update (mixed precision)
+    int iter;        // iterations done in this solve
+    int active;      // 1 while iterating
+    int status;      // WL_OK / WL_NOT_CONVERGED / WL_BREAKDOWN
+    int maxiter;
+};
+
+struct VecArgs {
+    void *v[4][2];     // up to 4 fields, each given per half (half 0 / half 1)
+    long n;            // points per half
+    int nrhs;
+    double a, b;       // scalars (see each kernel)
+    double *partials;  // per-block partial sums, rhs r at partials[r * part_stride + block]
+    long part_stride;
+    CGScalars *sc;     // per-rhs solver scalars (kernels that use them)
+    const int *flag;   // if non-null and *flag != 0 the launch does nothing
+};
+
+// all launchers: nhalves = 1 (EVEN/ODD field) or 2 (FULL field)
+hipError_t blas_axpby(int prec, VecArgs &a, int nhalves, bool norm, hipStream_t s);      // v1 = a v0 + b v1 [, ||v1||^2]
+hipError_t blas_dot(int prec, VecArgs &a, int nhalves, hipStream_t s);                   // <v0, v1>: re at rhs r, im at rhs nrhs + r
+hipError_t blas_norm2(int prec, VecArgs &a, int nhalves, hipStream_t s);                 // ||v0||^2
+hipError_t blas_zero(int prec, VecArgs &a, int nhalves, hipStream_t s);                  // v0 = 0
+// x += alpha p ; r -= alpha s ; ||r||^2 partials (alpha = sc[rhs].alpha):
+// v0 = x (FP64 or low precision, xprec), v1 = p, v2 = r, v3 = s
+hipError_t cg_update_xr(int prec, int xprec, VecArgs &a, int nhalves, hipStream_t s);
+// p = r + beta p (beta = sc[rhs].beta): v0 = r, v1 = p
+hipError_t cg_update_p(int prec, VecArgs &a, int nhalves, hipStream_t s);
+// v1 (prec dprec) = v0 (prec sprec), or v1 += v0 if accumulate
+hipError_t blas_convert(int dprec, int sprec, bool accumulate, VecArgs &a, int nhalves, hipStream_t s);
+// r = b - v  (v2 = r output, v0 = b, v1 = v), ||r||^2 partials: used for true residuals
+hipError_t blas_residual(int prec, VecArgs &a, int nhalves, hipStream_t s);
+
+inline int blas_block() { return 256; }
+inline long blas_blocks(long n) { return (n + blas_block() - 1) / blas_block(); }
+
+// single-block reductions of `nblk` partials per rhs
+//   out[r] = sum_b partials[r * stride + b]   (r < nvals)
+hipError_t reduce_partials(const double *partials, long stride, long nblk, int nvals, double *out,
+                           hipStream_t s);
+// CG scalar steps (one launch each, all rhs):
+//   alpha: pap = sum; breakdown check; alpha = rho / pap
+//   beta : rho' = sum; convergence / maxiter checks; beta = rho' / rho; sets *done when no rhs is active
+hipError_t cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
+                    const int *flag, hipStream_t s);
+//   reset_max: the residual was just refreshed in FP64; restart the rho_max record from it
+hipError_t cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *done,
+                   int reset_max, hipStream_t s);
+// initialise: rho = sum(partials) (||r0||^2), target = tol^2 * bnorm2[r]; active if rho > target
+hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
+                   const double *bnorm2, double tol, int maxiter, int *done, hipStream_t s);
+
+}  // namespace wl

@@ -1,0 +1,406 @@
+// BLAS-1 steps of the solvers on internal spinor fields (gfx950).
+//
+// Each kernel streams whole spinor points (12 complex) with one thread per
+// point; the reductions are accumulated in FP64, first per block (wavefront
+// shuffles, then LDS, in a fixed order) into a partials array, then by a
+// single-block kernel in a fixed order, so results are bitwise reproducible
+// from run to run.
+#include "wl_blas.h"
+
+namespace wl {
+
+#define WL_FLAG_EXIT \
+    if (a.flag && *a.flag) return;
+
+template <int SP, bool NORM>
+__global__ void __launch_bounds__(256) k_axpby(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (gid < a.n) {
+        cpx<T> x[12], y[12];
+        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
+        SpinorIO<SP>::load(a.v[1][h], a.n, gid, y);
+        const T aa = (T)a.a, bb = (T)a.b;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) y[k] = {fma(aa, x[k].re, bb * y[k].re), fma(aa, x[k].im, bb * y[k].im)};
+        SpinorIO<SP>::store(a.v[1][h], a.n, gid, y);
+        if constexpr (NORM) {
+            if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[1][h], a.n, gid, y);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) nrm += (double)y[k].re * y[k].re + (double)y[k].im * y[k].im;
+        }
+    }
+    if constexpr (NORM) {
+        __shared__ double lds[256];
+        block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + (long)blockIdx.y * gridDim.x + blockIdx.x,
+                      a.part_stride);
+    }
+}
+
+template <int SP>
+__global__ void __launch_bounds__(256) k_dot(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double re = 0.0, im = 0.0;
+    if (gid < a.n) {
+        cpx<T> x[12], y[12];
+        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
+        SpinorIO<SP>::load(a.v[1][h], a.n, gid, y);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            re += (double)x[k].re * y[k].re + (double)x[k].im * y[k].im;
+            im += (double)x[k].re * y[k].im - (double)x[k].im * y[k].re;
+        }
+    }
+    __shared__ double lds[256];
+    const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
+    block_sum_rhs(re, gid, a.nrhs, lds, a.partials + blk, a.part_stride);
+    block_sum_rhs(im, gid, a.nrhs, lds, a.partials + (long)a.nrhs * a.part_stride + blk, a.part_stride);
+}
+
+template <int SP>
+__global__ void __launch_bounds__(256) k_norm2(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (gid < a.n) {
+        cpx<T> x[12];
+        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nrm += (double)x[k].re * x[k].re + (double)x[k].im * x[k].im;
+    }
+    __shared__ double lds[256];
+    block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + (long)blockIdx.y * gridDim.x + blockIdx.x,
+                  a.part_stride);
+}
+
+template <int SP>
+__global__ void __launch_bounds__(256) k_zero(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < a.n) {
+        cpx<T> z[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) z[k] = {T(0), T(0)};
+        SpinorIO<SP>::store(a.v[0][blockIdx.y], a.n, gid, z);
+    }
+}
+
+// x (FP64) += alpha p ; r -= alpha s ; partial ||r||^2
+template <int SP>
+__global__ void __launch_bounds__(256) k_cg_xr(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (gid < a.n) {
+        const int rhs = (int)(gid % a.nrhs);
+        const CGScalars &sc = a.sc[rhs];
+        if (sc.active) {
+            const double alpha = sc.alpha;
+            cpx<T> p[12], r[12], s[12];
+            cpx<double> x[12];
+            SpinorIO<SP>::load(a.v[1][h], a.n, gid, p);
+            SpinorIO<WL_F64>::load(a.v[0][h], a.n, gid, x);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                x[k] = {fma(alpha, (double)p[k].re, x[k].re), fma(alpha, (double)p[k].im, x[k].im)};
+            SpinorIO<WL_F64>::store(a.v[0][h], a.n, gid, x);
+            SpinorIO<SP>::load(a.v[2][h], a.n, gid, r);
+            SpinorIO<SP>::load(a.v[3][h], a.n, gid, s);
+            const T al = (T)alpha;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) r[k] = {fma(-al, s[k].re, r[k].re), fma(-al, s[k].im, r[k].im)};
+            SpinorIO<SP>::store(a.v[2][h], a.n, gid, r);
+            if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[2][h], a.n, gid, r);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) nrm += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
+        }
+    }
+    __shared__ double lds[256];
+    block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + (long)blockIdx.y * gridDim.x + blockIdx.x,
+                  a.part_stride);
+}
+
+// p = r + beta p
+template <int SP>
+__global__ void __launch_bounds__(256) k_cg_p(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < a.n) {
+        const int rhs = (int)(gid % a.nrhs);
+        if (!a.sc[rhs].active) return;
+        const T beta = (T)a.sc[rhs].beta;
+        cpx<T> r[12], p[12];
+        SpinorIO<SP>::load(a.v[0][h], a.n, gid, r);
+        SpinorIO<SP>::load(a.v[1][h], a.n, gid, p);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[k] = {fma(beta, p[k].re, r[k].re), fma(beta, p[k].im, r[k].im)};
+        SpinorIO<SP>::store(a.v[1][h], a.n, gid, p);
+    }
+}
+
+template <int DP, int SP, bool ACC>
+__global__ void __launch_bounds__(256) k_convert(const VecArgs a) {
+    using TS = typename SpinorIO<SP>::real;
+    using TD = typename SpinorIO<DP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < a.n) {
+        cpx<TS> x[12];
+        cpx<TD> y[12];
+        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
+        if constexpr (ACC) {
+            SpinorIO<DP>::load(a.v[1][h], a.n, gid, y);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) y[k] = {y[k].re + (TD)x[k].re, y[k].im + (TD)x[k].im};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) y[k] = {(TD)x[k].re, (TD)x[k].im};
+        }
+        SpinorIO<DP>::store(a.v[1][h], a.n, gid, y);
+    }
+}
+
+// r = b - v, partial ||r||^2
+template <int SP>
+__global__ void __launch_bounds__(256) k_residual(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (gid < a.n) {
+        cpx<T> b[12], v[12];
+        SpinorIO<SP>::load(a.v[0][h], a.n, gid, b);
+        SpinorIO<SP>::load(a.v[1][h], a.n, gid, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = b[k] - v[k];
+        SpinorIO<SP>::store(a.v[2][h], a.n, gid, v);
+        if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[2][h], a.n, gid, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nrm += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
+    }
+    __shared__ double lds[256];
+    block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + (long)blockIdx.y * gridDim.x + blockIdx.x,
+                  a.part_stride);
+}
+
+// ------------------------------------------------------------------ single-block reductions
+__device__ double sum_partials(const double *p, long nblk, double *lds) {
+    double s = 0.0;
+    for (long b = threadIdx.x; b < nblk; b += blockDim.x) s += p[b];
+    return block_sum(s, lds);  // valid in thread 0
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const double *partials, long stride, long nblk, int nvals,
+                                                double *out) {
+    __shared__ double lds[16];
+    for (int r = 0; r < nvals; ++r) {
+        const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+        if (threadIdx.x == 0) out[r] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride,
+                                                  long nblk, const int *flag) {
+    if (flag && *flag) return;
+    __shared__ double lds[16];
+    for (int r = 0; r < nrhs; ++r) {
+        const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+        if (threadIdx.x == 0) {
+            CGScalars &c = sc[r];
+            if (c.active) {
+                c.pap = s;
+                if (!(s > 0.0) || !isfinite(s) || !isfinite(c.rho)) {
+                    c.status = WL_BREAKDOWN;
+                    c.active = 0;
+                    c.alpha = 0.0;
+                } else {
+                    c.alpha = c.rho / s;
+                }
+            } else {
+                c.alpha = 0.0;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride,
+                                                 long nblk, int *done, int reset_max) {
+    if (*done) return;
+    __shared__ double lds[16];
+    int any = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+        if (threadIdx.x == 0) {
+            CGScalars &c = sc[r];
+            c.beta = 0.0;
+            if (c.active) {
+                c.iter += 1;
+                if (!isfinite(s)) {
+                    c.status = WL_BREAKDOWN;
+                    c.active = 0;
+                } else {
+                    c.beta = s / c.rho;
+                    c.rho = s;
+                    c.rho_max = reset_max ? s : fmax(c.rho_max, s);
+                    if (s <= c.target) {
+                        c.status = WL_OK;
+                        c.active = 0;
+                    } else if (c.iter >= c.maxiter) {
+                        c.status = WL_NOT_CONVERGED;
+                        c.active = 0;
+                    }
+                }
+            }
+            any |= c.active;
+        }
+    }
+    if (threadIdx.x == 0) *done = any ? 0 : 1;
+}
+
+__global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const double *partials, long stride,
+                                                 long nblk, const double *bnorm2, double tol, int maxiter,
+                                                 int *done) {
+    __shared__ double lds[16];
+    int any = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+        if (threadIdx.x == 0) {
+            CGScalars &c = sc[r];
+            c.rho = s;
+            c.rho_max = s;
+            c.pap = 0.0;
+            c.alpha = 0.0;
+            c.beta = 0.0;
+            c.target = tol * tol * bnorm2[r];
+            c.iter = 0;
+            c.maxiter = maxiter;
+            if (!isfinite(s)) {
+                c.status = WL_BREAKDOWN;
+                c.active = 0;
+            } else if (s <= c.target) {
+                c.status = WL_OK;
+                c.active = 0;
+            } else if (maxiter <= 0) {
+                c.status = WL_NOT_CONVERGED;
+                c.active = 0;
+            } else {
+                c.status = WL_NOT_CONVERGED;
+                c.active = 1;
+            }
+            any |= c.active;
+        }
+    }
+    if (threadIdx.x == 0) *done = any ? 0 : 1;
+}
+
+// ------------------------------------------------------------------ launchers
+#define WL_DISPATCH_PREC(prec, KERNEL, ...)                                                            \
+    switch (prec) {                                                                                    \
+    case WL_F64: hipLaunchKernelGGL((KERNEL<WL_F64 __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break;   \
+    case WL_F32: hipLaunchKernelGGL((KERNEL<WL_F32 __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break;   \
+    case WL_F16N: hipLaunchKernelGGL((KERNEL<WL_F16N __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break; \
+    case WL_BF16N: hipLaunchKernelGGL((KERNEL<WL_BF16N __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break; \
+    default: return hipErrorInvalidValue;                                                              \
+    }                                                                                                  \
+    return hipGetLastError();
+
+static dim3 vgrid(const VecArgs &a, int nh) { return dim3((unsigned)blas_blocks(a.n), (unsigned)nh); }
+
+hipError_t blas_axpby(int prec, VecArgs &a, int nh, bool norm, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    if (norm) {
+        WL_DISPATCH_PREC(prec, k_axpby, , true)
+    } else {
+        WL_DISPATCH_PREC(prec, k_axpby, , false)
+    }
+}
+hipError_t blas_dot(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_dot)
+}
+hipError_t blas_norm2(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_norm2)
+}
+hipError_t blas_zero(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_zero)
+}
+hipError_t cg_update_xr(int prec, int xprec, VecArgs &a, int nh, hipStream_t s) {
+    if (xprec != WL_F64) return hipErrorInvalidValue;
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_cg_xr)
+}
+hipError_t cg_update_p(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_cg_p)
+}
+hipError_t blas_residual(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_residual)
+}
+
+template <int DP, bool ACC>
+static hipError_t convert_src(int sprec, VecArgs &a, dim3 grid, hipStream_t s) {
+    switch (sprec) {
+    case WL_F64: hipLaunchKernelGGL((k_convert<DP, WL_F64, ACC>), grid, dim3(blas_block()), 0, s, a); break;
+    case WL_F32: hipLaunchKernelGGL((k_convert<DP, WL_F32, ACC>), grid, dim3(blas_block()), 0, s, a); break;
+    case WL_F16N: hipLaunchKernelGGL((k_convert<DP, WL_F16N, ACC>), grid, dim3(blas_block()), 0, s, a); break;
+    case WL_BF16N: hipLaunchKernelGGL((k_convert<DP, WL_BF16N, ACC>), grid, dim3(blas_block()), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template <bool ACC>
+static hipError_t convert_dst(int dprec, int sprec, VecArgs &a, dim3 grid, hipStream_t s) {
+    switch (dprec) {
+    case WL_F64: return convert_src<WL_F64, ACC>(sprec, a, grid, s);
+    case WL_F32: return convert_src<WL_F32, ACC>(sprec, a, grid, s);
+    case WL_F16N: return convert_src<WL_F16N, ACC>(sprec, a, grid, s);
+    case WL_BF16N: return convert_src<WL_BF16N, ACC>(sprec, a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+hipError_t blas_convert(int dprec, int sprec, bool acc, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    return acc ? convert_dst<true>(dprec, sprec, a, grid, s) : convert_dst<false>(dprec, sprec, a, grid, s);
+}
+
+hipError_t reduce_partials(const double *partials, long stride, long nblk, int nvals, double *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, stride, nblk, nvals, out);
+    return hipGetLastError();
+}
+hipError_t cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
+                    const int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, sc, nrhs, partials, stride, nblk, flag);
+    return hipGetLastError();
+}
+hipError_t cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *done,
+                   int reset_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, sc, nrhs, partials, stride, nblk, done, reset_max);
+    return hipGetLastError();
+}
+hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
+                   const double *bnorm2, double tol, int maxiter, int *done, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, s, sc, nrhs, partials, stride, nblk, bnorm2, tol,
+                       maxiter, done);
+    return hipGetLastError();
+}
+
+}  // namespace wl

@@ -1,0 +1,356 @@
+// Internal definitions shared by the kernels of the Wilson library (gfx950).
+//
+// Complex arithmetic helpers, the storage formats of spinor and link fields,
+// the lattice geometry and the block-level FP64 reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wilson.h"
+
+namespace wl {
+
+// ------------------------------------------------------------------ complex
+template <typename T> struct cpx {
+    T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cpx<T> mk(T r, T i) { return {r, i}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+// i * a
+template <typename T> __device__ __forceinline__ cpx<T> ti(cpx<T> a) { return {-a.im, a.re}; }
+// a * b
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T> __device__ __forceinline__ cpx<T> cjmul(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// c + a * b
+template <typename T> __device__ __forceinline__ cpx<T> cfma(cpx<T> a, cpx<T> b, cpx<T> c) {
+    return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+// c + conj(a) * b
+template <typename T> __device__ __forceinline__ cpx<T> cjfma(cpx<T> a, cpx<T> b, cpx<T> c) {
+    return {fma(a.re, b.re, fma(a.im, b.im, c.re)), fma(a.re, b.im, fma(-a.im, b.re, c.im))};
+}
+template <typename T> __device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return {a.re, -a.im}; }
+
+// ------------------------------------------------------------------ 16-bit conversions
+// FP16 through the hardware conversion (round to nearest even); BF16 by
+// integer rounding of the FP32 bit pattern (round to nearest even, NaN kept).
+__device__ __forceinline__ uint16_t f32_to_f16(float f) {
+    _Float16 h = (_Float16)f;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t u) { return (float)__builtin_bit_cast(_Float16, u); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t u) { return __builtin_bit_cast(float, (uint32_t)u << 16); }
+
+template <int P> struct Half16;
+template <> struct Half16<WL_F16N> {
+    __device__ static float dec(uint16_t u) { return f16_to_f32(u); }
+    __device__ static uint16_t enc(float f) { return f32_to_f16(f); }
+};
+template <> struct Half16<WL_BF16N> {
+    __device__ static float dec(uint16_t u) { return bf16_to_f32(u); }
+    __device__ static uint16_t enc(float f) { return f32_to_bf16(f); }
+};
+
+// ------------------------------------------------------------------ spinor storage
+// An internal field of one parity holds n = Vh * nrhs "points" (site, rhs),
+// rhs fastest.  The 12 complex components c = 3 * spin + colour are stored as
+// structure-of-arrays with the point index fastest, in 16-byte units:
+//   F64  : 12 arrays of double2                        (192 B / point)
+//   F32  :  6 arrays of float4 (components 2k, 2k+1)   ( 96 B / point)
+//   F16N / BF16N: 3 arrays of 8 x 16-bit (components 4k .. 4k+3), then one
+//          array of float norms                         ( 52 B / point)
+template <int P> struct SpinorIO;
+
+template <> struct SpinorIO<WL_F64> {
+    using real = double;
+    static constexpr size_t bytes_per_point = 192;
+    __device__ static void load(const void *base, long n, long i, cpx<double> v[12]) {
+        const double2 *p = (const double2 *)base;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            double2 d = p[c * n + i];
+            v[c] = {d.x, d.y};
+        }
+    }
+    __device__ static void store(void *base, long n, long i, const cpx<double> v[12]) {
+        double2 *p = (double2 *)base;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c * n + i] = make_double2(v[c].re, v[c].im);
+    }
+};
+
+template <> struct SpinorIO<WL_F32> {
+    using real = float;
+    static constexpr size_t bytes_per_point = 96;
+    __device__ static void load(const void *base, long n, long i, cpx<float> v[12]) {
+        const float4 *p = (const float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            float4 d = p[k * n + i];
+            v[2 * k] = {d.x, d.y};
+            v[2 * k + 1] = {d.z, d.w};
+        }
+    }
+    __device__ static void store(void *base, long n, long i, const cpx<float> v[12]) {
+        float4 *p = (float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            p[k * n + i] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    }
+};
+
+template <int P> struct SpinorIO16 {
+    using real = float;
+    static constexpr size_t bytes_per_point = 52;
+    __device__ static void load(const void *base, long n, long i, cpx<float> v[12]) {
+        const uint4 *p = (const uint4 *)base;
+        const float s = ((const float *)(p + 3 * n))[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 d = p[k * n + i];
+            uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[4 * k + j] = {s * Half16<P>::dec((uint16_t)(w[j] & 0xffffu)),
+                                s * Half16<P>::dec((uint16_t)(w[j] >> 16))};
+        }
+    }
+    __device__ static void store(void *base, long n, long i, const cpx<float> v[12]) {
+        uint4 *p = (uint4 *)base;
+        float s = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s = fmaxf(s, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+        const float inv = s > 0.f ? 1.0f / s : 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                w[j] = (uint32_t)Half16<P>::enc(v[4 * k + j].re * inv) |
+                       ((uint32_t)Half16<P>::enc(v[4 * k + j].im * inv) << 16);
+            p[k * n + i] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        ((float *)(p + 3 * n))[i] = s;
+    }
+};
+template <> struct SpinorIO<WL_F16N> : SpinorIO16<WL_F16N> {};
+template <> struct SpinorIO<WL_BF16N> : SpinorIO16<WL_BF16N> {};
+
+// ------------------------------------------------------------------ link storage
+// Links of one (parity, mu) slab: Vh links, structure of arrays, site fastest.
+//   F64 18: 9 double2 (row-major entries)           144 B
+//   F64 12: 6 double2 (rows 0 and 1)                 96 B
+//   F32 18: 4 float4 (entries 0..7) + 1 float2 (8)   72 B
+//   F32 12: 3 float4 (entries 0..5)                  48 B
+//   16-bit 12: 1 x 8 halves (entries 0..3) + 1 x 4 halves (entries 4, 5)   24 B
+// For 12-real storage the third row is rebuilt as conj(row0 x row1) (valid for
+// SU(3)); boundary phases are applied afterwards, outside the link.
+template <int P, int R> struct LinkIO;
+
+template <typename T> __device__ __forceinline__ void recon_row2(cpx<T> u[9]) {
+    // row2 = conj(row0 x row1)
+    u[6] = conjg(cmul(u[1], u[5]) - cmul(u[2], u[4]));
+    u[7] = conjg(cmul(u[2], u[3]) - cmul(u[0], u[5]));
+    u[8] = conjg(cmul(u[0], u[4]) - cmul(u[1], u[3]));
+}
+
+template <> struct LinkIO<WL_F64, 18> {
+    using real = double;
+    static constexpr size_t bytes_per_link = 144;
+    __device__ static void load(const void *base, long vh, long i, cpx<double> u[9]) {
+        const double2 *p = (const double2 *)base;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double2 d = p[k * vh + i];
+            u[k] = {d.x, d.y};
+        }
+    }
+    __device__ static void store(void *base, long vh, long i, const cpx<double> u[9]) {
+        double2 *p = (double2 *)base;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) p[k * vh + i] = make_double2(u[k].re, u[k].im);
+    }
+};
+template <> struct LinkIO<WL_F64, 12> {
+    using real = double;
+    static constexpr size_t bytes_per_link = 96;
+    __device__ static void load(const void *base, long vh, long i, cpx<double> u[9]) {
+        const double2 *p = (const double2 *)base;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double2 d = p[k * vh + i];
+            u[k] = {d.x, d.y};
+        }
+        recon_row2(u);
+    }
+    __device__ static void store(void *base, long vh, long i, const cpx<double> u[9]) {
+        double2 *p = (double2 *)base;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) p[k * vh + i] = make_double2(u[k].re, u[k].im);
+    }
+};
+template <> struct LinkIO<WL_F32, 18> {
+    using real = float;
+    static constexpr size_t bytes_per_link = 72;
+    __device__ static void load(const void *base, long vh, long i, cpx<float> u[9]) {
+        const float4 *p = (const float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float4 d = p[k * vh + i];
+            u[2 * k] = {d.x, d.y};
+            u[2 * k + 1] = {d.z, d.w};
+        }
+        float2 e = ((const float2 *)(p + 4 * vh))[i];
+        u[8] = {e.x, e.y};
+    }
+    __device__ static void store(void *base, long vh, long i, const cpx<float> u[9]) {
+        float4 *p = (float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            p[k * vh + i] = make_float4(u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im);
+        ((float2 *)(p + 4 * vh))[i] = make_float2(u[8].re, u[8].im);
+    }
+};
+template <> struct LinkIO<WL_F32, 12> {
+    using real = float;
+    static constexpr size_t bytes_per_link = 48;
+    __device__ static void load(const void *base, long vh, long i, cpx<float> u[9]) {
+        const float4 *p = (const float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float4 d = p[k * vh + i];
+            u[2 * k] = {d.x, d.y};
+            u[2 * k + 1] = {d.z, d.w};
+        }
+        recon_row2(u);
+    }
+    __device__ static void store(void *base, long vh, long i, const cpx<float> u[9]) {
+        float4 *p = (float4 *)base;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            p[k * vh + i] = make_float4(u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im);
+    }
+};
+template <int P> struct LinkIO16 {
+    using real = float;
+    static constexpr size_t bytes_per_link = 24;
+    __device__ static void load(const void *base, long vh, long i, cpx<float> u[9]) {
+        const uint4 *p = (const uint4 *)base;
+        uint4 a = p[i];
+        uint2 b = ((const uint2 *)(p + vh))[i];
+        uint32_t w[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            u[k] = {Half16<P>::dec((uint16_t)(w[k] & 0xffffu)), Half16<P>::dec((uint16_t)(w[k] >> 16))};
+        recon_row2(u);
+    }
+    __device__ static void store(void *base, long vh, long i, const cpx<float> u[9]) {
+        uint32_t w[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            w[k] = (uint32_t)Half16<P>::enc(u[k].re) | ((uint32_t)Half16<P>::enc(u[k].im) << 16);
+        uint4 *p = (uint4 *)base;
+        p[i] = make_uint4(w[0], w[1], w[2], w[3]);
+        ((uint2 *)(p + vh))[i] = make_uint2(w[4], w[5]);
+    }
+};
+template <> struct LinkIO<WL_F16N, 12> : LinkIO16<WL_F16N> {};
+template <> struct LinkIO<WL_BF16N, 12> : LinkIO16<WL_BF16N> {};
+
+// host-side sizes
+inline size_t spinor_point_bytes(int prec) {
+    switch (prec) {
+    case WL_F64: return 192;
+    case WL_F32: return 96;
+    default: return 52;
+    }
+}
+inline size_t link_bytes(int prec, int recon) {
+    if (prec == WL_F64) return recon == 12 ? 96 : 144;
+    if (prec == WL_F32) return recon == 12 ? 48 : 72;
+    return 24;
+}
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int L[4];      // Lx, Ly, Lz, Lt
+    int lxh;       // Lx / 2
+    int vh;        // sites per parity
+    int sy, sz, st;  // even/odd index strides of y, z, t
+    int phase_mask;  // bit mu set if z_mu != 1
+    double zr[4], zi[4];
+};
+
+// coordinates of even/odd site i of parity p
+__device__ __forceinline__ void eo_coords(const Geom &g, int i, int p, int c[4]) {
+    int xh = i % g.lxh;
+    int r = i / g.lxh;
+    c[1] = r % g.L[1];
+    r /= g.L[1];
+    c[2] = r % g.L[2];
+    c[3] = r / g.L[2];
+    c[0] = 2 * xh + ((c[1] + c[2] + c[3] + p) & 1);
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic sum over the block of `v` (blockDim.x multiple of 64, <= 1024);
+// the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) s += lds[w];
+    __syncthreads();
+    return s;
+}
+
+// Per-right-hand-side block sum: the thread with global point index gid adds
+// v to rhs gid % nrhs; out[r * stride] receives the block's sum for rhs r.
+// Deterministic (fixed order).  lds must hold blockDim.x doubles; needs
+// nrhs <= blockDim.x.  Every thread of the block must call it.
+__device__ __forceinline__ void block_sum_rhs(double v, long gid, int nrhs, double *lds, double *out,
+                                              long stride) {
+    if (nrhs == 1) {
+        const double s = block_sum(v, lds);
+        if (threadIdx.x == 0) out[0] = s;
+        return;
+    }
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+        const long g0 = gid - threadIdx.x;
+        const int r = threadIdx.x;
+        const int t0 = (int)(((long)r - g0 % nrhs + nrhs) % nrhs);
+        double s = 0.0;
+        for (int t = t0; t < (int)blockDim.x; t += nrhs) s += lds[t];
+        out[(long)r * stride] = s;
+    }
+    __syncthreads();
+}
+
+}  // namespace wl

@@ -1,0 +1,303 @@
+"""Python binding of the Wilson-operator C ABI (``include/wilson.h``).
+
+Argument marshalling only: every ``wl_*`` function below forwards to the
+C function of the same name in ``libwilson.so``; all computation happens in
+the library's HIP kernels.  Device buffers are passed as torch tensors (or raw
+integer addresses) and the HIP stream defaults to torch's current stream.
+There is no CPU fallback: if the library is missing, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwilson.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "wilson.h")
+
+# enums (wilson.h)
+WL_OK, WL_NOT_CONVERGED, WL_BREAKDOWN = 0, 1, 2
+WL_ERR_ARG, WL_ERR_DIMS, WL_ERR_HIP, WL_ERR_NOMEM, WL_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
+WL_F64, WL_F32, WL_F16N, WL_BF16N = 0, 1, 2, 3
+WL_EVEN, WL_ODD, WL_FULL = 0, 1, 2
+WL_OP_D, WL_OP_DHAT = 0, 1
+
+PREC = {"f64": WL_F64, "f32": WL_F32, "f16n": WL_F16N, "bf16n": WL_BF16N}
+SUBSET = {"even": WL_EVEN, "odd": WL_ODD, "full": WL_FULL}
+OP = {"D": WL_OP_D, "Dhat": WL_OP_DHAT}
+
+
+class WilsonError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("wilson library error %d: %s" % (status, message))
+        self.status = status
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int),
+        ("check_every", ctypes.c_int),
+        ("max_restarts", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("recon", ctypes.c_int),
+        ("reliable_every", ctypes.c_int),
+        ("reliable_delta", ctypes.c_double),
+        ("use_graph", ctypes.c_int),
+    ]
+
+
+class SolverInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("reliable_updates", ctypes.c_int),
+        ("rel_resid", ctypes.c_double),
+        ("true_rel_resid", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "wl_ctx_create": (ctypes.c_int, [_ip, _dp, _dp, ctypes.POINTER(_vp)]),
+    "wl_ctx_destroy": (ctypes.c_int, [_vp]),
+    "wl_ctx_prepare_links": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "wl_spinor_bytes": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "wl_pack_spinor": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_unpack_spinor": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_convert_spinor": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_dslash_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_dslash_dagger_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_dirac_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_eo_prepare": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_eo_reconstruct": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         _vp]),
+    "wl_blas_axpy": (ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_blas_dot": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _vp]),
+    "wl_blas_norm2": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _vp]),
+    "wl_solver_params_default": (None, [ctypes.POINTER(SolverParams)]),
+    "wl_cg_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                   ctypes.POINTER(SolverParams), ctypes.POINTER(SolverInfo), _vp]),
+    "wl_last_error": (ctypes.c_char_p, []),
+    "wl_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def header_functions(path: str = HEADER):
+    """Names of every function declared in include/wilson.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wl_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """Load libwilson.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libwilson.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        # torch ships its own HIP runtime; importing it first makes libwilson bind
+        # to that same runtime instead of mapping a second one into the process
+        import torch  # noqa: F401
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def last_error() -> str:
+    return lib().wl_last_error().decode()
+
+
+def _check(status):
+    if status < 0:
+        raise WilsonError(status, last_error())
+    return status
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- 1:1 wrappers
+def wl_ctx_create(dims, phases, gauge_host: np.ndarray) -> int:
+    g = np.ascontiguousarray(gauge_host, dtype=np.complex128)
+    d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+    z = np.asarray(phases, dtype=np.complex128).reshape(4)
+    ph = np.ascontiguousarray(np.stack([z.real, z.imag], -1).reshape(8))
+    out = _vp()
+    _check(lib().wl_ctx_create(d, ph.ctypes.data_as(_dp), g.view(np.float64).ctypes.data_as(_dp), ctypes.byref(out)))
+    return out.value
+
+
+def wl_ctx_destroy(ctx):
+    return _check(lib().wl_ctx_destroy(ctx))
+
+
+def wl_ctx_prepare_links(ctx, prec, recon):
+    return _check(lib().wl_ctx_prepare_links(ctx, prec, recon))
+
+
+def wl_spinor_bytes(ctx, subset, prec, nrhs=1) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().wl_spinor_bytes(ctx, subset, prec, nrhs, ctypes.byref(n)))
+    return n.value
+
+
+def wl_pack_spinor(ctx, dst, src, subset, prec, nrhs=1, stream=None):
+    return _check(lib().wl_pack_spinor(ctx, _ptr(dst), _ptr(src), subset, prec, nrhs, _stream(stream)))
+
+
+def wl_unpack_spinor(ctx, dst, src, subset, prec, nrhs=1, stream=None):
+    return _check(lib().wl_unpack_spinor(ctx, _ptr(dst), _ptr(src), subset, prec, nrhs, _stream(stream)))
+
+
+def wl_convert_spinor(ctx, dst, dprec, src, sprec, subset, nrhs=1, stream=None):
+    return _check(lib().wl_convert_spinor(ctx, _ptr(dst), dprec, _ptr(src), sprec, subset, nrhs, _stream(stream)))
+
+
+def wl_dslash_apply(ctx, out, inp, subset, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_dslash_apply(ctx, _ptr(out), _ptr(inp), subset, prec, recon, nrhs, _stream(stream)))
+
+
+def wl_dslash_dagger_apply(ctx, out, inp, subset, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_dslash_dagger_apply(ctx, _ptr(out), _ptr(inp), subset, prec, recon, nrhs,
+                                               _stream(stream)))
+
+
+def wl_dirac_apply(ctx, out, inp, op, dagger, kappa, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_dirac_apply(ctx, _ptr(out), _ptr(inp), op, int(bool(dagger)), float(kappa), prec, recon,
+                                       nrhs, _stream(stream)))
+
+
+def wl_eo_prepare(ctx, bhat_e, b_e, b_o, kappa, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_eo_prepare(ctx, _ptr(bhat_e), _ptr(b_e), _ptr(b_o), float(kappa), prec, recon, nrhs,
+                                      _stream(stream)))
+
+
+def wl_eo_reconstruct(ctx, x_o, x_e, b_o, kappa, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_eo_reconstruct(ctx, _ptr(x_o), _ptr(x_e), _ptr(b_o), float(kappa), prec, recon, nrhs,
+                                          _stream(stream)))
+
+
+def wl_blas_axpy(ctx, a, x, y, subset, prec=WL_F64, nrhs=1, stream=None):
+    return _check(lib().wl_blas_axpy(ctx, float(a), _ptr(x), _ptr(y), subset, prec, nrhs, _stream(stream)))
+
+
+def wl_blas_dot(ctx, x, y, subset, prec=WL_F64, nrhs=1, stream=None) -> complex:
+    out = (ctypes.c_double * 2)()
+    _check(lib().wl_blas_dot(ctx, _ptr(x), _ptr(y), subset, prec, nrhs, out, _stream(stream)))
+    return complex(out[0], out[1])
+
+
+def wl_blas_norm2(ctx, x, subset, prec=WL_F64, nrhs=1, stream=None) -> float:
+    out = ctypes.c_double()
+    _check(lib().wl_blas_norm2(ctx, _ptr(x), subset, prec, nrhs, ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def wl_solver_params_default() -> SolverParams:
+    p = SolverParams()
+    lib().wl_solver_params_default(ctypes.byref(p))
+    return p
+
+
+def wl_cg_solve(ctx, x, b, op, kappa, nrhs=1, params: SolverParams | None = None, stream=None):
+    """Returns (status, [info dict per rhs]); raises on negative status."""
+    p = params if params is not None else wl_solver_params_default()
+    info = (SolverInfo * nrhs)()
+    st = _check(lib().wl_cg_solve(ctx, _ptr(x), _ptr(b), op, float(kappa), nrhs, ctypes.byref(p), info,
+                                  _stream(stream)))
+    return st, [info[i].as_dict() for i in range(nrhs)]
+
+
+def wl_version() -> str:
+    return lib().wl_version().decode()
+
+
+# ---------------------------------------------------------------- convenience
+@dataclass
+class Lattice:
+    """A context plus helpers that allocate internal fields as torch tensors."""
+
+    dims: tuple
+    phases: tuple
+    ctx: int
+
+    @classmethod
+    def create(cls, gauge: np.ndarray, phases=(1, 1, 1, -1)):
+        lt, lz, ly, lx = gauge.shape[:4]
+        dims = (lx, ly, lz, lt)
+        return cls(dims, tuple(complex(p) for p in phases), wl_ctx_create(dims, phases, gauge))
+
+    def close(self):
+        if self.ctx:
+            wl_ctx_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def volume(self):
+        return int(np.prod(self.dims))
+
+    def new(self, subset=WL_FULL, prec=WL_F64, nrhs=1, zero=True):
+        import torch
+        n = wl_spinor_bytes(self.ctx, subset, prec, nrhs)
+        f = torch.empty(n, dtype=torch.uint8, device="cuda")
+        if zero:
+            f.zero_()
+        return f
+
+    def pack(self, canonical, subset=WL_FULL, prec=WL_F64, nrhs=1):
+        """canonical numpy/torch complex128 field -> new internal field."""
+        import torch
+        t = torch.as_tensor(np.ascontiguousarray(canonical)) if isinstance(canonical, np.ndarray) else canonical
+        t = t.to(device="cuda", dtype=torch.complex128).contiguous()
+        out = self.new(subset, prec, nrhs, zero=False)
+        wl_pack_spinor(self.ctx, out, t, subset, prec, nrhs)
+        return out
+
+    def unpack(self, internal, subset=WL_FULL, prec=WL_F64, nrhs=1) -> np.ndarray:
+        """internal field -> numpy complex128, shape (nrhs, nsites, 4, 3) (nrhs axis dropped if 1)."""
+        import torch
+        nsite = self.volume if subset == WL_FULL else self.volume // 2
+        out = torch.empty((nrhs, nsite, 4, 3), dtype=torch.complex128, device="cuda")
+        wl_unpack_spinor(self.ctx, out, internal, subset, prec, nrhs)
+        torch.cuda.synchronize()
+        a = out.cpu().numpy()
+        return a[0] if nrhs == 1 else a

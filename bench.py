@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: even/odd preconditioned Wilson CG on one MI355X.
+
+Workload (default): 24^3 x 48 lattice, links exp(0.2 i H) (seeded Gaussian
+traceless Hermitian H, reunitarised; seed 201), Gaussian source (seed 202),
+kappa = 0.135, periodic in space and antiperiodic in time, FP64 storage and
+arithmetic, 18-real links.
+
+One step solves D x = eta through the Schur complement D_hat = 1 - kappa^2 H_eo H_oe:
+  bhat = b_e + kappa H_eo b_o;  rhs = D_hat^+ bhat;
+  CG on D_hat^+ D_hat x_e = rhs to ||rhs - A x_e|| <= 1e-10 ||rhs||;
+  x_o = b_o + kappa H_oe x_e.
+All of it runs in the library's kernels; inputs are resident in HBM before the
+timed region starts.
+
+Reported:
+  value      whole-step throughput in GB/s = algorithmic bytes of every kernel
+             of the step (table in `step_bytes`) / step time;
+  roofline   the dominant kernel (the plain FP64 half-dslash, 1536 B per output
+             site) timed live with HIP events on its own stream over the timed
+             region: achieved = 1536 * Vh / average launch duration;
+  cpu_baseline  the FP64 CPU oracle running a bounded sample of the same CG
+             (fixed iterations) on the host cores, in the same unit.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+SITE_BYTES = {  # algorithmic bytes per output site of one half-dslash, FP64 storage, 18-real links
+    "hop": 8 * 144 + 192 + 192,          # 8 links + input spinor once + output spinor
+    "hop_xpay": 8 * 144 + 3 * 192,       # + the epilogue field x
+}
+WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.2, gauge_seed=201, src_seed=202, kappa=0.135,
+                phases=(1, 1, 1, -1), tol=1e-10)
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "hop_f64_24x24x24x48_traffic.txt")
+KERNEL_SOURCES = ["paper_1405_0700_amd/csrc/wl_dslash.hip", "paper_1405_0700_amd/csrc/wl_dslash.h",
+                  "paper_1405_0700_amd/csrc/wl_common.h"]
+
+
+def step_bytes(vh: int, iters: int, restarts: int) -> int:
+    """Algorithmic HBM bytes of one step (FP64 storage, 192 B per spinor site):
+
+      eo_prepare (hop + x read)                   1728
+      rhs = D_hat^+ bhat (hop, hop+x)             1536 + 1728
+      ||rhs||^2                                    192
+      per CG cycle (1 + restarts):
+        true residual b - A x at start and end:   2 x (2 x 1536 + 2 x 1728 + 576)
+        p = r copy                                  384
+      per CG iteration:
+        q = D_hat p (hop, hop+x, fused norm)      1536 + 1728
+        s = D_hat^+ q                             1536 + 1728
+        x += a p, r -= a s (x, r read+write; p, s read)   1152
+        p = r + b p                                 576
+      eo_reconstruct (hop + x read)               1728
+    per even site; the single-block scalar kernels are not counted.
+    """
+    h, hx = SITE_BYTES["hop"], SITE_BYTES["hop_xpay"]
+    true_res = 2 * h + 2 * hx + 576
+    per_iter = 2 * h + 2 * hx + 1152 + 576
+    fixed = hx + (h + hx) + 192 + hx
+    per_cycle = 2 * true_res + 384
+    return vh * (fixed + (1 + restarts) * per_cycle + iters * per_iter)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_inputs(wl):
+    from paper_1405_0700_amd import synth
+    u = synth.su3_links(wl["dims"], wl["eps"], wl["gauge_seed"])
+    eta = synth.gaussian_spinor(wl["dims"], wl["src_seed"])
+    return u, eta
+
+
+def cpu_baseline(u, eta, wl, x_gpu_even, x_gpu_odd, sample_iters):
+    """The FP64 oracle on the host: a fixed number of CG iterations on the same
+    Schur system, timed; also restates the GPU solution's residual."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    dims, kappa, ph = wl["dims"], wl["kappa"], wl["phases"]
+    be, bo = orc.eo_split(eta, dims)
+    bhat = orc.eo_prepare(be, bo, u, kappa, ph)
+    rhs = orc.schur(bhat, u, kappa, ph, dagger=True)
+    apply_a = lambda v: orc.schur(orc.schur(v, u, kappa, ph), u, kappa, ph, dagger=True)
+    t0 = time.perf_counter()
+    orc.cg(apply_a, rhs, fixed_iters=sample_iters)
+    dt = time.perf_counter() - t0
+    vh = be.shape[0]
+    # the sample's algorithmic bytes: iterations + its final true-residual check
+    nbytes = vh * (sample_iters * (2 * SITE_BYTES["hop"] + 2 * SITE_BYTES["hop_xpay"] + 1152 + 576)
+                   + 2 * SITE_BYTES["hop"] + 2 * SITE_BYTES["hop_xpay"] + 576)
+    out = {"value": round(nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": orc.max_threads(), "kind": "oracle",
+           "sample": "%d fixed CG iterations on D_hat^+ D_hat (24^3x48, FP64) plus its final residual check, "
+                     "%.1f s" % (sample_iters, dt)}
+    # the full-lattice residual of the GPU solution, restated by the oracle
+    x = orc.eo_join(x_gpu_even, x_gpu_odd, dims)
+    r = orc.dirac(x, u, kappa, ph) - eta
+    resid = float(np.linalg.norm(r) / np.linalg.norm(eta))
+    return out, resid
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--cpu-iters", type=int, default=5, help="CG iterations of the CPU-oracle sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of this size (counter calibration) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (--gpus 1); %d requested" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU available", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "launches": 5}))
+        return
+
+    from paper_1405_0700_amd import wilson as W
+    wl = WORKLOAD
+    t0 = time.perf_counter()
+    u, eta = make_inputs(wl)
+    print("[bench] inputs generated in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    lat = W.Lattice.create(u, wl["phases"])
+    vh = lat.volume // 2
+    # an internal FULL field is the EVEN half followed by the ODD half
+    B = lat.pack(eta, W.WL_FULL)
+    Be, Bo = B[: B.numel() // 2], B[B.numel() // 2:]
+    bhat = lat.new(W.WL_EVEN)
+    rhs = lat.new(W.WL_EVEN)
+    xe = lat.new(W.WL_EVEN)
+    xo = lat.new(W.WL_ODD)
+    kappa = wl["kappa"]
+    params = W.wl_solver_params_default()
+    params.tol = wl["tol"]
+
+    def step():
+        xe.zero_()
+        W.wl_eo_prepare(lat.ctx, bhat, Be, Bo, kappa)
+        W.wl_dirac_apply(lat.ctx, rhs, bhat, W.WL_OP_DHAT, True, kappa)
+        st, info = W.wl_cg_solve(lat.ctx, xe, rhs, W.WL_OP_DHAT, kappa, params=params)
+        W.wl_eo_reconstruct(lat.ctx, xo, xe, Bo, kappa)
+        return st, info[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    W.wl_timing_enable(lat.ctx, True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        st, info = step()
+        if st != W.WL_OK:
+            print("[bench] solver status %d: %s" % (st, W.last_error()), file=sys.stderr)
+        infos.append(info)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    nbytes = sum(step_bytes(vh, i["iters"], i["restarts"]) for i in infos)
+    value = nbytes / (total_ms * 1e-3) / 1e9
+
+    n_hop, ms_hop = W.wl_timing_read(lat.ctx, W.WL_F64, 18, False, 0)
+    W.wl_timing_enable(lat.ctx, False)
+    avg_ms = ms_hop / max(n_hop, 1)
+    achieved = SITE_BYTES["hop"] * vh / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "hop_kernel<F64,F64,18,dagger=false,epilogue=0> (half-dslash H_oe)",
+                "launches": n_hop, "avg_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": SITE_BYTES["hop"] * vh}
+
+    cpu = None
+    resid = None
+    if not args.no_cpu:
+        xe_np = lat.unpack(xe, W.WL_EVEN)
+        xo_np = lat.unpack(xo, W.WL_ODD)
+        cpu, resid = cpu_baseline(u, eta, wl, xe_np, xo_np, args.cpu_iters)
+
+    last = infos[-1]
+    line = {
+        "metric": "dslash GB/s (% HBM peak); CG time-to-1e-10: plain FP64 vs mixed/learned",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "even/odd Wilson CG to 1e-10, 24^3x48, kappa 0.135, links exp(0.2iH) seed 201, "
+                               "Gaussian source seed 202, FP64, 18-real links",
+                   "lattice": list(wl["dims"]), "kappa": kappa, "precision": "f64", "recon": 18},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "time_to_solution_ms": round(ms_per_step, 3),
+        "cg_iters": last["iters"],
+        "cg_restarts": last["restarts"],
+        "true_rel_resid_gpu": last["true_rel_resid"],
+        "oracle_full_system_rel_resid": resid,
+        "algorithmic_bytes_per_step": nbytes // args.steps,
+    }
+    print(json.dumps(line))
+    lat.close()
+
+
+if __name__ == "__main__":
+    main()

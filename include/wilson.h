@@ -102,6 +102,29 @@ wl_status wl_ctx_destroy(wl_ctx *ctx);
  * as the complex conjugate of their cross product).  Synchronous. */
 wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
 
+/* Launch configuration of the hopping kernel for one storage precision.
+ *   block   threads per block: 64, 128, 192 or 256
+ *   swizzle 1: reorder blocks so that each of the 8 XCDs (each with its own L2)
+ *           processes one contiguous range of the processing order; 0: hardware order
+ *   tps     threads per output point: 1 (one thread does all 8 hops) or 2 (the
+ *           forward and backward hops run in the two halves of a wavefront;
+ *           FP64 and FP32 storage only, else WL_ERR_UNSUPPORTED)
+ *   tchunk  processing order of the output sites: 0 = even/odd index order
+ *           (t slowest); k > 0 = the lattice is cut into chunks of k time
+ *           slices and each chunk is walked with z slowest, so that the
+ *           neighbours in t and z of a site are read close together in time
+ * Results do not depend on block, swizzle or tchunk; tps changes the
+ * summation order of the 8 hops (rounding only).  Defaults are chosen per
+ * precision by measurement (see wl_ctx_get_launch). */
+typedef struct {
+    int block;
+    int swizzle;
+    int tps;
+    int tchunk;
+} wl_launch;
+wl_status wl_ctx_set_launch(wl_ctx *ctx, wl_prec prec, const wl_launch *cfg);
+wl_status wl_ctx_get_launch(const wl_ctx *ctx, wl_prec prec, wl_launch *cfg);
+
 /* Bytes of an internal spinor field of `nrhs` right-hand sides. */
 wl_status wl_spinor_bytes(const wl_ctx *ctx, wl_subset subset, wl_prec prec,
                           int nrhs, size_t *bytes);
@@ -196,6 +219,21 @@ void wl_solver_params_default(wl_solver_params *p);
  * Synchronous: returns when done.  info may be NULL (else nrhs entries). */
 wl_status wl_cg_solve(wl_ctx *ctx, void *x, const void *b, wl_op op, double kappa, int nrhs,
                       const wl_solver_params *params, wl_solver_info *info, void *stream);
+
+/* ---------------------------------------------------------------- kernel timing */
+
+/* While enabled, every launch of the hopping-term kernel made through this
+ * context (by the operators and the solvers) is bracketed by a pair of HIP
+ * events recorded on the stream it is launched on.  Enabling (or disabling)
+ * discards what was recorded.  At most 1 << 16 launches are recorded. */
+wl_status wl_timing_enable(wl_ctx *ctx, int enable);
+
+/* Number and summed GPU duration (milliseconds) of the recorded launches of
+ * the hopping kernel with the given storage precision, link format, dagger
+ * flag and epilogue (0 = plain out = H in; 1 = out = a x + b H in;
+ * 3 = the same plus the fused ||out||^2).  Synchronises on the recorded events. */
+wl_status wl_timing_read(wl_ctx *ctx, wl_prec prec, int recon, int dagger, int epilogue, int *count,
+                         double *total_ms);
 
 /* ---------------------------------------------------------------- misc */
 

@@ -61,8 +61,25 @@ struct wl_ctx {
     size_t buf_bytes[S_NSLOTS] = {};
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
-    LaunchCfg cfg;
+    LaunchCfg cfg[4];  // hopping-kernel launch configuration per storage precision
+    // kernel timing
+    bool timing = false;
+    struct TimedLaunch {
+        int key;
+        hipEvent_t ev[2];
+        int iter;   // CG iteration the launch belongs to (-1: none)
+        int cycle;  // CG cycle serial number
+    };
+    int timing_iter = -1;
+    int timing_cycle = 0;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+    size_t pool_used = 0;
 };
+
+static int timing_key(int prec, int recon, int dagger, int epi) {
+    return ((prec * 2 + (recon == 12 ? 1 : 0)) * 2 + (dagger ? 1 : 0)) * 4 + epi;
+}
 
 static bool prec_ok(int p) { return p >= WL_F64 && p <= WL_BF16N; }
 static bool recon_ok(int prec, int r) {
@@ -294,6 +311,7 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
 extern "C" wl_status wl_ctx_destroy(wl_ctx *c) {
     if (!c) return WL_OK;
     (void)hipDeviceSynchronize();
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     for (int p = 0; p < 4; ++p)
         for (int r = 0; r < 2; ++r)
             if (c->gauge[p][r]) (void)hipFree(c->gauge[p][r]);
@@ -453,8 +471,26 @@ static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, voi
         h.x[p] = x;
         h.out_par0 = p;
     }
-    HIP_TRY(launch_hop(prec, recon, dag, epi, h, np, c->cfg, s));
-    if (nblk_out) *nblk_out = hop_blocks(h.npts, c->cfg.block) * np;
+    hipEvent_t *ev = nullptr;
+    if (c->timing && c->timed.size() < (1u << 16)) {
+        if (c->pool_used + 2 > c->event_pool.size()) {
+            for (int k = 0; k < 256; ++k) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                c->event_pool.push_back(e);
+            }
+        }
+        c->timed.push_back({timing_key(prec, recon, dag, epi),
+                            {c->event_pool[c->pool_used], c->event_pool[c->pool_used + 1]},
+                            c->timing_iter, c->timing_cycle});
+        c->pool_used += 2;
+        ev = c->timed.back().ev;
+        HIP_TRY(hipEventRecord(ev[0], s));
+    }
+    const LaunchCfg &cfg = c->cfg[prec];
+    HIP_TRY(launch_hop(prec, recon, dag, epi, h, np, cfg, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (nblk_out) *nblk_out = hop_blocks(h.npts, cfg.block, effective_tps(prec, cfg)) * np;
     return WL_OK;
 }
 
@@ -547,7 +583,7 @@ extern "C" wl_status wl_eo_reconstruct(const wl_ctx *c, void *x_o, const void *x
 // ------------------------------------------------------------------ BLAS API
 static long part_stride_for(const wl_ctx *c, int nrhs) {
     const long n = c->Vh * (long)nrhs;
-    const long hb = hop_blocks(n, 64) * 2;  // the smallest block size any kernel may use
+    const long hb = hop_blocks(n, 64, 2) * 2;  // the most blocks any hopping launch may use
     const long bb = blas_blocks(n) * 2;
     return std::max(hb, bb);
 }
@@ -825,30 +861,54 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
         st = load_residual(R);
         if (st) return st;
         int since_reliable = 0, k = 0;
+        // Iterations are enqueued in blocks between host reads of the device
+        // scalars.  Near convergence the block is sized from the observed decay
+        // of ||r||^2 (with a margin), so that few or no iterations are enqueued
+        // after the last one that does work (those launches exit at once).
+        int block = std::max(1, std::min(P.check_every, remaining));
+        std::vector<double> prev_rho(nrhs, -1.0);
+        std::vector<int> prev_it(nrhs, 0);
+        ++c->timing_cycle;
         for (;;) {
-            for (int j = 0; j < P.check_every; ++j, ++k) {
+            for (int j = 0; j < block; ++j, ++k) {
                 bool ru = false;
                 if (mixed && P.reliable_every > 0 && ++since_reliable >= P.reliable_every) {
                     ru = true;
                     since_reliable = 0;
                     for (int r = 0; r < nrhs; ++r) reliable[r]++;
                 }
+                c->timing_iter = k;
                 st = cg_iteration(R, ru);
+                c->timing_iter = -1;
                 if (st) return st;
             }
             HIP_TRY(hipMemcpyAsync(c->host_pinned, R.sc, sizeof(CGScalars) * nrhs, hipMemcpyDeviceToHost, R.s));
             HIP_TRY(hipStreamSynchronize(R.s));
             std::memcpy(hsc.data(), c->host_pinned, sizeof(CGScalars) * nrhs);
             bool any = false, need_ru = false;
+            int next = 1;
             for (int r = 0; r < nrhs; ++r) {
-                any |= hsc[r].active != 0;
-                if (mixed && hsc[r].active && hsc[r].rho < P.reliable_delta * P.reliable_delta * hsc[r].rho_max)
-                    need_ru = true;
+                const CGScalars &h = hsc[r];
+                any |= h.active != 0;
+                if (!h.active) continue;
+                if (mixed && h.rho < P.reliable_delta * P.reliable_delta * h.rho_max) need_ru = true;
+                int est = P.check_every;
+                if (prev_rho[r] > 0.0 && h.rho < prev_rho[r] && h.iter > prev_it[r] && h.target > 0.0) {
+                    const double rate = std::log(h.rho / prev_rho[r]) / (h.iter - prev_it[r]);
+                    const double left = std::log(h.target / h.rho) / rate;
+                    if (std::isfinite(left)) est = (int)std::floor(0.8 * left);
+                }
+                prev_rho[r] = h.rho;
+                prev_it[r] = h.iter;
+                next = std::max(next, std::min(est, P.check_every));
             }
             if (!any) break;
+            block = std::max(1, next);
             if (need_ru) {
                 // an FP64 refresh forced by the residual drop, carried by the next iteration
+                c->timing_iter = k++;
                 st = cg_iteration(R, true);
+                c->timing_iter = -1;
                 if (st) return st;
                 since_reliable = 0;
                 for (int r = 0; r < nrhs; ++r) reliable[r]++;
@@ -863,6 +923,15 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
             breakdown |= hsc[r].status == WL_BREAKDOWN;
         }
         remaining -= maxit;
+        if (c->timing) {
+            // launches of iterations past the last one that ran exited at once: drop them
+            auto &t = c->timed;
+            t.erase(std::remove_if(t.begin(), t.end(),
+                                   [&](const wl_ctx::TimedLaunch &x) {
+                                       return x.cycle == c->timing_cycle && x.iter >= maxit;
+                                   }),
+                    t.end());
+        }
         // FP64 true residual of the result
         st = true_residual(R);
         if (st) return st;
@@ -902,4 +971,68 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
     if (result == WL_BREAKDOWN) fail(WL_BREAKDOWN, "CG breakdown (NaN/Inf or non-positive <p, A p>)");
     else if (result == WL_NOT_CONVERGED) fail(WL_NOT_CONVERGED, "CG did not reach the tolerance");
     return result;
+}
+
+// ------------------------------------------------------------------ timing API
+extern "C" wl_status wl_timing_enable(wl_ctx *c, int enable) {
+    g_err.clear();
+    if (!c) return fail(WL_ERR_ARG, "null context");
+    HIP_TRY(hipDeviceSynchronize());
+    c->timed.clear();
+    c->pool_used = 0;
+    c->timing = enable != 0;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_timing_read(wl_ctx *c, wl_prec prec, int recon, int dagger, int epilogue, int *count,
+                                    double *total_ms) {
+    g_err.clear();
+    if (!c || !count || !total_ms) return fail(WL_ERR_ARG, "null argument");
+    if (!prec_ok(prec) || !recon_ok(prec, recon) || epilogue < 0 || epilogue > 3)
+        return fail(WL_ERR_ARG, "bad kernel selector");
+    const int key = timing_key(prec, recon, dagger != 0, epilogue);
+    int n = 0;
+    double ms = 0.0;
+    for (auto &t : c->timed) {
+        if (t.key != key) continue;
+        HIP_TRY(hipEventSynchronize(t.ev[1]));
+        float m = 0.f;
+        HIP_TRY(hipEventElapsedTime(&m, t.ev[0], t.ev[1]));
+        ms += m;
+        ++n;
+    }
+    *count = n;
+    *total_ms = ms;
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ launch configuration
+extern "C" wl_status wl_ctx_set_launch(wl_ctx *c, wl_prec prec, const wl_launch *l) {
+    g_err.clear();
+    if (!c || !l) return fail(WL_ERR_ARG, "null argument");
+    if (!prec_ok(prec)) return fail(WL_ERR_ARG, "bad precision %d", (int)prec);
+    if (l->block < 64 || l->block > 256 || l->block % 64)
+        return fail(WL_ERR_ARG, "block %d not in {64, 128, 192, 256}", l->block);
+    if (l->tps != 1 && l->tps != 2) return fail(WL_ERR_ARG, "tps %d not in {1, 2}", l->tps);
+    if (l->tps == 2 && prec != WL_F64 && prec != WL_F32)
+        return fail(WL_ERR_UNSUPPORTED, "two threads per point needs FP64 or FP32 storage");
+    if (l->tchunk < 0) return fail(WL_ERR_ARG, "tchunk %d < 0", l->tchunk);
+    LaunchCfg &g = c->cfg[prec];
+    g.block = l->block;
+    g.swizzle = l->swizzle ? 1 : 0;
+    g.tps = l->tps;
+    g.tchunk = l->tchunk;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ctx_get_launch(const wl_ctx *c, wl_prec prec, wl_launch *l) {
+    g_err.clear();
+    if (!c || !l) return fail(WL_ERR_ARG, "null argument");
+    if (!prec_ok(prec)) return fail(WL_ERR_ARG, "bad precision %d", (int)prec);
+    const LaunchCfg &g = c->cfg[prec];
+    l->block = g.block;
+    l->swizzle = g.swizzle;
+    l->tps = g.tps;
+    l->tchunk = g.tchunk;
+    return WL_OK;
 }

@@ -93,6 +93,20 @@ template <> struct SpinorIO<WL_F64> {
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c * n + i] = make_double2(v[c].re, v[c].im);
     }
+    // components 6 hf .. 6 hf + 5 (spins 2 hf, 2 hf + 1)
+    __device__ static void load_half(const void *base, long n, long i, int hf, cpx<double> v[6]) {
+        const double2 *p = (const double2 *)base + (long)(6 * hf) * n;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            double2 d = p[c * n + i];
+            v[c] = {d.x, d.y};
+        }
+    }
+    __device__ static void store_half(void *base, long n, long i, int hf, const cpx<double> v[6]) {
+        double2 *p = (double2 *)base + (long)(6 * hf) * n;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) p[c * n + i] = make_double2(v[c].re, v[c].im);
+    }
 };
 
 template <> struct SpinorIO<WL_F32> {
@@ -111,6 +125,22 @@ template <> struct SpinorIO<WL_F32> {
         float4 *p = (float4 *)base;
 #pragma unroll
         for (int k = 0; k < 6; ++k)
+            p[k * n + i] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    }
+    // components 6 hf .. 6 hf + 5 (spins 2 hf, 2 hf + 1)
+    __device__ static void load_half(const void *base, long n, long i, int hf, cpx<float> v[6]) {
+        const float4 *p = (const float4 *)base + (long)(3 * hf) * n;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float4 d = p[k * n + i];
+            v[2 * k] = {d.x, d.y};
+            v[2 * k + 1] = {d.z, d.w};
+        }
+    }
+    __device__ static void store_half(void *base, long n, long i, int hf, const cpx<float> v[6]) {
+        float4 *p = (float4 *)base + (long)(3 * hf) * n;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
             p[k * n + i] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
     }
 };
@@ -348,6 +378,28 @@ __device__ __forceinline__ void block_sum_rhs(double v, long gid, int nrhs, doub
         const int t0 = (int)(((long)r - g0 % nrhs + nrhs) % nrhs);
         double s = 0.0;
         for (int t = t0; t < (int)blockDim.x; t += nrhs) s += lds[t];
+        out[(long)r * stride] = s;
+    }
+    __syncthreads();
+}
+
+// Per-right-hand-side block sum where each thread names its own rhs.
+// lds / lrhs must hold blockDim.x entries.  Every thread must call it.
+__device__ __forceinline__ void block_sum_by_rhs(double v, int rhs, int nrhs, double *lds, int *lrhs, double *out,
+                                                 long stride) {
+    if (nrhs == 1) {
+        const double s = block_sum(v, lds);
+        if (threadIdx.x == 0) out[0] = s;
+        return;
+    }
+    lds[threadIdx.x] = v;
+    lrhs[threadIdx.x] = rhs;
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+        const int r = threadIdx.x;
+        double s = 0.0;
+        for (int t = 0; t < (int)blockDim.x; ++t)
+            if (lrhs[t] == r) s += lds[t];
         out[(long)r * stride] = s;
     }
     __syncthreads();

@@ -22,11 +22,17 @@ struct HopArgs {
     long part_stride;     // distance between the partials of consecutive rhs
     const int *flag;      // if non-null and *flag != 0 the launch does nothing
     int swizzle;          // map consecutive blocks to the same XCD
+    int tchunk;           // processing order (see LaunchCfg)
+    int chunk_sites;      // sites of a full chunk: tchunk * Lz * (Lx/2) * Ly
 };
 
 struct LaunchCfg {
-    int block = 256;
-    int swizzle = 1;
+    int block = 256;   // threads per block (multiple of 64, <= 256)
+    int swizzle = 1;   // give each XCD one contiguous range of blocks
+    int tps = 1;       // threads per output point: 1, or 2 (forward / backward hops in
+                       // the two halves of a wavefront; FP64 and FP32 storage only)
+    int tchunk = 0;    // processing order: 0 = e/o index order; k = chunks of k time
+                       // slices, each walked with z slowest
 };
 
 // Enqueue out = a x + b H in (H^+ if dagger) over `nparity` output parities.
@@ -34,7 +40,10 @@ struct LaunchCfg {
 hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int nparity,
                       const LaunchCfg &cfg, hipStream_t stream);
 
+// threads per point actually used for a storage precision
+int effective_tps(int prec, const LaunchCfg &cfg);
+
 // number of blocks per parity for a given configuration
-inline long hop_blocks(long npts, int block) { return (npts + block - 1) / block; }
+inline long hop_blocks(long npts, int block, int tps = 1) { return (npts * tps + block - 1) / block; }
 
 }  // namespace wl

@@ -17,6 +17,11 @@
 // on one contiguous range of sites and the neighbour re-reads hit its L2.
 #include "wl_dslash.h"
 
+// minimum waves per SIMD requested for the split kernel (1: no register cap)
+#ifndef WL_SPLIT_MINW
+#define WL_SPLIT_MINW 1
+#endif
+
 namespace wl {
 
 // -i a
@@ -134,6 +139,116 @@ __device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, co
     accumulate<T, MU, S>(acc, v);
 }
 
+// ---- split variant: the direction of the hop (forward / backward) is a
+// per-lane runtime value, so that both halves of a wavefront run the same
+// instruction stream; the projector sign becomes a runtime +-1 and the
+// backward link is transposed and conjugated by selects.
+
+// h = upper + s * A_mu * lower
+template <typename T, int MU>
+__device__ __forceinline__ void project_rt(const cpx<T> f[12], T s, cpx<T> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> u0 = f[c], u1 = f[3 + c], l0 = f[6 + c], l1 = f[9 + c];
+        cpx<T> a0, a1;
+        if constexpr (MU == 0) {
+            a0 = mi(l1);
+            a1 = mi(l0);
+        } else if constexpr (MU == 1) {
+            a0 = -l1;
+            a1 = l0;
+        } else if constexpr (MU == 2) {
+            a0 = mi(l0);
+            a1 = ti(l1);
+        } else {
+            a0 = -l0;
+            a1 = -l1;
+        }
+        h[c] = {fma(s, a0.re, u0.re), fma(s, a0.im, u0.im)};
+        h[3 + c] = {fma(s, a1.re, u1.re), fma(s, a1.im, u1.im)};
+    }
+}
+
+// acc_up += v ; acc_lo += s * A_mu^+ v
+template <typename T, int MU>
+__device__ __forceinline__ void accumulate_rt(cpx<T> acc[12], const cpx<T> v[6], T s) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> v0 = v[c], v1 = v[3 + c];
+        acc[c] = acc[c] + v0;
+        acc[3 + c] = acc[3 + c] + v1;
+        cpx<T> w0, w1;
+        if constexpr (MU == 0) {
+            w0 = ti(v1);
+            w1 = ti(v0);
+        } else if constexpr (MU == 1) {
+            w0 = v1;
+            w1 = -v0;
+        } else if constexpr (MU == 2) {
+            w0 = ti(v0);
+            w1 = mi(v1);
+        } else {
+            w0 = -v0;
+            w1 = -v1;
+        }
+        acc[6 + c] = {fma(s, w0.re, acc[6 + c].re), fma(s, w0.im, acc[6 + c].im)};
+        acc[9 + c] = {fma(s, w1.re, acc[9 + c].re), fma(s, w1.im, acc[9 + c].im)};
+    }
+}
+
+template <int SP, int GP, int RECON, bool DAG, int MU>
+__device__ __forceinline__ void hop_rt(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs, bool fwd,
+                                       cpx<typename SpinorIO<SP>::real> acc[12]) {
+    using T = typename SpinorIO<SP>::real;
+    const Geom &g = a.g;
+    int j;
+    bool wrap;
+    if constexpr (MU == 0) {
+        int x = c[0] + (fwd ? 1 : -1);
+        wrap = fwd ? (x == g.L[0]) : (x < 0);
+        if (wrap) x = fwd ? 0 : g.L[0] - 1;
+        j = (i - xh) + (x >> 1);
+    } else {
+        const int stride = MU == 1 ? g.sy : (MU == 2 ? g.sz : g.st);
+        wrap = fwd ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
+        j = fwd ? i + stride : i - stride;
+        if (wrap) j += fwd ? -g.L[MU] * stride : g.L[MU] * stride;
+    }
+    const T s = (fwd != DAG) ? T(-1) : T(1);
+    cpx<T> f[12], h[6], u[9], w[9], v[6];
+    SpinorIO<SP>::load(a.in[1 - par], a.npts, (long)j * a.nrhs + rhs, f);
+    const int lpar = fwd ? par : 1 - par;
+    const char *slab = (const char *)a.gauge + (size_t)(lpar * 4 + MU) * a.slab_bytes;
+    LinkIO<GP, RECON>::load(slab, g.vh, fwd ? i : j, u);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) w[3 * r + q] = fwd ? u[3 * r + q] : conjg(u[3 * q + r]);
+    project_rt<T, MU>(f, s, h);
+    su3_mul2<T, true>(w, h, v);
+    if (wrap && ((g.phase_mask >> MU) & 1)) {
+        const cpx<T> z = {(T)g.zr[MU], fwd ? (T)g.zi[MU] : -(T)g.zi[MU]};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = cmul(z, v[k]);
+    }
+    accumulate_rt<T, MU>(acc, v, s);
+}
+
+// e/o index of the site at position ps of the processing order
+__device__ __forceinline__ int site_of(const HopArgs &a, long ps) {
+    if (a.tchunk <= 0) return (int)ps;
+    const Geom &g = a.g;
+    const int plane = g.sz;  // (Lx/2) * Ly sites of one (z, t)
+    const long chunk = ps / a.chunk_sites;
+    const int r = (int)(ps - chunk * a.chunk_sites);
+    const int t0 = (int)chunk * a.tchunk;
+    const int trc = min(a.tchunk, g.L[3] - t0);  // the last chunk may be shorter
+    const int yx = r % plane;
+    const int q = r / plane;
+    const int tl = q % trc, z = q / trc;
+    return yx + plane * (z + g.L[2] * (t0 + tl));
+}
+
 __device__ __forceinline__ long logical_block(int swizzle) {
     const long nb = gridDim.x, bid = blockIdx.x;
     if (!swizzle || nb < 16) return bid;
@@ -142,19 +257,22 @@ __device__ __forceinline__ long logical_block(int swizzle) {
     return xcd * q + (xcd < r ? xcd : r) + bid / 8;
 }
 
+// One thread per output point.
 template <int SP, int GP, int RECON, bool DAG, int EPI>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     using T = typename SpinorIO<SP>::real;
     if (a.flag && *a.flag) return;
     const int par = a.out_par0 + blockIdx.y;
     const long lb = logical_block(a.swizzle);
-    const long gid = lb * blockDim.x + threadIdx.x;
+    const long gid = lb * blockDim.x + threadIdx.x;  // position in the processing order
+    long pt = 0;                                       // memory index of the point
     const bool active = gid < a.npts;
     double nrm = 0.0;
-    int rhs = 0;
     if (active) {
-        const int i = (int)(gid / a.nrhs);
-        rhs = (int)(gid - (long)i * a.nrhs);
+        const long ps = gid / a.nrhs;
+        const int rhs = (int)(gid - ps * a.nrhs);
+        const int i = site_of(a, ps);
+        pt = (long)i * a.nrhs + rhs;
         int c[4];
         eo_coords(a.g, i, par, c);
         const int xh = c[0] >> 1;
@@ -172,7 +290,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         const T b = (T)a.b;
         if constexpr (EPI & EPI_XPAY) {
             cpx<T> xv[12];
-            SpinorIO<SP>::load(a.x[par], a.npts, gid, xv);
+            SpinorIO<SP>::load(a.x[par], a.npts, pt, xv);
             const T aa = (T)a.a;
 #pragma unroll
             for (int k = 0; k < 12; ++k)
@@ -181,7 +299,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = b * acc[k];
         }
-        SpinorIO<SP>::store(a.out[par], a.npts, gid, acc);
+        SpinorIO<SP>::store(a.out[par], a.npts, pt, acc);
         if constexpr (EPI & EPI_NORM) {
             if constexpr (SP == WL_F64) {
 #pragma unroll
@@ -189,7 +307,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
             } else {
                 // the norm of what was stored (after rounding to the storage format)
                 cpx<T> st[12];
-                SpinorIO<SP>::load(a.out[par], a.npts, gid, st);
+                SpinorIO<SP>::load(a.out[par], a.npts, pt, st);
 #pragma unroll
                 for (int k = 0; k < 12; ++k)
                     nrm += (double)st[k].re * st[k].re + (double)st[k].im * st[k].im;
@@ -203,41 +321,129 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     }
 }
 
+// Two threads per output point: lanes 0-31 of a wavefront take the forward
+// hops of 32 consecutive points, lanes 32-63 the backward hops of the same
+// points; the partial sums are exchanged across the halves and each half
+// finishes and stores two of the four spin components.
+template <int SP, int GP, int RECON, bool DAG, int EPI>
+__global__ void __launch_bounds__(256, WL_SPLIT_MINW) hop_kernel_split(const HopArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    if (a.flag && *a.flag) return;
+    const int par = a.out_par0 + blockIdx.y;
+    const long lb = logical_block(a.swizzle);
+    const int lane = threadIdx.x & 63;
+    const bool fwd = lane < 32;
+    const int hf = fwd ? 0 : 1;  // spin half this lane stores
+    const long gid = ((lb * blockDim.x + threadIdx.x) >> 6) * 32 + (lane & 31);
+    long pt = 0;
+    const bool active = gid < a.npts;
+    cpx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    if (active) {
+        const long ps = gid / a.nrhs;
+        const int rhs = (int)(gid - ps * a.nrhs);
+        const int i = site_of(a, ps);
+        pt = (long)i * a.nrhs + rhs;
+        int c[4];
+        eo_coords(a.g, i, par, c);
+        const int xh = c[0] >> 1;
+        hop_rt<SP, GP, RECON, DAG, 0>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, 1>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, 2>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, 3>(a, par, i, xh, c, rhs, fwd, acc);
+    }
+    // every lane takes part in the exchange
+    cpx<T> res[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const cpx<T> send = fwd ? acc[6 + k] : acc[k];
+        const cpx<T> own = fwd ? acc[k] : acc[6 + k];
+        const cpx<T> recv = {__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
+        res[k] = own + recv;
+    }
+    double nrm = 0.0;
+    if (active) {
+        const T b = (T)a.b;
+        if constexpr (EPI & EPI_XPAY) {
+            cpx<T> xv[6];
+            SpinorIO<SP>::load_half(a.x[par], a.npts, pt, hf, xv);
+            const T aa = (T)a.a;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                res[k] = {fma(b, res[k].re, aa * xv[k].re), fma(b, res[k].im, aa * xv[k].im)};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) res[k] = b * res[k];
+        }
+        SpinorIO<SP>::store_half(a.out[par], a.npts, pt, hf, res);
+        if constexpr (EPI & EPI_NORM) {
+            if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(a.out[par], a.npts, pt, hf, res);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
+        }
+    }
+    if constexpr (EPI & EPI_NORM) {
+        __shared__ double lds[256];
+        __shared__ int lrhs[256];
+        const long blk = (long)blockIdx.y * gridDim.x + lb;
+        block_sum_by_rhs(nrm, (int)(gid % a.nrhs), a.nrhs, lds, lrhs, a.partials + blk, a.part_stride);
+    }
+}
+
+template <int SP, int GP, int RECON, bool DAG, int EPI>
+static void launch_one(int tps, dim3 grid, dim3 block, hipStream_t s, const HopArgs &a) {
+    if constexpr (SP == WL_F64 || SP == WL_F32) {
+        if (tps == 2) {
+            hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI>), grid, block, 0, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI>), grid, block, 0, s, a);
+}
+
 template <int SP, int GP, int RECON, bool DAG>
-static hipError_t launch_epi(int epi, HopArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+static hipError_t launch_epi(int epi, int tps, HopArgs &a, dim3 grid, dim3 block, hipStream_t s) {
     switch (epi) {
-    case 0: hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, 0>), grid, block, 0, s, a); break;
-    case EPI_XPAY: hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI_XPAY>), grid, block, 0, s, a); break;
-    case EPI_NORM: hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI_NORM>), grid, block, 0, s, a); break;
-    case EPI_XPAY | EPI_NORM:
-        hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM>), grid, block, 0, s, a);
-        break;
+    case 0: launch_one<SP, GP, RECON, DAG, 0>(tps, grid, block, s, a); break;
+    case EPI_XPAY: launch_one<SP, GP, RECON, DAG, EPI_XPAY>(tps, grid, block, s, a); break;
+    case EPI_NORM: launch_one<SP, GP, RECON, DAG, EPI_NORM>(tps, grid, block, s, a); break;
+    case EPI_XPAY | EPI_NORM: launch_one<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM>(tps, grid, block, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <int SP, int GP, int RECON>
-static hipError_t launch_dag(bool dag, int epi, HopArgs &a, dim3 grid, dim3 block, hipStream_t s) {
-    return dag ? launch_epi<SP, GP, RECON, true>(epi, a, grid, block, s)
-               : launch_epi<SP, GP, RECON, false>(epi, a, grid, block, s);
+static hipError_t launch_dag(bool dag, int epi, int tps, HopArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+    return dag ? launch_epi<SP, GP, RECON, true>(epi, tps, a, grid, block, s)
+               : launch_epi<SP, GP, RECON, false>(epi, tps, a, grid, block, s);
+}
+
+int effective_tps(int prec, const LaunchCfg &cfg) {
+    return (prec == WL_F64 || prec == WL_F32) && cfg.tps == 2 ? 2 : 1;
 }
 
 hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int nparity,
                       const LaunchCfg &cfg, hipStream_t stream) {
     const int block = cfg.block;
     if (block <= 0 || block > 256 || block % 64) return hipErrorInvalidValue;
+    const int tps = effective_tps(prec, cfg);
     a.swizzle = cfg.swizzle;
-    dim3 grid((unsigned)hop_blocks(a.npts, block), (unsigned)nparity);
+    a.tchunk = cfg.tchunk > 0 && cfg.tchunk < a.g.L[3] ? cfg.tchunk : 0;
+    a.chunk_sites = a.tchunk * a.g.L[2] * a.g.sz;
+    dim3 grid((unsigned)hop_blocks(a.npts, block, tps), (unsigned)nparity);
     dim3 blk(block);
     if (prec == WL_F64)
-        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, epi, a, grid, blk, stream)
-                           : launch_dag<WL_F64, WL_F64, 18>(dagger, epi, a, grid, blk, stream);
+        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, epi, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F64, WL_F64, 18>(dagger, epi, tps, a, grid, blk, stream);
     if (prec == WL_F32)
-        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, epi, a, grid, blk, stream)
-                           : launch_dag<WL_F32, WL_F32, 18>(dagger, epi, a, grid, blk, stream);
-    if (prec == WL_F16N && recon == 12) return launch_dag<WL_F16N, WL_F16N, 12>(dagger, epi, a, grid, blk, stream);
-    if (prec == WL_BF16N && recon == 12) return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, epi, a, grid, blk, stream);
+        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, epi, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F32, WL_F32, 18>(dagger, epi, tps, a, grid, blk, stream);
+    if (prec == WL_F16N && recon == 12)
+        return launch_dag<WL_F16N, WL_F16N, 12>(dagger, epi, tps, a, grid, blk, stream);
+    if (prec == WL_BF16N && recon == 12)
+        return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, epi, tps, a, grid, blk, stream);
     return hipErrorInvalidValue;
 }
 

@@ -90,6 +90,10 @@ _SIGS = {
     "wl_solver_params_default": (None, [ctypes.POINTER(SolverParams)]),
     "wl_cg_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                    ctypes.POINTER(SolverParams), ctypes.POINTER(SolverInfo), _vp]),
+    "wl_ctx_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_void_p]),
+    "wl_ctx_get_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_void_p]),
+    "wl_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "wl_timing_read": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _dp]),
     "wl_last_error": (ctypes.c_char_p, []),
     "wl_version": (ctypes.c_char_p, []),
 }
@@ -239,6 +243,37 @@ def wl_cg_solve(ctx, x, b, op, kappa, nrhs=1, params: SolverParams | None = None
     st = _check(lib().wl_cg_solve(ctx, _ptr(x), _ptr(b), op, float(kappa), nrhs, ctypes.byref(p), info,
                                   _stream(stream)))
     return st, [info[i].as_dict() for i in range(nrhs)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("swizzle", ctypes.c_int), ("tps", ctypes.c_int), ("tchunk", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.block, self.swizzle, self.tps, self.tchunk)
+
+
+def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=0):
+    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk))
+    return _check(lib().wl_ctx_set_launch(ctx, prec, ctypes.addressof(cfg)))
+
+
+def wl_ctx_get_launch(ctx, prec):
+    """-> (block, swizzle, tps, tchunk)"""
+    cfg = Launch()
+    _check(lib().wl_ctx_get_launch(ctx, prec, ctypes.addressof(cfg)))
+    return cfg.as_tuple()
+
+
+def wl_timing_enable(ctx, enable=True):
+    return _check(lib().wl_timing_enable(ctx, int(bool(enable))))
+
+
+def wl_timing_read(ctx, prec, recon, dagger, epilogue):
+    """-> (count, total_ms) of the recorded hopping-kernel launches of that variant."""
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(lib().wl_timing_read(ctx, prec, recon, int(bool(dagger)), epilogue, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def wl_version() -> str:

@@ -353,3 +353,55 @@ def test_cg_free_field_plane_wave_one_iteration():
     assert st == W.WL_OK and info[0]["iters"] == 1
     assert rel(lat.unpack(x).reshape(b.shape), b / lam) < 1e-13
     lat.close()
+
+
+# ------------------------------------------------------------------ launch configurations
+@pytest.mark.parametrize("prec", [W.WL_F64, W.WL_F32])
+@pytest.mark.parametrize("block,swizzle,tps,tchunk", [(64, 0, 1, 0), (256, 1, 2, 0), (128, 0, 2, 3),
+                                                      (192, 1, 1, 4), (64, 1, 2, 5), (256, 1, 1, 1)])
+def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk):
+    dims = (6, 10, 4, 14)
+    kappa = 0.13
+    ph = random_phases(77)
+    u, lat = setup(dims, seed=78, phases=ph)
+    saved = W.wl_ctx_get_launch(lat.ctx, prec)
+    W.wl_ctx_set_launch(lat.ctx, prec, block, swizzle, tps, tchunk)
+    try:
+        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk)
+        phi = synth.gaussian_spinor(dims, seed=79)
+        for dagger in (False, True):
+            want = orc.hop(phi, u, ph, dagger=dagger)
+            out = lat.new(W.WL_FULL, prec)
+            fn = W.wl_dslash_dagger_apply if dagger else W.wl_dslash_apply
+            fn(lat.ctx, out, lat.pack(phi, W.WL_FULL, prec), W.WL_FULL, prec, 18)
+            assert rel(lat.unpack(out, W.WL_FULL, prec).reshape(want.shape), want) < TOL[prec]
+        # fused epilogue (x + b H in) through the Schur operator
+        pe, _ = orc.eo_split(phi, dims)
+        want_e = orc.schur(pe, u, kappa, ph, dagger=True)
+        oe = lat.new(W.WL_EVEN, prec)
+        W.wl_dirac_apply(lat.ctx, oe, lat.pack(pe, W.WL_EVEN, prec), W.WL_OP_DHAT, True, kappa, prec, 18)
+        assert rel(lat.unpack(oe, W.WL_EVEN, prec), want_e) < TOL[prec]
+        if prec == W.WL_F64:
+            # CG uses the fused-norm epilogue: iterates still match the oracle
+            b = synth.gaussian_spinor(dims, seed=80)
+            m = lambda v: orc.dirac(v, u, kappa, ph)
+            md = lambda v: orc.dirac(v, u, kappa, ph, dagger=True)
+            x_orc, _ = orc.cg_normal(m, md, b, fixed_iters=15)
+            p = W.wl_solver_params_default()
+            p.tol, p.maxiter, p.max_restarts = 0.0, 15, 0
+            x = lat.new(W.WL_FULL)
+            W.wl_cg_solve(lat.ctx, x, lat.pack(b), W.WL_OP_D, kappa, params=p)
+            assert rel(lat.unpack(x).reshape(b.shape), x_orc) < 1e-13
+    finally:
+        W.wl_ctx_set_launch(lat.ctx, prec, *saved)
+
+
+def test_launch_config_rejects_bad_values():
+    _, lat = setup((4, 4, 4, 4))
+    for args in [(W.WL_F64, 32, 0, 1), (W.WL_F64, 320, 0, 1), (W.WL_F64, 256, 0, 3), (W.WL_F64, 256, 0, 1, -1)]:
+        with pytest.raises(W.WilsonError) as e:
+            W.wl_ctx_set_launch(lat.ctx, *args)
+        assert e.value.status == W.WL_ERR_ARG
+    with pytest.raises(W.WilsonError) as e:
+        W.wl_ctx_set_launch(lat.ctx, W.WL_F16N, 256, 0, 2)
+    assert e.value.status == W.WL_ERR_UNSUPPORTED

@@ -140,7 +140,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--cpu-iters", type=int, default=5, help="CG iterations of the CPU-oracle sample")
+    ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -218,7 +218,7 @@ def main():
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "hop_kernel<F64,F64,18,dagger=false,epilogue=0> (half-dslash H_oe)",
+                "kernel": "wl::hop_kernel_split<0, 0, 18, false, 0> (FP64 half-dslash H_oe, 18-real links)",
                 "launches": n_hop, "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": SITE_BYTES["hop"] * vh}
 

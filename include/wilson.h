@@ -113,7 +113,11 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *           (t slowest); k > 0 = the lattice is cut into chunks of k time
  *           slices and each chunk is walked with z slowest, so that the
  *           neighbours in t and z of a site are read close together in time
- * Results do not depend on block, swizzle or tchunk; tps changes the
+ *   nt      1: non-temporal hints on the link loads and output stores (they
+ *           keep the single-use link stream from evicting re-read spinors from
+ *           L2, but also bypass the Infinity Cache); 0: off; -1: on when the
+ *           launch's links and spinor fields exceed 200 MB
+ * Results do not depend on block, swizzle, tchunk or nt; tps changes the
  * summation order of the 8 hops (rounding only).  Defaults are chosen per
  * precision by measurement (see wl_ctx_get_launch). */
 typedef struct {
@@ -121,6 +125,7 @@ typedef struct {
     int swizzle;
     int tps;
     int tchunk;
+    int nt;
 } wl_launch;
 wl_status wl_ctx_set_launch(wl_ctx *ctx, wl_prec prec, const wl_launch *cfg);
 wl_status wl_ctx_get_launch(const wl_ctx *ctx, wl_prec prec, wl_launch *cfg);

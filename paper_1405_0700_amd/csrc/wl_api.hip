@@ -89,7 +89,7 @@ static bool recon_ok(int prec, int r) {
 }
 
 static size_t half_bytes(const wl_ctx *c, int prec, int nrhs) {
-    return spinor_point_bytes(prec) * (size_t)c->Vh * (size_t)nrhs;
+    return spinor_point_bytes(prec) * (size_t)padded(c->Vh * (long)nrhs);
 }
 
 static wl_status ensure_buf(wl_ctx *c, int slot, size_t bytes) {
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) k_pack(Geom g, void *dst, size_t half_byt
     cpx<T> v[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = {(T)s[2 * k], (T)s[2 * k + 1]};
-    SpinorIO<SP>::store((char *)dst + h * half_bytes, n, gid, v);
+    SpinorIO<SP>::store((char *)dst + h * half_bytes, gid, v);
 }
 
 template <int SP>
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_unpack(Geom g, double *dst, const void 
         nsite = g.vh;
     }
     cpx<T> v[12];
-    SpinorIO<SP>::load((const char *)src + h * half_bytes, n, gid, v);
+    SpinorIO<SP>::load((const char *)src + h * half_bytes, gid, v);
     double *d = dst + ((long)rhs * nsite + idx) * 24;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -188,11 +188,11 @@ __global__ void __launch_bounds__(256) k_link_convert(void *dst, size_t dslab, c
     const int slab = blockIdx.y;
     if (i >= vh) return;
     cpx<double> u[9];
-    LinkIO<WL_F64, 18>::load((const char *)src + slab * sslab, vh, i, u);
+    LinkIO<WL_F64, 18>::load((const char *)src + slab * sslab, i, u);
     cpx<T> w[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = {(T)u[k].re, (T)u[k].im};
-    LinkIO<GP, R>::store((char *)dst + slab * dslab, vh, i, w);
+    LinkIO<GP, R>::store((char *)dst + slab * dslab, i, w);
 }
 
 template <template <int> class K, typename... A>
@@ -269,7 +269,7 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
         if (!(phases[2 * m] == 1.0 && phases[2 * m + 1] == 0.0)) g.phase_mask |= 1 << m;
     }
     // host packing of the canonical FP64 gauge field into the FP64 18-real internal layout
-    const size_t slab = LinkIO<WL_F64, 18>::bytes_per_link * (size_t)c->Vh;
+    const size_t slab = LinkIO<WL_F64, 18>::bytes_per_link * (size_t)padded(c->Vh);
     std::vector<double> host(slab / sizeof(double) * 8);
     for (long lex = 0; lex < V; ++lex) {
         long r = lex;
@@ -284,7 +284,9 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
         for (int mu = 0; mu < 4; ++mu)
             for (int k = 0; k < 9; ++k) {
                 const double *src = gauge_host + ((lex * 4 + mu) * 9 + k) * 2;
-                double *dst = host.data() + (((size_t)(par * 4 + mu) * 9 + k) * c->Vh + i) * 2;
+                // slab (par, mu); block i / 64, unit k, lane i % 64 (double2 units)
+                double *dst = host.data() + (size_t)(par * 4 + mu) * (slab / sizeof(double)) +
+                              ((size_t)((i >> 6) * 9 + k) * 64 + (i & 63)) * 2;
                 dst[0] = src[0];
                 dst[1] = src[1];
             }
@@ -303,6 +305,11 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
         return fail(WL_ERR_HIP, "gauge upload failed: %s", hipGetErrorString(e));
     }
     c->gauge[WL_F64][0] = d;
+    // measured defaults (MI355X, 24^3x48 and 32^3x64 lattices)
+    c->cfg[WL_F64] = {128, 1, 2, 0, -1};
+    c->cfg[WL_F32] = {128, 1, 2, 0, -1};
+    c->cfg[WL_F16N] = {256, 1, 1, 0, -1};
+    c->cfg[WL_BF16N] = {256, 1, 1, 0, -1};
     c->slab[WL_F64][0] = slab;
     *out = c;
     return WL_OK;
@@ -326,7 +333,7 @@ static wl_status get_links(wl_ctx *c, int prec, int recon, const void **ptr, siz
     if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "link format prec %d / recon %d not supported", prec, recon);
     const int ri = recon == 12 ? 1 : 0;
     if (!c->gauge[prec][ri]) {
-        const size_t sl = link_bytes(prec, recon) * (size_t)c->Vh;
+        const size_t sl = link_bytes(prec, recon) * (size_t)padded(c->Vh);
         void *d = nullptr;
         hipError_t e = hipMalloc(&d, sl * 8);
         if (e != hipSuccess) {
@@ -1017,11 +1024,13 @@ extern "C" wl_status wl_ctx_set_launch(wl_ctx *c, wl_prec prec, const wl_launch 
     if (l->tps == 2 && prec != WL_F64 && prec != WL_F32)
         return fail(WL_ERR_UNSUPPORTED, "two threads per point needs FP64 or FP32 storage");
     if (l->tchunk < 0) return fail(WL_ERR_ARG, "tchunk %d < 0", l->tchunk);
+    if (l->nt < -1 || l->nt > 1) return fail(WL_ERR_ARG, "nt %d not in {-1, 0, 1}", l->nt);
     LaunchCfg &g = c->cfg[prec];
     g.block = l->block;
     g.swizzle = l->swizzle ? 1 : 0;
     g.tps = l->tps;
     g.tchunk = l->tchunk;
+    g.nt = l->nt;
     return WL_OK;
 }
 
@@ -1034,5 +1043,6 @@ extern "C" wl_status wl_ctx_get_launch(const wl_ctx *c, wl_prec prec, wl_launch 
     l->swizzle = g.swizzle;
     l->tps = g.tps;
     l->tchunk = g.tchunk;
+    l->nt = g.nt;
     return WL_OK;
 }

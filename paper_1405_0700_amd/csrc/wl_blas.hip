@@ -21,14 +21,14 @@ __global__ void __launch_bounds__(256) k_axpby(const VecArgs a) {
     double nrm = 0.0;
     if (gid < a.n) {
         cpx<T> x[12], y[12];
-        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
-        SpinorIO<SP>::load(a.v[1][h], a.n, gid, y);
+        SpinorIO<SP>::load(a.v[0][h], gid, x);
+        SpinorIO<SP>::load(a.v[1][h], gid, y);
         const T aa = (T)a.a, bb = (T)a.b;
 #pragma unroll
         for (int k = 0; k < 12; ++k) y[k] = {fma(aa, x[k].re, bb * y[k].re), fma(aa, x[k].im, bb * y[k].im)};
-        SpinorIO<SP>::store(a.v[1][h], a.n, gid, y);
+        SpinorIO<SP>::store(a.v[1][h], gid, y);
         if constexpr (NORM) {
-            if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[1][h], a.n, gid, y);
+            if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[1][h], gid, y);
 #pragma unroll
             for (int k = 0; k < 12; ++k) nrm += (double)y[k].re * y[k].re + (double)y[k].im * y[k].im;
         }
@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(256) k_dot(const VecArgs a) {
     double re = 0.0, im = 0.0;
     if (gid < a.n) {
         cpx<T> x[12], y[12];
-        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
-        SpinorIO<SP>::load(a.v[1][h], a.n, gid, y);
+        SpinorIO<SP>::load(a.v[0][h], gid, x);
+        SpinorIO<SP>::load(a.v[1][h], gid, y);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             re += (double)x[k].re * y[k].re + (double)x[k].im * y[k].im;
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) k_norm2(const VecArgs a) {
     double nrm = 0.0;
     if (gid < a.n) {
         cpx<T> x[12];
-        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
+        SpinorIO<SP>::load(a.v[0][h], gid, x);
 #pragma unroll
         for (int k = 0; k < 12; ++k) nrm += (double)x[k].re * x[k].re + (double)x[k].im * x[k].im;
     }
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(256) k_zero(const VecArgs a) {
         cpx<T> z[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) z[k] = {T(0), T(0)};
-        SpinorIO<SP>::store(a.v[0][blockIdx.y], a.n, gid, z);
+        SpinorIO<SP>::store(a.v[0][blockIdx.y], gid, z);
     }
 }
 
@@ -109,19 +109,19 @@ __global__ void __launch_bounds__(256) k_cg_xr(const VecArgs a) {
             const double alpha = sc.alpha;
             cpx<T> p[12], r[12], s[12];
             cpx<double> x[12];
-            SpinorIO<SP>::load(a.v[1][h], a.n, gid, p);
-            SpinorIO<WL_F64>::load(a.v[0][h], a.n, gid, x);
+            SpinorIO<SP>::load(a.v[1][h], gid, p);
+            SpinorIO<WL_F64>::load(a.v[0][h], gid, x);
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 x[k] = {fma(alpha, (double)p[k].re, x[k].re), fma(alpha, (double)p[k].im, x[k].im)};
-            SpinorIO<WL_F64>::store(a.v[0][h], a.n, gid, x);
-            SpinorIO<SP>::load(a.v[2][h], a.n, gid, r);
-            SpinorIO<SP>::load(a.v[3][h], a.n, gid, s);
+            SpinorIO<WL_F64>::store(a.v[0][h], gid, x);
+            SpinorIO<SP>::load(a.v[2][h], gid, r);
+            SpinorIO<SP>::load(a.v[3][h], gid, s);
             const T al = (T)alpha;
 #pragma unroll
             for (int k = 0; k < 12; ++k) r[k] = {fma(-al, s[k].re, r[k].re), fma(-al, s[k].im, r[k].im)};
-            SpinorIO<SP>::store(a.v[2][h], a.n, gid, r);
-            if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[2][h], a.n, gid, r);
+            SpinorIO<SP>::store(a.v[2][h], gid, r);
+            if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[2][h], gid, r);
 #pragma unroll
             for (int k = 0; k < 12; ++k) nrm += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
         }
@@ -143,11 +143,11 @@ __global__ void __launch_bounds__(256) k_cg_p(const VecArgs a) {
         if (!a.sc[rhs].active) return;
         const T beta = (T)a.sc[rhs].beta;
         cpx<T> r[12], p[12];
-        SpinorIO<SP>::load(a.v[0][h], a.n, gid, r);
-        SpinorIO<SP>::load(a.v[1][h], a.n, gid, p);
+        SpinorIO<SP>::load(a.v[0][h], gid, r);
+        SpinorIO<SP>::load(a.v[1][h], gid, p);
 #pragma unroll
         for (int k = 0; k < 12; ++k) p[k] = {fma(beta, p[k].re, r[k].re), fma(beta, p[k].im, r[k].im)};
-        SpinorIO<SP>::store(a.v[1][h], a.n, gid, p);
+        SpinorIO<SP>::store(a.v[1][h], gid, p);
     }
 }
 
@@ -161,16 +161,16 @@ __global__ void __launch_bounds__(256) k_convert(const VecArgs a) {
     if (gid < a.n) {
         cpx<TS> x[12];
         cpx<TD> y[12];
-        SpinorIO<SP>::load(a.v[0][h], a.n, gid, x);
+        SpinorIO<SP>::load(a.v[0][h], gid, x);
         if constexpr (ACC) {
-            SpinorIO<DP>::load(a.v[1][h], a.n, gid, y);
+            SpinorIO<DP>::load(a.v[1][h], gid, y);
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = {y[k].re + (TD)x[k].re, y[k].im + (TD)x[k].im};
         } else {
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = {(TD)x[k].re, (TD)x[k].im};
         }
-        SpinorIO<DP>::store(a.v[1][h], a.n, gid, y);
+        SpinorIO<DP>::store(a.v[1][h], gid, y);
     }
 }
 
@@ -184,12 +184,12 @@ __global__ void __launch_bounds__(256) k_residual(const VecArgs a) {
     double nrm = 0.0;
     if (gid < a.n) {
         cpx<T> b[12], v[12];
-        SpinorIO<SP>::load(a.v[0][h], a.n, gid, b);
-        SpinorIO<SP>::load(a.v[1][h], a.n, gid, v);
+        SpinorIO<SP>::load(a.v[0][h], gid, b);
+        SpinorIO<SP>::load(a.v[1][h], gid, v);
 #pragma unroll
         for (int k = 0; k < 12; ++k) v[k] = b[k] - v[k];
-        SpinorIO<SP>::store(a.v[2][h], a.n, gid, v);
-        if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[2][h], a.n, gid, v);
+        SpinorIO<SP>::store(a.v[2][h], gid, v);
+        if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.v[2][h], gid, v);
 #pragma unroll
         for (int k = 0; k < 12; ++k) nrm += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
     }

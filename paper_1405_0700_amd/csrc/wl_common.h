@@ -69,91 +69,124 @@ template <> struct Half16<WL_BF16N> {
 
 // ------------------------------------------------------------------ spinor storage
 // An internal field of one parity holds n = Vh * nrhs "points" (site, rhs),
-// rhs fastest.  The 12 complex components c = 3 * spin + colour are stored as
-// structure-of-arrays with the point index fastest, in 16-byte units:
-//   F64  : 12 arrays of double2                        (192 B / point)
-//   F32  :  6 arrays of float4 (components 2k, 2k+1)   ( 96 B / point)
-//   F16N / BF16N: 3 arrays of 8 x 16-bit (components 4k .. 4k+3), then one
-//          array of float norms                         ( 52 B / point)
+// rhs fastest.  Points are grouped in blocks of 64 (a wavefront); a block
+// stores its points' components as structure-of-arrays of 16-byte units, and
+// blocks follow each other, so the loads of one wavefront touch one
+// contiguous stretch of memory:
+//   F64  : 12 units of double2 (component c)                      192 B / point
+//   F32  :  6 units of float4 (components 2k, 2k+1)               96 B / point
+//   F16N / BF16N: 3 units of 8 x 16-bit (components 4k .. 4k+3), then the
+//          64 float norms of the block                            52 B / point
+// Unit k of point i lives at unit index ((i / 64) * NU + k) * 64 + i % 64.
+// A field of one parity occupies ceil(n / 64) blocks.
+constexpr int BLK = 64;
+
+// Loads of single-use data (the links of an operator application) and stores
+// of outputs can carry the non-temporal hint (NT = true), so that they do not
+// push the re-read neighbour spinors out of L2.  The hint also keeps them out
+// of the Infinity Cache, so it only pays once the working set exceeds it.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+template <bool NT, typename V> __device__ __forceinline__ V ld_link(const void *p) {
+    if constexpr (NT) return __builtin_nontemporal_load((const V *)p);
+    else return *(const V *)p;
+}
+template <bool NT, typename V> __device__ __forceinline__ void st_out(void *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, (V *)p);
+    else *(V *)p = v;
+}
+__device__ __forceinline__ long blk_unit(long i, int nu, int k) { return ((i >> 6) * nu + k) * BLK + (i & 63); }
+
 template <int P> struct SpinorIO;
 
 template <> struct SpinorIO<WL_F64> {
     using real = double;
     static constexpr size_t bytes_per_point = 192;
-    __device__ static void load(const void *base, long n, long i, cpx<double> v[12]) {
-        const double2 *p = (const double2 *)base;
+    __device__ static void load(const void *base, long i, cpx<double> v[12]) {
+        const double2 *p = (const double2 *)base + blk_unit(i, 12, 0);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            double2 d = p[c * n + i];
+            double2 d = p[c * BLK];
             v[c] = {d.x, d.y};
         }
     }
-    __device__ static void store(void *base, long n, long i, const cpx<double> v[12]) {
-        double2 *p = (double2 *)base;
+    template <bool NT = false> __device__ static void store(void *base, long i, const cpx<double> v[12]) {
+        double2 *p = (double2 *)base + blk_unit(i, 12, 0);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) p[c * n + i] = make_double2(v[c].re, v[c].im);
+        for (int c = 0; c < 12; ++c) st_out<NT, v2d>(p + c * BLK, v2d{v[c].re, v[c].im});
     }
     // components 6 hf .. 6 hf + 5 (spins 2 hf, 2 hf + 1)
-    __device__ static void load_half(const void *base, long n, long i, int hf, cpx<double> v[6]) {
-        const double2 *p = (const double2 *)base + (long)(6 * hf) * n;
+    __device__ static void load_half(const void *base, long i, int hf, cpx<double> v[6]) {
+        const double2 *p = (const double2 *)base + blk_unit(i, 12, 6 * hf);
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            double2 d = p[c * n + i];
+            double2 d = p[c * BLK];
             v[c] = {d.x, d.y};
         }
     }
-    __device__ static void store_half(void *base, long n, long i, int hf, const cpx<double> v[6]) {
-        double2 *p = (double2 *)base + (long)(6 * hf) * n;
+    template <bool NT = false> __device__ static void store_half(void *base, long i, int hf, const cpx<double> v[6]) {
+        double2 *p = (double2 *)base + blk_unit(i, 12, 6 * hf);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) p[c * n + i] = make_double2(v[c].re, v[c].im);
+        for (int c = 0; c < 6; ++c) st_out<NT, v2d>(p + c * BLK, v2d{v[c].re, v[c].im});
     }
 };
 
 template <> struct SpinorIO<WL_F32> {
     using real = float;
     static constexpr size_t bytes_per_point = 96;
-    __device__ static void load(const void *base, long n, long i, cpx<float> v[12]) {
-        const float4 *p = (const float4 *)base;
+    __device__ static void load(const void *base, long i, cpx<float> v[12]) {
+        const float4 *p = (const float4 *)base + blk_unit(i, 6, 0);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            float4 d = p[k * n + i];
+            float4 d = p[k * BLK];
             v[2 * k] = {d.x, d.y};
             v[2 * k + 1] = {d.z, d.w};
         }
     }
-    __device__ static void store(void *base, long n, long i, const cpx<float> v[12]) {
-        float4 *p = (float4 *)base;
+    template <bool NT = false> __device__ static void store(void *base, long i, const cpx<float> v[12]) {
+        float4 *p = (float4 *)base + blk_unit(i, 6, 0);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            p[k * n + i] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+            st_out<NT, v4f>(p + k * BLK, v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im});
     }
-    // components 6 hf .. 6 hf + 5 (spins 2 hf, 2 hf + 1)
-    __device__ static void load_half(const void *base, long n, long i, int hf, cpx<float> v[6]) {
-        const float4 *p = (const float4 *)base + (long)(3 * hf) * n;
+    __device__ static void load_half(const void *base, long i, int hf, cpx<float> v[6]) {
+        const float4 *p = (const float4 *)base + blk_unit(i, 6, 3 * hf);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            float4 d = p[k * n + i];
+            float4 d = p[k * BLK];
             v[2 * k] = {d.x, d.y};
             v[2 * k + 1] = {d.z, d.w};
         }
     }
-    __device__ static void store_half(void *base, long n, long i, int hf, const cpx<float> v[6]) {
-        float4 *p = (float4 *)base + (long)(3 * hf) * n;
+    template <bool NT = false> __device__ static void store_half(void *base, long i, int hf, const cpx<float> v[6]) {
+        float4 *p = (float4 *)base + blk_unit(i, 6, 3 * hf);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            p[k * n + i] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+            st_out<NT, v4f>(p + k * BLK, v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im});
     }
 };
 
+// 16-bit storage with a per-point FP32 norm; a block is 3 * 64 uint4 followed
+// by 64 floats (3328 bytes).
 template <int P> struct SpinorIO16 {
     using real = float;
     static constexpr size_t bytes_per_point = 52;
-    __device__ static void load(const void *base, long n, long i, cpx<float> v[12]) {
-        const uint4 *p = (const uint4 *)base;
-        const float s = ((const float *)(p + 3 * n))[i];
+    static constexpr long block_bytes = 52 * BLK;
+    __device__ static const uint4 *units(const void *base, long i) {
+        return (const uint4 *)((const char *)base + (i >> 6) * block_bytes) + (i & 63);
+    }
+    __device__ static float *norm_ptr(const void *base, long i) {
+        return (float *)((char *)base + (i >> 6) * block_bytes + 48 * BLK) + (i & 63);
+    }
+    __device__ static void load(const void *base, long i, cpx<float> v[12]) {
+        const uint4 *p = units(base, i);
+        const float s = *norm_ptr(base, i);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            uint4 d = p[k * n + i];
+            uint4 d = p[k * BLK];
             uint32_t w[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -161,8 +194,8 @@ template <int P> struct SpinorIO16 {
                                 s * Half16<P>::dec((uint16_t)(w[j] >> 16))};
         }
     }
-    __device__ static void store(void *base, long n, long i, const cpx<float> v[12]) {
-        uint4 *p = (uint4 *)base;
+    template <bool NT = false> __device__ static void store(void *base, long i, const cpx<float> v[12]) {
+        uint4 *p = (uint4 *)units(base, i);
         float s = 0.f;
 #pragma unroll
         for (int c = 0; c < 12; ++c) s = fmaxf(s, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
@@ -174,21 +207,22 @@ template <int P> struct SpinorIO16 {
             for (int j = 0; j < 4; ++j)
                 w[j] = (uint32_t)Half16<P>::enc(v[4 * k + j].re * inv) |
                        ((uint32_t)Half16<P>::enc(v[4 * k + j].im * inv) << 16);
-            p[k * n + i] = make_uint4(w[0], w[1], w[2], w[3]);
+            st_out<NT, v4u>(p + k * BLK, v4u{w[0], w[1], w[2], w[3]});
         }
-        ((float *)(p + 3 * n))[i] = s;
+        st_out<NT, float>(norm_ptr(base, i), s);
     }
 };
 template <> struct SpinorIO<WL_F16N> : SpinorIO16<WL_F16N> {};
 template <> struct SpinorIO<WL_BF16N> : SpinorIO16<WL_BF16N> {};
 
 // ------------------------------------------------------------------ link storage
-// Links of one (parity, mu) slab: Vh links, structure of arrays, site fastest.
-//   F64 18: 9 double2 (row-major entries)           144 B
-//   F64 12: 6 double2 (rows 0 and 1)                 96 B
-//   F32 18: 4 float4 (entries 0..7) + 1 float2 (8)   72 B
-//   F32 12: 3 float4 (entries 0..5)                  48 B
-//   16-bit 12: 1 x 8 halves (entries 0..3) + 1 x 4 halves (entries 4, 5)   24 B
+// Links of one (parity, mu) slab: Vh links in blocks of 64 sites, each block
+// structure-of-arrays of 16-byte (or 8-byte) units, like the spinors:
+//   F64 18: 9 double2 (row-major entries)                     144 B
+//   F64 12: 6 double2 (rows 0 and 1)                           96 B
+//   F32 18: 4 float4 (entries 0..7), then 1 float2 (entry 8)   72 B
+//   F32 12: 3 float4 (entries 0..5)                            48 B
+//   16-bit 12: 1 x 8 halves (entries 0..3), then 1 x 4 halves (4, 5)   24 B
 // For 12-real storage the third row is rebuilt as conj(row0 x row1) (valid for
 // SU(3)); boundary phases are applied afterwards, outside the link.
 template <int P, int R> struct LinkIO;
@@ -200,110 +234,102 @@ template <typename T> __device__ __forceinline__ void recon_row2(cpx<T> u[9]) {
     u[8] = conjg(cmul(u[0], u[4]) - cmul(u[1], u[3]));
 }
 
-template <> struct LinkIO<WL_F64, 18> {
+template <int NU> struct LinkIOF64 {
     using real = double;
-    static constexpr size_t bytes_per_link = 144;
-    __device__ static void load(const void *base, long vh, long i, cpx<double> u[9]) {
-        const double2 *p = (const double2 *)base;
+    static constexpr size_t bytes_per_link = 16 * NU;
+    template <bool NT = false> __device__ static void load(const void *base, long i, cpx<double> u[9]) {
+        const double2 *p = (const double2 *)base + blk_unit(i, NU, 0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            double2 d = p[k * vh + i];
+        for (int k = 0; k < NU; ++k) {
+            v2d d = ld_link<NT, v2d>(p + k * BLK);
             u[k] = {d.x, d.y};
         }
+        if constexpr (NU == 6) recon_row2(u);
     }
-    __device__ static void store(void *base, long vh, long i, const cpx<double> u[9]) {
-        double2 *p = (double2 *)base;
+    __device__ static void store(void *base, long i, const cpx<double> u[9]) {
+        double2 *p = (double2 *)base + blk_unit(i, NU, 0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) p[k * vh + i] = make_double2(u[k].re, u[k].im);
+        for (int k = 0; k < NU; ++k) p[k * BLK] = make_double2(u[k].re, u[k].im);
     }
 };
-template <> struct LinkIO<WL_F64, 12> {
-    using real = double;
-    static constexpr size_t bytes_per_link = 96;
-    __device__ static void load(const void *base, long vh, long i, cpx<double> u[9]) {
-        const double2 *p = (const double2 *)base;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            double2 d = p[k * vh + i];
-            u[k] = {d.x, d.y};
-        }
-        recon_row2(u);
-    }
-    __device__ static void store(void *base, long vh, long i, const cpx<double> u[9]) {
-        double2 *p = (double2 *)base;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) p[k * vh + i] = make_double2(u[k].re, u[k].im);
-    }
-};
+template <> struct LinkIO<WL_F64, 18> : LinkIOF64<9> {};
+template <> struct LinkIO<WL_F64, 12> : LinkIOF64<6> {};
+
 template <> struct LinkIO<WL_F32, 18> {
     using real = float;
     static constexpr size_t bytes_per_link = 72;
-    __device__ static void load(const void *base, long vh, long i, cpx<float> u[9]) {
-        const float4 *p = (const float4 *)base;
+    // block: 4 * 64 float4, then 64 float2
+    template <bool NT = false> __device__ static void load(const void *base, long i, cpx<float> u[9]) {
+        const char *b = (const char *)base + (i >> 6) * (72 * BLK);
+        const float4 *p = (const float4 *)b + (i & 63);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            float4 d = p[k * vh + i];
+            v4f d = ld_link<NT, v4f>(p + k * BLK);
             u[2 * k] = {d.x, d.y};
             u[2 * k + 1] = {d.z, d.w};
         }
-        float2 e = ((const float2 *)(p + 4 * vh))[i];
+        v2f e = ld_link<NT, v2f>((const float2 *)(b + 64 * BLK) + (i & 63));
         u[8] = {e.x, e.y};
     }
-    __device__ static void store(void *base, long vh, long i, const cpx<float> u[9]) {
-        float4 *p = (float4 *)base;
+    __device__ static void store(void *base, long i, const cpx<float> u[9]) {
+        char *b = (char *)base + (i >> 6) * (72 * BLK);
+        float4 *p = (float4 *)b + (i & 63);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            p[k * vh + i] = make_float4(u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im);
-        ((float2 *)(p + 4 * vh))[i] = make_float2(u[8].re, u[8].im);
+            p[k * BLK] = make_float4(u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im);
+        ((float2 *)(b + 64 * BLK))[i & 63] = make_float2(u[8].re, u[8].im);
     }
 };
 template <> struct LinkIO<WL_F32, 12> {
     using real = float;
     static constexpr size_t bytes_per_link = 48;
-    __device__ static void load(const void *base, long vh, long i, cpx<float> u[9]) {
-        const float4 *p = (const float4 *)base;
+    template <bool NT = false> __device__ static void load(const void *base, long i, cpx<float> u[9]) {
+        const float4 *p = (const float4 *)base + blk_unit(i, 3, 0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            float4 d = p[k * vh + i];
+            v4f d = ld_link<NT, v4f>(p + k * BLK);
             u[2 * k] = {d.x, d.y};
             u[2 * k + 1] = {d.z, d.w};
         }
         recon_row2(u);
     }
-    __device__ static void store(void *base, long vh, long i, const cpx<float> u[9]) {
-        float4 *p = (float4 *)base;
+    __device__ static void store(void *base, long i, const cpx<float> u[9]) {
+        float4 *p = (float4 *)base + blk_unit(i, 3, 0);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            p[k * vh + i] = make_float4(u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im);
+            p[k * BLK] = make_float4(u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im);
     }
 };
 template <int P> struct LinkIO16 {
     using real = float;
     static constexpr size_t bytes_per_link = 24;
-    __device__ static void load(const void *base, long vh, long i, cpx<float> u[9]) {
-        const uint4 *p = (const uint4 *)base;
-        uint4 a = p[i];
-        uint2 b = ((const uint2 *)(p + vh))[i];
-        uint32_t w[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+    // block: 64 uint4, then 64 uint2
+    template <bool NT = false> __device__ static void load(const void *base, long i, cpx<float> u[9]) {
+        const char *b = (const char *)base + (i >> 6) * (24 * BLK);
+        v4u a = ld_link<NT, v4u>((const uint4 *)b + (i & 63));
+        v2u c = ld_link<NT, v2u>((const uint2 *)(b + 16 * BLK) + (i & 63));
+        uint32_t w[6] = {a.x, a.y, a.z, a.w, c.x, c.y};
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             u[k] = {Half16<P>::dec((uint16_t)(w[k] & 0xffffu)), Half16<P>::dec((uint16_t)(w[k] >> 16))};
         recon_row2(u);
     }
-    __device__ static void store(void *base, long vh, long i, const cpx<float> u[9]) {
+    __device__ static void store(void *base, long i, const cpx<float> u[9]) {
         uint32_t w[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             w[k] = (uint32_t)Half16<P>::enc(u[k].re) | ((uint32_t)Half16<P>::enc(u[k].im) << 16);
-        uint4 *p = (uint4 *)base;
-        p[i] = make_uint4(w[0], w[1], w[2], w[3]);
-        ((uint2 *)(p + vh))[i] = make_uint2(w[4], w[5]);
+        char *b = (char *)base + (i >> 6) * (24 * BLK);
+        ((uint4 *)b)[i & 63] = make_uint4(w[0], w[1], w[2], w[3]);
+        ((uint2 *)(b + 16 * BLK))[i & 63] = make_uint2(w[4], w[5]);
     }
 };
 template <> struct LinkIO<WL_F16N, 12> : LinkIO16<WL_F16N> {};
 template <> struct LinkIO<WL_BF16N, 12> : LinkIO16<WL_BF16N> {};
 
-// host-side sizes
+// host-side sizes: a field of n points (or a slab of n links) occupies
+// ceil(n / 64) blocks
+inline long padded(long n) { return (n + 63) / 64 * 64; }
 inline size_t spinor_point_bytes(int prec) {
     switch (prec) {
     case WL_F64: return 192;

@@ -33,7 +33,12 @@ struct LaunchCfg {
                        // the two halves of a wavefront; FP64 and FP32 storage only)
     int tchunk = 0;    // processing order: 0 = e/o index order; k = chunks of k time
                        // slices, each walked with z slowest
+    int nt = -1;       // non-temporal link loads / output stores: 1 on, 0 off,
+                       // -1 on when the launch's working set exceeds 200 MB
 };
+
+// whether a launch uses the non-temporal hints
+bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int nparity, int epi);
 
 // Enqueue out = a x + b H in (H^+ if dagger) over `nparity` output parities.
 // Returns hipSuccess or the launch error.

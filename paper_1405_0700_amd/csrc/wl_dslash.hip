@@ -17,10 +17,6 @@
 // on one contiguous range of sites and the neighbour re-reads hit its L2.
 #include "wl_dslash.h"
 
-// minimum waves per SIMD requested for the split kernel (1: no register cap)
-#ifndef WL_SPLIT_MINW
-#define WL_SPLIT_MINW 1
-#endif
 
 namespace wl {
 
@@ -104,7 +100,7 @@ __device__ __forceinline__ void su3_mul2(const cpx<T> u[9], const cpx<T> h[6], c
         }
 }
 
-template <int SP, int GP, int RECON, bool DAG, int MU, bool FWD>
+template <int SP, int GP, int RECON, bool DAG, bool NT, int MU, bool FWD>
 __device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs,
                                     cpx<typename SpinorIO<SP>::real> acc[12]) {
     using T = typename SpinorIO<SP>::real;
@@ -125,10 +121,10 @@ __device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, co
     // Forward hop (H): (1 - gamma) -> S = -1; backward: (1 + gamma) -> S = +1; H^+ swaps them.
     constexpr int S = (FWD != DAG) ? -1 : 1;
     cpx<T> f[12], h[6], u[9], v[6];
-    SpinorIO<SP>::load(a.in[1 - par], a.npts, (long)j * a.nrhs + rhs, f);
+    SpinorIO<SP>::load(a.in[1 - par], (long)j * a.nrhs + rhs, f);
     const int lpar = FWD ? par : 1 - par;
     const char *slab = (const char *)a.gauge + (size_t)(lpar * 4 + MU) * a.slab_bytes;
-    LinkIO<GP, RECON>::load(slab, g.vh, FWD ? i : j, u);
+    LinkIO<GP, RECON>::template load<NT>(slab, FWD ? i : j, u);
     project<T, MU, S>(f, h);
     su3_mul2<T, FWD>(u, h, v);
     if (wrap && ((g.phase_mask >> MU) & 1)) {
@@ -196,7 +192,7 @@ __device__ __forceinline__ void accumulate_rt(cpx<T> acc[12], const cpx<T> v[6],
     }
 }
 
-template <int SP, int GP, int RECON, bool DAG, int MU>
+template <int SP, int GP, int RECON, bool DAG, bool NT, int MU>
 __device__ __forceinline__ void hop_rt(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs, bool fwd,
                                        cpx<typename SpinorIO<SP>::real> acc[12]) {
     using T = typename SpinorIO<SP>::real;
@@ -216,10 +212,10 @@ __device__ __forceinline__ void hop_rt(const HopArgs &a, int par, int i, int xh,
     }
     const T s = (fwd != DAG) ? T(-1) : T(1);
     cpx<T> f[12], h[6], u[9], w[9], v[6];
-    SpinorIO<SP>::load(a.in[1 - par], a.npts, (long)j * a.nrhs + rhs, f);
+    SpinorIO<SP>::load(a.in[1 - par], (long)j * a.nrhs + rhs, f);
     const int lpar = fwd ? par : 1 - par;
     const char *slab = (const char *)a.gauge + (size_t)(lpar * 4 + MU) * a.slab_bytes;
-    LinkIO<GP, RECON>::load(slab, g.vh, fwd ? i : j, u);
+    LinkIO<GP, RECON>::template load<NT>(slab, fwd ? i : j, u);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -258,7 +254,7 @@ __device__ __forceinline__ long logical_block(int swizzle) {
 }
 
 // One thread per output point.
-template <int SP, int GP, int RECON, bool DAG, int EPI>
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     using T = typename SpinorIO<SP>::real;
     if (a.flag && *a.flag) return;
@@ -279,18 +275,18 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         cpx<T> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
-        hop<SP, GP, RECON, DAG, 0, true>(a, par, i, xh, c, rhs, acc);
-        hop<SP, GP, RECON, DAG, 0, false>(a, par, i, xh, c, rhs, acc);
-        hop<SP, GP, RECON, DAG, 1, true>(a, par, i, xh, c, rhs, acc);
-        hop<SP, GP, RECON, DAG, 1, false>(a, par, i, xh, c, rhs, acc);
-        hop<SP, GP, RECON, DAG, 2, true>(a, par, i, xh, c, rhs, acc);
-        hop<SP, GP, RECON, DAG, 2, false>(a, par, i, xh, c, rhs, acc);
-        hop<SP, GP, RECON, DAG, 3, true>(a, par, i, xh, c, rhs, acc);
-        hop<SP, GP, RECON, DAG, 3, false>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 0, true>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 0, false>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 1, true>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 1, false>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 2, true>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 2, false>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 3, true>(a, par, i, xh, c, rhs, acc);
+        hop<SP, GP, RECON, DAG, NT, 3, false>(a, par, i, xh, c, rhs, acc);
         const T b = (T)a.b;
         if constexpr (EPI & EPI_XPAY) {
             cpx<T> xv[12];
-            SpinorIO<SP>::load(a.x[par], a.npts, pt, xv);
+            SpinorIO<SP>::load(a.x[par], pt, xv);
             const T aa = (T)a.a;
 #pragma unroll
             for (int k = 0; k < 12; ++k)
@@ -299,7 +295,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = b * acc[k];
         }
-        SpinorIO<SP>::store(a.out[par], a.npts, pt, acc);
+        SpinorIO<SP>::template store<NT>(a.out[par], pt, acc);
         if constexpr (EPI & EPI_NORM) {
             if constexpr (SP == WL_F64) {
 #pragma unroll
@@ -307,7 +303,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
             } else {
                 // the norm of what was stored (after rounding to the storage format)
                 cpx<T> st[12];
-                SpinorIO<SP>::load(a.out[par], a.npts, pt, st);
+                SpinorIO<SP>::load(a.out[par], pt, st);
 #pragma unroll
                 for (int k = 0; k < 12; ++k)
                     nrm += (double)st[k].re * st[k].re + (double)st[k].im * st[k].im;
@@ -325,8 +321,8 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 // hops of 32 consecutive points, lanes 32-63 the backward hops of the same
 // points; the partial sums are exchanged across the halves and each half
 // finishes and stores two of the four spin components.
-template <int SP, int GP, int RECON, bool DAG, int EPI>
-__global__ void __launch_bounds__(256, WL_SPLIT_MINW) hop_kernel_split(const HopArgs a) {
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
     using T = typename SpinorIO<SP>::real;
     if (a.flag && *a.flag) return;
     const int par = a.out_par0 + blockIdx.y;
@@ -348,10 +344,10 @@ __global__ void __launch_bounds__(256, WL_SPLIT_MINW) hop_kernel_split(const Hop
         int c[4];
         eo_coords(a.g, i, par, c);
         const int xh = c[0] >> 1;
-        hop_rt<SP, GP, RECON, DAG, 0>(a, par, i, xh, c, rhs, fwd, acc);
-        hop_rt<SP, GP, RECON, DAG, 1>(a, par, i, xh, c, rhs, fwd, acc);
-        hop_rt<SP, GP, RECON, DAG, 2>(a, par, i, xh, c, rhs, fwd, acc);
-        hop_rt<SP, GP, RECON, DAG, 3>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, NT, 0>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, NT, 1>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, NT, 2>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, NT, 3>(a, par, i, xh, c, rhs, fwd, acc);
     }
     // every lane takes part in the exchange
     cpx<T> res[6];
@@ -367,7 +363,7 @@ __global__ void __launch_bounds__(256, WL_SPLIT_MINW) hop_kernel_split(const Hop
         const T b = (T)a.b;
         if constexpr (EPI & EPI_XPAY) {
             cpx<T> xv[6];
-            SpinorIO<SP>::load_half(a.x[par], a.npts, pt, hf, xv);
+            SpinorIO<SP>::load_half(a.x[par], pt, hf, xv);
             const T aa = (T)a.a;
 #pragma unroll
             for (int k = 0; k < 6; ++k)
@@ -376,9 +372,9 @@ __global__ void __launch_bounds__(256, WL_SPLIT_MINW) hop_kernel_split(const Hop
 #pragma unroll
             for (int k = 0; k < 6; ++k) res[k] = b * res[k];
         }
-        SpinorIO<SP>::store_half(a.out[par], a.npts, pt, hf, res);
+        SpinorIO<SP>::template store_half<NT>(a.out[par], pt, hf, res);
         if constexpr (EPI & EPI_NORM) {
-            if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(a.out[par], a.npts, pt, hf, res);
+            if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(a.out[par], pt, hf, res);
 #pragma unroll
             for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
         }
@@ -391,33 +387,44 @@ __global__ void __launch_bounds__(256, WL_SPLIT_MINW) hop_kernel_split(const Hop
     }
 }
 
-template <int SP, int GP, int RECON, bool DAG, int EPI>
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 static void launch_one(int tps, dim3 grid, dim3 block, hipStream_t s, const HopArgs &a) {
     if constexpr (SP == WL_F64 || SP == WL_F32) {
         if (tps == 2) {
-            hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>), grid, block, 0, s, a);
             return;
         }
     }
-    hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI, NT>), grid, block, 0, s, a);
 }
 
-template <int SP, int GP, int RECON, bool DAG>
+template <int SP, int GP, int RECON, bool DAG, bool NT>
 static hipError_t launch_epi(int epi, int tps, HopArgs &a, dim3 grid, dim3 block, hipStream_t s) {
     switch (epi) {
-    case 0: launch_one<SP, GP, RECON, DAG, 0>(tps, grid, block, s, a); break;
-    case EPI_XPAY: launch_one<SP, GP, RECON, DAG, EPI_XPAY>(tps, grid, block, s, a); break;
-    case EPI_NORM: launch_one<SP, GP, RECON, DAG, EPI_NORM>(tps, grid, block, s, a); break;
-    case EPI_XPAY | EPI_NORM: launch_one<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM>(tps, grid, block, s, a); break;
+    case 0: launch_one<SP, GP, RECON, DAG, 0, NT>(tps, grid, block, s, a); break;
+    case EPI_XPAY: launch_one<SP, GP, RECON, DAG, EPI_XPAY, NT>(tps, grid, block, s, a); break;
+    case EPI_NORM: launch_one<SP, GP, RECON, DAG, EPI_NORM, NT>(tps, grid, block, s, a); break;
+    case EPI_XPAY | EPI_NORM: launch_one<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM, NT>(tps, grid, block, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <int SP, int GP, int RECON>
-static hipError_t launch_dag(bool dag, int epi, int tps, HopArgs &a, dim3 grid, dim3 block, hipStream_t s) {
-    return dag ? launch_epi<SP, GP, RECON, true>(epi, tps, a, grid, block, s)
-               : launch_epi<SP, GP, RECON, false>(epi, tps, a, grid, block, s);
+static hipError_t launch_dag(bool dag, bool nt, int epi, int tps, HopArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+    if (nt)
+        return dag ? launch_epi<SP, GP, RECON, true, true>(epi, tps, a, grid, block, s)
+                   : launch_epi<SP, GP, RECON, false, true>(epi, tps, a, grid, block, s);
+    return dag ? launch_epi<SP, GP, RECON, true, false>(epi, tps, a, grid, block, s)
+               : launch_epi<SP, GP, RECON, false, false>(epi, tps, a, grid, block, s);
+}
+
+bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int nparity, int epi) {
+    if (cfg.nt >= 0) return cfg.nt != 0;
+    // links read by one launch (8 slabs) + input, output and epilogue fields
+    const double pts = (double)padded(a.npts) * nparity;
+    const double ws = 8.0 * (double)a.slab_bytes + pts * spinor_point_bytes(prec) * ((epi & EPI_XPAY) ? 3 : 2);
+    return ws > 200e6;
 }
 
 int effective_tps(int prec, const LaunchCfg &cfg) {
@@ -434,16 +441,17 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
     a.chunk_sites = a.tchunk * a.g.L[2] * a.g.sz;
     dim3 grid((unsigned)hop_blocks(a.npts, block, tps), (unsigned)nparity);
     dim3 blk(block);
+    const bool nt = use_nontemporal(prec, cfg, a, nparity, epi);
     if (prec == WL_F64)
-        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, epi, tps, a, grid, blk, stream)
-                           : launch_dag<WL_F64, WL_F64, 18>(dagger, epi, tps, a, grid, blk, stream);
+        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, nt, epi, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F64, WL_F64, 18>(dagger, nt, epi, tps, a, grid, blk, stream);
     if (prec == WL_F32)
-        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, epi, tps, a, grid, blk, stream)
-                           : launch_dag<WL_F32, WL_F32, 18>(dagger, epi, tps, a, grid, blk, stream);
+        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, nt, epi, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F32, WL_F32, 18>(dagger, nt, epi, tps, a, grid, blk, stream);
     if (prec == WL_F16N && recon == 12)
-        return launch_dag<WL_F16N, WL_F16N, 12>(dagger, epi, tps, a, grid, blk, stream);
+        return launch_dag<WL_F16N, WL_F16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
     if (prec == WL_BF16N && recon == 12)
-        return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, epi, tps, a, grid, blk, stream);
+        return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
     return hipErrorInvalidValue;
 }
 

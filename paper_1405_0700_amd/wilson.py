@@ -246,19 +246,20 @@ def wl_cg_solve(ctx, x, b, op, kappa, nrhs=1, params: SolverParams | None = None
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int), ("swizzle", ctypes.c_int), ("tps", ctypes.c_int), ("tchunk", ctypes.c_int)]
+    _fields_ = [("block", ctypes.c_int), ("swizzle", ctypes.c_int), ("tps", ctypes.c_int), ("tchunk", ctypes.c_int),
+                ("nt", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.block, self.swizzle, self.tps, self.tchunk)
+        return (self.block, self.swizzle, self.tps, self.tchunk, self.nt)
 
 
-def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=0):
-    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk))
+def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=0, nt=-1):
+    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt))
     return _check(lib().wl_ctx_set_launch(ctx, prec, ctypes.addressof(cfg)))
 
 
 def wl_ctx_get_launch(ctx, prec):
-    """-> (block, swizzle, tps, tchunk)"""
+    """-> (block, swizzle, tps, tchunk, nt)"""
     cfg = Launch()
     _check(lib().wl_ctx_get_launch(ctx, prec, ctypes.addressof(cfg)))
     return cfg.as_tuple()

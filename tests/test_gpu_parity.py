@@ -357,17 +357,17 @@ def test_cg_free_field_plane_wave_one_iteration():
 
 # ------------------------------------------------------------------ launch configurations
 @pytest.mark.parametrize("prec", [W.WL_F64, W.WL_F32])
-@pytest.mark.parametrize("block,swizzle,tps,tchunk", [(64, 0, 1, 0), (256, 1, 2, 0), (128, 0, 2, 3),
-                                                      (192, 1, 1, 4), (64, 1, 2, 5), (256, 1, 1, 1)])
-def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk):
+@pytest.mark.parametrize("block,swizzle,tps,tchunk,nt", [(64, 0, 1, 0, 0), (256, 1, 2, 0, 1), (128, 0, 2, 3, -1),
+                                                         (192, 1, 1, 4, 1), (64, 1, 2, 5, 0), (256, 1, 1, 1, 1)])
+def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
     dims = (6, 10, 4, 14)
     kappa = 0.13
     ph = random_phases(77)
     u, lat = setup(dims, seed=78, phases=ph)
     saved = W.wl_ctx_get_launch(lat.ctx, prec)
-    W.wl_ctx_set_launch(lat.ctx, prec, block, swizzle, tps, tchunk)
+    W.wl_ctx_set_launch(lat.ctx, prec, block, swizzle, tps, tchunk, nt)
     try:
-        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk)
+        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk, nt)
         phi = synth.gaussian_spinor(dims, seed=79)
         for dagger in (False, True):
             want = orc.hop(phi, u, ph, dagger=dagger)
@@ -398,7 +398,7 @@ def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk):
 
 def test_launch_config_rejects_bad_values():
     _, lat = setup((4, 4, 4, 4))
-    for args in [(W.WL_F64, 32, 0, 1), (W.WL_F64, 320, 0, 1), (W.WL_F64, 256, 0, 3), (W.WL_F64, 256, 0, 1, -1)]:
+    for args in [(W.WL_F64, 32, 0, 1), (W.WL_F64, 320, 0, 1), (W.WL_F64, 256, 0, 3), (W.WL_F64, 256, 0, 1, -1), (W.WL_F64, 256, 0, 1, 0, 2)]:
         with pytest.raises(W.WilsonError) as e:
             W.wl_ctx_set_launch(lat.ctx, *args)
         assert e.value.status == W.WL_ERR_ARG

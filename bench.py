@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
+    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator"], default="eo-cg",
+                    help="eo-cg: the headline (24^3x48 FP64 e/o CG); mixed: 32^3x64 FP64 vs mixed-precision CG; "
+                         "propagator: 12 point sources, multi-RHS vs sequential")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -164,6 +167,65 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n, "launches": 5}))
         return
 
+    if args.workload == "mixed":
+        return run_mixed(args)
+    if args.workload == "propagator":
+        return run_propagator(args)
+    return run_eo_cg(args)
+
+
+class EoSolver:
+    """One e/o solve of D x = eta on a context: prepare, D_hat^+, CG, reconstruct."""
+
+    def __init__(self, lat, eta_full_internal, kappa, tol, nrhs=1):
+        from paper_1405_0700_amd import wilson as W
+        self.W, self.lat, self.kappa, self.nrhs = W, lat, kappa, nrhs
+        B = eta_full_internal
+        # an internal FULL field is the EVEN half followed by the ODD half
+        self.Be, self.Bo = B[: B.numel() // 2], B[B.numel() // 2:]
+        self.bhat = lat.new(W.WL_EVEN, W.WL_F64, nrhs)
+        self.rhs = lat.new(W.WL_EVEN, W.WL_F64, nrhs)
+        self.xe = lat.new(W.WL_EVEN, W.WL_F64, nrhs)
+        self.xo = lat.new(W.WL_ODD, W.WL_F64, nrhs)
+        self.params = W.wl_solver_params_default()
+        self.params.tol = tol
+
+    def set_precision(self, prec, recon):
+        self.params.prec, self.params.recon = prec, recon
+
+    def step(self):
+        W, lat, k, n = self.W, self.lat, self.kappa, self.nrhs
+        self.xe.zero_()
+        W.wl_eo_prepare(lat.ctx, self.bhat, self.Be, self.Bo, k, nrhs=n)
+        W.wl_dirac_apply(lat.ctx, self.rhs, self.bhat, W.WL_OP_DHAT, True, k, nrhs=n)
+        st, info = W.wl_cg_solve(lat.ctx, self.xe, self.rhs, W.WL_OP_DHAT, k, nrhs=n, params=self.params)
+        W.wl_eo_reconstruct(lat.ctx, self.xo, self.xe, self.Bo, k, nrhs=n)
+        if st != W.WL_OK:
+            print("[bench] solver status %d: %s" % (st, W.last_error()), file=sys.stderr)
+        return st, info
+
+    def timed(self, steps, warmup):
+        """-> (ms per step, infos of the last step)"""
+        import torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        ev0.record(stream)
+        infos = []
+        for _ in range(steps):
+            infos.append(self.step()[1])
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps, infos
+
+
+MIXED = [("f32_18", 1, 18), ("f32_12", 1, 12), ("f16n_12", 2, 12), ("bf16n_12", 3, 12), ("i16n_12", 4, 12)]
+
+
+def run_eo_cg(args):
+    import torch
     from paper_1405_0700_amd import wilson as W
     wl = WORKLOAD
     t0 = time.perf_counter()
@@ -171,27 +233,11 @@ def main():
     print("[bench] inputs generated in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     lat = W.Lattice.create(u, wl["phases"])
     vh = lat.volume // 2
-    # an internal FULL field is the EVEN half followed by the ODD half
-    B = lat.pack(eta, W.WL_FULL)
-    Be, Bo = B[: B.numel() // 2], B[B.numel() // 2:]
-    bhat = lat.new(W.WL_EVEN)
-    rhs = lat.new(W.WL_EVEN)
-    xe = lat.new(W.WL_EVEN)
-    xo = lat.new(W.WL_ODD)
     kappa = wl["kappa"]
-    params = W.wl_solver_params_default()
-    params.tol = wl["tol"]
-
-    def step():
-        xe.zero_()
-        W.wl_eo_prepare(lat.ctx, bhat, Be, Bo, kappa)
-        W.wl_dirac_apply(lat.ctx, rhs, bhat, W.WL_OP_DHAT, True, kappa)
-        st, info = W.wl_cg_solve(lat.ctx, xe, rhs, W.WL_OP_DHAT, kappa, params=params)
-        W.wl_eo_reconstruct(lat.ctx, xo, xe, Bo, kappa)
-        return st, info[0]
+    solver = EoSolver(lat, lat.pack(eta, W.WL_FULL), kappa, wl["tol"])
 
     for _ in range(args.warmup):
-        step()
+        solver.step()
     torch.cuda.synchronize()
     W.wl_timing_enable(lat.ctx, True)
     stream = torch.cuda.current_stream()
@@ -200,10 +246,8 @@ def main():
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
-        st, info = step()
-        if st != W.WL_OK:
-            print("[bench] solver status %d: %s" % (st, W.last_error()), file=sys.stderr)
-        infos.append(info)
+        st, info = solver.step()
+        infos.append(info[0])
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
@@ -218,15 +262,25 @@ def main():
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "wl::hop_kernel_split<0, 0, 18, false, 0> (FP64 half-dslash H_oe, 18-real links)",
+                "kernel": "wl::hop_kernel_split<0, 0, 18, false, 0, true> (FP64 half-dslash H_oe, 18-real links)",
                 "launches": n_hop, "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": SITE_BYTES["hop"] * vh}
+    xe_np = lat.unpack(solver.xe, W.WL_EVEN)
+    xo_np = lat.unpack(solver.xo, W.WL_ODD)
+
+    # the same solve with reduced-precision storage (time to the same FP64 tolerance)
+    mixed = {}
+    for name, prec, recon in MIXED:
+        solver.set_precision(prec, recon)
+        ms, inf = solver.timed(args.steps, 1)
+        mixed[name] = {"time_to_solution_ms": round(ms, 3), "iters": inf[-1][0]["iters"],
+                       "reliable_updates": inf[-1][0]["reliable_updates"],
+                       "true_rel_resid": inf[-1][0]["true_rel_resid"],
+                       "speedup_vs_f64": round(ms_per_step / ms, 3)}
 
     cpu = None
     resid = None
     if not args.no_cpu:
-        xe_np = lat.unpack(xe, W.WL_EVEN)
-        xo_np = lat.unpack(xo, W.WL_ODD)
         cpu, resid = cpu_baseline(u, eta, wl, xe_np, xo_np, args.cpu_iters)
 
     last = infos[-1]
@@ -254,8 +308,93 @@ def main():
         "true_rel_resid_gpu": last["true_rel_resid"],
         "oracle_full_system_rel_resid": resid,
         "algorithmic_bytes_per_step": nbytes // args.steps,
+        "mixed_precision_same_system": mixed,
     }
     print(json.dumps(line))
+    lat.close()
+
+
+def run_mixed(args):
+    """32^3x64, kappa 0.137: FP64 CG against mixed-precision CG (FP64 reliable updates)."""
+    from paper_1405_0700_amd import wilson as W
+    wl = dict(dims=(32, 32, 32, 64), eps=0.2, gauge_seed=301, src_seed=302, kappa=0.137, phases=(1, 1, 1, -1),
+              tol=1e-10)
+    u, eta = make_inputs(wl)
+    lat = W.Lattice.create(u, wl["phases"])
+    solver = EoSolver(lat, lat.pack(eta, W.WL_FULL), wl["kappa"], wl["tol"])
+    res = {}
+    for name, prec, recon in [("f64_18", 0, 18)] + MIXED:
+        solver.set_precision(prec, recon)
+        ms, inf = solver.timed(args.steps, args.warmup)
+        res[name] = {"time_to_solution_ms": round(ms, 3), "iters": inf[-1][0]["iters"],
+                     "reliable_updates": inf[-1][0]["reliable_updates"],
+                     "restarts": inf[-1][0]["restarts"], "true_rel_resid": inf[-1][0]["true_rel_resid"]}
+        print("[bench] %s %s" % (name, res[name]), file=sys.stderr, flush=True)
+    best = min((v["time_to_solution_ms"], k) for k, v in res.items() if k != "f64_18")
+    print(json.dumps({"metric": "CG time-to-1e-10, plain FP64 vs mixed precision", "workload":
+                      "even/odd Wilson CG, 32^3x64, kappa 0.137, links exp(0.2iH) seed 301, source seed 302",
+                      "unit": "ms", "higher_is_better": False, "results": res,
+                      "best_mixed": best[1], "speedup_best_mixed_vs_f64": round(res["f64_18"]["time_to_solution_ms"] / best[0], 3)}))
+    lat.close()
+
+
+def run_propagator(args):
+    """24^3x48, kappa 0.135: the 12 spin-colour point sources at the origin, solved one by
+    one and together in one multi-RHS solve; plus the multi-RHS dslash throughput."""
+    import numpy as np
+    import torch
+    from paper_1405_0700_amd import synth
+    from paper_1405_0700_amd import wilson as W
+    dims, kappa = (24, 24, 24, 48), 0.135
+    u = synth.su3_links(dims, 0.2, 401)
+    lat = W.Lattice.create(u, (1, 1, 1, -1))
+    vh = lat.volume // 2
+    etas = np.stack([synth.point_source(dims, s, c).reshape(-1, 4, 3) for s in range(4) for c in range(3)])
+    res = {}
+    for name, prec, recon in [("f64_18", 0, 18), ("f32_18", 1, 18), ("f16n_12", 2, 12)]:
+        multi = EoSolver(lat, lat.pack(etas, W.WL_FULL, W.WL_F64, 12), kappa, 1e-10, nrhs=12)
+        multi.set_precision(prec, recon)
+        ms_multi, inf = multi.timed(args.steps, args.warmup)
+        iters = [i["iters"] for i in inf[-1]]
+        singles = [EoSolver(lat, lat.pack(etas[k], W.WL_FULL), kappa, 1e-10) for k in range(12)]
+        for s_ in singles:
+            s_.set_precision(prec, recon)
+        def all12():
+            for s_ in singles:
+                s_.step()
+        for _ in range(args.warmup):
+            all12()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            all12()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_seq = ev0.elapsed_time(ev1) / args.steps
+        res[name] = {"twelve_rhs_one_solve_ms": round(ms_multi, 3), "twelve_sequential_solves_ms": round(ms_seq, 3),
+                     "speedup": round(ms_seq / ms_multi, 3), "iters": iters}
+        print("[bench] %s %s" % (name, res[name]), file=sys.stderr, flush=True)
+        del multi, singles
+    # 12-RHS half-dslash throughput (FP32 storage, 18-real links): 576 B of links + 12 x 192 B of spinors per site
+    x = lat.new(W.WL_ODD, W.WL_F32, 12)
+    y = lat.new(W.WL_EVEN, W.WL_F32, 12)
+    for _ in range(3):
+        W.wl_dslash_apply(lat.ctx, y, x, W.WL_EVEN, W.WL_F32, 18, 12)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        W.wl_dslash_apply(lat.ctx, y, x, W.WL_EVEN, W.WL_F32, 18, 12)
+    ev1.record()
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) / 20 * 1e3
+    gbs = (576 + 12 * 192) * vh / us / 1e3
+    print(json.dumps({"metric": "12-RHS propagator: one multi-RHS solve vs 12 solves", "unit": "ms",
+                      "workload": "24^3x48, kappa 0.135, links exp(0.2iH) seed 401, 12 point sources at the origin",
+                      "higher_is_better": False, "results": res,
+                      "dslash_12rhs_f32_18": {"us": round(us, 2), "algorithmic_GBps": round(gbs, 1),
+                                               "bytes_per_site": 576 + 12 * 192}}))
     lat.close()
 
 

@@ -72,8 +72,10 @@ typedef enum {
 
 /* Storage precision of internal spinor and link fields.  Arithmetic is FP64 for
  * WL_F64 and FP32 for all others.  The 16-bit formats store each spinor point
- * scaled by its own FP32 norm s = max |component| (s = 0 stores zeros). */
-typedef enum { WL_F64 = 0, WL_F32 = 1, WL_F16N = 2, WL_BF16N = 3 } wl_prec;
+ * scaled by its own FP32 norm s = max |component| (s = 0 stores zeros), as
+ * IEEE half (F16N), bfloat16 (BF16N) or 16-bit fixed point q = round(32767 v / s)
+ * (I16N); 16-bit links are stored unscaled (|U_ij| <= 1), 12-real only. */
+typedef enum { WL_F64 = 0, WL_F32 = 1, WL_F16N = 2, WL_BF16N = 3, WL_I16N = 4 } wl_prec;
 
 typedef enum { WL_EVEN = 0, WL_ODD = 1, WL_FULL = 2 } wl_subset;
 
@@ -200,7 +202,11 @@ typedef struct {
     int recon;           /* 18 or 12                                                  */
     int reliable_every;  /* mixed precision: FP64 residual refresh every this many iters */
     double reliable_delta; /* mixed precision: also refresh when ||r|| < delta * max ||r|| */
-    int use_graph;       /* capture the iteration block in a hipGraph and replay it    */
+    int use_graph;       /* replay each plain iteration from a captured hipGraph        */
+    int ru_restart;      /* mixed precision: restart the search direction (p = r) at
+                            every FP64 residual refresh; 1 on, 0 off, -1 on for the
+                            16-bit formats (whose iterated residual drifts too far
+                            for the old direction to stay useful)                    */
 } wl_solver_params;
 
 typedef struct {
@@ -213,7 +219,12 @@ typedef struct {
 } wl_solver_info;
 
 /* Fill in defaults: tol 1e-10, maxiter 100000, check_every 25, max_restarts 5,
- * prec WL_F64, recon 18, reliable_every 100, reliable_delta 0.1, no graph. */
+ * prec WL_F64, recon 18, reliable_every 100, reliable_delta 0.1, no graph,
+ * ru_restart -1.
+ * Mixed precision: the FP64 residual is refreshed every reliable_every
+ * iterations and whenever ||r|| has dropped by reliable_delta since the last
+ * refresh; the iteration of that drop is predicted from the observed decay of
+ * ||r|| (no device-to-host read in between). */
 void wl_solver_params_default(wl_solver_params *p);
 
 /* Conjugate gradient on the normal equations M^+ M x = b, M = D or D_hat.

@@ -55,13 +55,13 @@ struct wl_ctx {
     long V, Vh;
     int device;
     Geom g;
-    void *gauge[4][2] = {};  // [prec][recon == 12]
-    size_t slab[4][2] = {};
+    void *gauge[5][2] = {};  // [prec][recon == 12]
+    size_t slab[5][2] = {};
     void *buf[S_NSLOTS] = {};
     size_t buf_bytes[S_NSLOTS] = {};
     void *host_pinned = nullptr;
     size_t host_pinned_bytes = 0;
-    LaunchCfg cfg[4];  // hopping-kernel launch configuration per storage precision
+    LaunchCfg cfg[5];  // hopping-kernel launch configuration per storage precision
     // kernel timing
     bool timing = false;
     struct TimedLaunch {
@@ -75,16 +75,23 @@ struct wl_ctx {
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
     size_t pool_used = 0;
+    bool capturing = false;  // no timing events inside a stream capture
+    // hipGraph replay of one CG iteration (solver param use_graph)
+    hipStream_t own_stream = nullptr;  // capture needs a stream other than the null stream
+    hipEvent_t handoff[2] = {nullptr, nullptr};
+    hipGraph_t cg_graph = nullptr;
+    hipGraphExec_t cg_exec = nullptr;
+    std::vector<uintptr_t> cg_graph_key;
 };
 
 static int timing_key(int prec, int recon, int dagger, int epi) {
     return ((prec * 2 + (recon == 12 ? 1 : 0)) * 2 + (dagger ? 1 : 0)) * 4 + epi;
 }
 
-static bool prec_ok(int p) { return p >= WL_F64 && p <= WL_BF16N; }
+static bool prec_ok(int p) { return p >= WL_F64 && p <= WL_I16N; }
 static bool recon_ok(int prec, int r) {
     if (r != 12 && r != 18) return false;
-    if ((prec == WL_F16N || prec == WL_BF16N) && r != 12) return false;
+    if (prec >= WL_F16N && r != 12) return false;
     return true;
 }
 
@@ -202,6 +209,7 @@ static hipError_t launch_prec(int prec, dim3 grid, hipStream_t s, A... args) {
     case WL_F32: hipLaunchKernelGGL(K<WL_F32>::fn, grid, dim3(256), 0, s, args...); break;
     case WL_F16N: hipLaunchKernelGGL(K<WL_F16N>::fn, grid, dim3(256), 0, s, args...); break;
     case WL_BF16N: hipLaunchKernelGGL(K<WL_BF16N>::fn, grid, dim3(256), 0, s, args...); break;
+    case WL_I16N: hipLaunchKernelGGL(K<WL_I16N>::fn, grid, dim3(256), 0, s, args...); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -310,6 +318,7 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
     c->cfg[WL_F32] = {128, 1, 2, 0, -1};
     c->cfg[WL_F16N] = {256, 1, 1, 0, -1};
     c->cfg[WL_BF16N] = {256, 1, 1, 0, -1};
+    c->cfg[WL_I16N] = {256, 1, 1, 0, -1};
     c->slab[WL_F64][0] = slab;
     *out = c;
     return WL_OK;
@@ -319,7 +328,12 @@ extern "C" wl_status wl_ctx_destroy(wl_ctx *c) {
     if (!c) return WL_OK;
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
-    for (int p = 0; p < 4; ++p)
+    if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
+    if (c->cg_graph) (void)hipGraphDestroy(c->cg_graph);
+    for (hipEvent_t e : c->handoff)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    for (int p = 0; p < 5; ++p)
         for (int r = 0; r < 2; ++r)
             if (c->gauge[p][r]) (void)hipFree(c->gauge[p][r]);
     for (int s = 0; s < S_NSLOTS; ++s)
@@ -349,6 +363,7 @@ static wl_status get_links(wl_ctx *c, int prec, int recon, const void **ptr, siz
         else if (prec == WL_F32 && recon == 12) hipLaunchKernelGGL((k_link_convert<WL_F32, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
         else if (prec == WL_F16N) hipLaunchKernelGGL((k_link_convert<WL_F16N, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
         else if (prec == WL_BF16N) hipLaunchKernelGGL((k_link_convert<WL_BF16N, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
+        else if (prec == WL_I16N) hipLaunchKernelGGL((k_link_convert<WL_I16N, 12>), grid, dim3(256), 0, 0, d, sl, src, ss, vh);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipDeviceSynchronize());
         c->gauge[prec][ri] = d;
@@ -479,7 +494,7 @@ static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, voi
         h.out_par0 = p;
     }
     hipEvent_t *ev = nullptr;
-    if (c->timing && c->timed.size() < (1u << 16)) {
+    if (c->timing && !c->capturing && c->timed.size() < (1u << 16)) {
         if (c->pool_used + 2 > c->event_pool.size()) {
             for (int k = 0; k < 256; ++k) {
                 hipEvent_t e;
@@ -693,6 +708,7 @@ extern "C" void wl_solver_params_default(wl_solver_params *p) {
     p->reliable_every = 100;
     p->reliable_delta = 0.1;
     p->use_graph = 0;
+    p->ru_restart = -1;
 }
 
 namespace {
@@ -711,6 +727,7 @@ struct CGRun {
     double *bnorm2;
     int *done;
     long nblk_blas;
+    int ru_restart;
 };
 }  // namespace
 
@@ -775,13 +792,59 @@ static wl_status cg_iteration(CGRun &R, bool reliable) {
         w.flag = R.done;
         HIP_TRY(blas_convert(R.prec, WL_F64, false, w, R.nh, R.s));
     }
-    HIP_TRY(cg_beta(R.sc, R.nrhs, R.partials, R.stride, R.nblk_blas, R.done, reliable ? 1 : 0, R.s));
+    HIP_TRY(cg_beta(R.sc, R.nrhs, R.partials, R.stride, R.nblk_blas, R.done,
+                    reliable ? (R.ru_restart ? 2 : 1) : 0, R.s));
     VecArgs u = vec_args(R.c, R.prec, R.nrhs);
     set_vec(u, 0, R.r, R.hb_lo);
     set_vec(u, 1, R.p, R.hb_lo);
     u.sc = R.sc;
     u.flag = R.done;
     HIP_TRY(cg_update_p(R.prec, u, R.nh, R.s));
+    return WL_OK;
+}
+
+// Everything one plain iteration depends on; a captured graph is reused only
+// while this key is unchanged.
+static std::vector<uintptr_t> graph_key(const CGRun &R) {
+    const LaunchCfg &g = R.c->cfg[R.prec];
+    uint64_t kb;
+    std::memcpy(&kb, &R.kappa, sizeof kb);
+    return {(uintptr_t)R.op, (uintptr_t)R.prec, (uintptr_t)R.recon, (uintptr_t)R.nrhs, (uintptr_t)kb,
+            (uintptr_t)R.x, (uintptr_t)R.r, (uintptr_t)R.p, (uintptr_t)R.q, (uintptr_t)R.sv, (uintptr_t)R.tmp,
+            (uintptr_t)R.partials, (uintptr_t)R.stride, (uintptr_t)R.sc, (uintptr_t)R.done,
+            (uintptr_t)R.nblk_blas, (uintptr_t)g.block, (uintptr_t)g.swizzle, (uintptr_t)g.tps,
+            (uintptr_t)g.tchunk, (uintptr_t)(g.nt + 1)};
+}
+
+// Capture one plain CG iteration on R.s (the context's own stream) into a
+// graph, unless the cached one matches.
+static wl_status ensure_iteration_graph(CGRun &R) {
+    wl_ctx *c = R.c;
+    std::vector<uintptr_t> key = graph_key(R);
+    if (c->cg_exec && key == c->cg_graph_key) return WL_OK;
+    if (c->cg_exec) HIP_TRY(hipGraphExecDestroy(c->cg_exec));
+    if (c->cg_graph) HIP_TRY(hipGraphDestroy(c->cg_graph));
+    c->cg_exec = nullptr;
+    c->cg_graph = nullptr;
+    c->cg_graph_key.clear();
+    HIP_TRY(hipStreamBeginCapture(R.s, hipStreamCaptureModeRelaxed));
+    c->capturing = true;
+    wl_status st = cg_iteration(R, false);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(R.s, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(WL_ERR_HIP, "stream capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->cg_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(WL_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    c->cg_graph = g;
+    c->cg_graph_key = key;
     return WL_OK;
 }
 
@@ -811,7 +874,21 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
     R.recon = P.recon;
     R.nh = nh;
     R.kappa = kappa;
+    R.ru_restart = P.ru_restart < 0 ? (P.prec >= WL_F16N ? 1 : 0) : P.ru_restart;
     R.s = (hipStream_t)stream;
+    const bool graph = P.use_graph != 0;
+    if (graph) {
+        // capture needs a stream other than the null stream: run the solve on the
+        // context's own stream, ordered after the caller's work and before its next
+        if (!c->own_stream) {
+            HIP_TRY(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&c->handoff[0], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&c->handoff[1], hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(c->handoff[0], (hipStream_t)stream));
+        HIP_TRY(hipStreamWaitEvent(c->own_stream, c->handoff[0], 0));
+        R.s = c->own_stream;
+    }
     R.hb_lo = half_bytes(c, P.prec, nrhs);
     R.hb_hi = half_bytes(c, WL_F64, nrhs);
     if (overlap(x, R.hb_hi * nh, b, R.hb_hi * nh)) return fail(WL_ERR_ARG, "x and b overlap");
@@ -871,39 +948,59 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
         // Iterations are enqueued in blocks between host reads of the device
         // scalars.  Near convergence the block is sized from the observed decay
         // of ||r||^2 (with a margin), so that few or no iterations are enqueued
-        // after the last one that does work (those launches exit at once).
+        // after the last one that does work (those launches exit at once).  In
+        // mixed precision the same decay rate predicts the iteration at which
+        // ||r|| will have dropped by reliable_delta, and the FP64 refresh is
+        // scheduled there.
         int block = std::max(1, std::min(P.check_every, remaining));
+        int ru_in = P.reliable_every > 0 ? P.reliable_every : INT32_MAX;  // iterations until the next refresh
         std::vector<double> prev_rho(nrhs, -1.0);
         std::vector<int> prev_it(nrhs, 0);
         ++c->timing_cycle;
         for (;;) {
             for (int j = 0; j < block; ++j, ++k) {
                 bool ru = false;
-                if (mixed && P.reliable_every > 0 && ++since_reliable >= P.reliable_every) {
+                if (mixed && ++since_reliable >= ru_in) {
                     ru = true;
                     since_reliable = 0;
+                    ru_in = P.reliable_every > 0 ? P.reliable_every : INT32_MAX;
                     for (int r = 0; r < nrhs; ++r) reliable[r]++;
                 }
                 c->timing_iter = k;
-                st = cg_iteration(R, ru);
+                if (graph && !ru) {
+                    st = ensure_iteration_graph(R);
+                    if (st) return st;
+                    HIP_TRY(hipGraphLaunch(c->cg_exec, R.s));
+                } else {
+                    st = cg_iteration(R, ru);
+                }
                 c->timing_iter = -1;
                 if (st) return st;
             }
             HIP_TRY(hipMemcpyAsync(c->host_pinned, R.sc, sizeof(CGScalars) * nrhs, hipMemcpyDeviceToHost, R.s));
             HIP_TRY(hipStreamSynchronize(R.s));
             std::memcpy(hsc.data(), c->host_pinned, sizeof(CGScalars) * nrhs);
-            bool any = false, need_ru = false;
+            bool any = false;
             int next = 1;
+            int ru_pred = INT32_MAX;
             for (int r = 0; r < nrhs; ++r) {
                 const CGScalars &h = hsc[r];
                 any |= h.active != 0;
                 if (!h.active) continue;
-                if (mixed && h.rho < P.reliable_delta * P.reliable_delta * h.rho_max) need_ru = true;
                 int est = P.check_every;
-                if (prev_rho[r] > 0.0 && h.rho < prev_rho[r] && h.iter > prev_it[r] && h.target > 0.0) {
-                    const double rate = std::log(h.rho / prev_rho[r]) / (h.iter - prev_it[r]);
-                    const double left = std::log(h.target / h.rho) / rate;
-                    if (std::isfinite(left)) est = (int)std::floor(0.8 * left);
+                if (prev_rho[r] > 0.0 && h.rho < prev_rho[r] && h.iter > prev_it[r]) {
+                    const double rate = std::log(h.rho / prev_rho[r]) / (h.iter - prev_it[r]);  // < 0
+                    if (h.target > 0.0) {
+                        const double left = std::log(h.target / h.rho) / rate;
+                        if (std::isfinite(left)) est = (int)std::floor(0.8 * left);
+                    }
+                    if (mixed) {
+                        const double drop = P.reliable_delta * P.reliable_delta * h.rho_max;
+                        const double until = h.rho <= drop ? 0.0 : std::log(drop / h.rho) / rate;
+                        if (std::isfinite(until)) ru_pred = std::min(ru_pred, std::max(1, (int)std::ceil(until)));
+                    }
+                } else if (mixed && h.rho < P.reliable_delta * P.reliable_delta * h.rho_max) {
+                    ru_pred = 1;
                 }
                 prev_rho[r] = h.rho;
                 prev_it[r] = h.iter;
@@ -911,14 +1008,10 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
             }
             if (!any) break;
             block = std::max(1, next);
-            if (need_ru) {
-                // an FP64 refresh forced by the residual drop, carried by the next iteration
-                c->timing_iter = k++;
-                st = cg_iteration(R, true);
-                c->timing_iter = -1;
-                if (st) return st;
-                since_reliable = 0;
-                for (int r = 0; r < nrhs; ++r) reliable[r]++;
+            if (mixed && ru_pred != INT32_MAX) {
+                // refresh at the predicted drop (counted from now), or at the fixed cadence
+                const int fixed_left = (P.reliable_every > 0 ? P.reliable_every : INT32_MAX) - since_reliable;
+                ru_in = since_reliable + std::max(1, std::min(ru_pred, fixed_left));
             }
         }
         int maxit = 0;
@@ -964,6 +1057,10 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
             break;
         }
         ++restarts;
+    }
+    if (graph) {
+        HIP_TRY(hipEventRecord(c->handoff[1], R.s));
+        HIP_TRY(hipStreamWaitEvent((hipStream_t)stream, c->handoff[1], 0));
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)

@@ -17,6 +17,7 @@ struct CGScalars {
     int active;      // 1 while iterating
     int status;      // WL_OK / WL_NOT_CONVERGED / WL_BREAKDOWN
     int maxiter;
+    int leaving;     // stopped at the alpha step; leaves the active count at the beta step
 };
 
 struct VecArgs {
@@ -27,7 +28,7 @@ struct VecArgs {
     double *partials;  // per-block partial sums, rhs r at partials[r * part_stride + block]
     long part_stride;
     CGScalars *sc;     // per-rhs solver scalars (kernels that use them)
-    const int *flag;   // if non-null and *flag != 0 the launch does nothing
+    const int *flag;   // if non-null and *flag == 0 (no system still iterating) the launch does nothing
 };
 
 // all launchers: nhalves = 1 (EVEN/ODD field) or 2 (FULL field)
@@ -54,12 +55,15 @@ hipError_t reduce_partials(const double *partials, long stride, long nblk, int n
                            hipStream_t s);
 // CG scalar steps (one launch each, all rhs):
 //   alpha: pap = sum; breakdown check; alpha = rho / pap
-//   beta : rho' = sum; convergence / maxiter checks; beta = rho' / rho; sets *done when no rhs is active
+//   beta : rho' = sum; convergence / maxiter checks; beta = rho' / rho
+// `done` / `flag` point at the number of systems still iterating (one block per
+// system; a system that stops decrements it)
 hipError_t cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                     const int *flag, hipStream_t s);
-//   reset_max: the residual was just refreshed in FP64; restart the rho_max record from it
+//   mode 1: the residual was just refreshed in FP64 (restart the rho_max record);
+//   mode 2: also restart the search direction (beta = 0)
 hipError_t cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *done,
-                   int reset_max, hipStream_t s);
+                   int mode, hipStream_t s);
 // initialise: rho = sum(partials) (||r0||^2), target = tol^2 * bnorm2[r]; active if rho > target
 hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                    const double *bnorm2, double tol, int maxiter, int *done, hipStream_t s);

@@ -10,7 +10,7 @@
 namespace wl {
 
 #define WL_FLAG_EXIT \
-    if (a.flag && *a.flag) return;
+    if (a.flag && *a.flag == 0) return;
 
 template <int SP, bool NORM>
 __global__ void __launch_bounds__(256) k_axpby(const VecArgs a) {
@@ -214,67 +214,77 @@ __global__ void __launch_bounds__(256) k_reduce(const double *partials, long str
     }
 }
 
-__global__ void __launch_bounds__(256) k_cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride,
-                                                  long nblk, const int *flag) {
-    if (flag && *flag) return;
+// One block per right-hand side.  `count` holds the number of right-hand
+// sides still iterating; a system leaves the count when it stops.
+__global__ void __launch_bounds__(256) k_cg_alpha(CGScalars *sc, const double *partials, long stride, long nblk,
+                                                  const int *count) {
+    if (count && *count == 0) return;
     __shared__ double lds[16];
-    for (int r = 0; r < nrhs; ++r) {
-        const double s = sum_partials(partials + (long)r * stride, nblk, lds);
-        if (threadIdx.x == 0) {
-            CGScalars &c = sc[r];
-            if (c.active) {
-                c.pap = s;
-                if (!(s > 0.0) || !isfinite(s) || !isfinite(c.rho)) {
-                    c.status = WL_BREAKDOWN;
-                    c.active = 0;
-                    c.alpha = 0.0;
-                } else {
-                    c.alpha = c.rho / s;
-                }
-            } else {
-                c.alpha = 0.0;
-            }
+    const int r = blockIdx.x;
+    CGScalars &c = sc[r];
+    if (!c.active) {
+        if (threadIdx.x == 0) c.alpha = 0.0;
+        return;
+    }
+    const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+    if (threadIdx.x == 0) {
+        c.pap = s;
+        if (!(s > 0.0) || !isfinite(s) || !isfinite(c.rho)) {
+            c.status = WL_BREAKDOWN;
+            c.active = 0;
+            c.alpha = 0.0;
+            // leaves the count at the beta step of this iteration
+            c.leaving = 1;
+        } else {
+            c.alpha = c.rho / s;
         }
     }
 }
 
-__global__ void __launch_bounds__(256) k_cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride,
-                                                 long nblk, int *done, int reset_max) {
-    if (*done) return;
+__global__ void __launch_bounds__(256) k_cg_beta(CGScalars *sc, const double *partials, long stride, long nblk,
+                                                 int *count, int mode) {
+    if (*count == 0) return;
     __shared__ double lds[16];
-    int any = 0;
-    for (int r = 0; r < nrhs; ++r) {
-        const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+    const int r = blockIdx.x;
+    CGScalars &c = sc[r];
+    if (!c.active) {
         if (threadIdx.x == 0) {
-            CGScalars &c = sc[r];
             c.beta = 0.0;
-            if (c.active) {
-                c.iter += 1;
-                if (!isfinite(s)) {
-                    c.status = WL_BREAKDOWN;
-                    c.active = 0;
-                } else {
-                    c.beta = s / c.rho;
-                    c.rho = s;
-                    c.rho_max = reset_max ? s : fmax(c.rho_max, s);
-                    if (s <= c.target) {
-                        c.status = WL_OK;
-                        c.active = 0;
-                    } else if (c.iter >= c.maxiter) {
-                        c.status = WL_NOT_CONVERGED;
-                        c.active = 0;
-                    }
-                }
+            if (c.leaving) {
+                c.leaving = 0;
+                atomicSub(count, 1);
             }
-            any |= c.active;
         }
+        return;
     }
-    if (threadIdx.x == 0) *done = any ? 0 : 1;
+    const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+    if (threadIdx.x == 0) {
+        c.beta = 0.0;
+        c.iter += 1;
+        if (!isfinite(s)) {
+            c.status = WL_BREAKDOWN;
+            c.active = 0;
+        } else {
+            // mode 0: plain step; 1: the residual was just refreshed in FP64 (restart
+            // the rho_max record); 2: also restart the search direction
+            c.beta = mode == 2 ? 0.0 : s / c.rho;
+            c.rho = s;
+            c.rho_max = mode ? s : fmax(c.rho_max, s);
+            if (s <= c.target) {
+                c.status = WL_OK;
+                c.active = 0;
+            } else if (c.iter >= c.maxiter) {
+                c.status = WL_NOT_CONVERGED;
+                c.active = 0;
+            }
+        }
+        if (!c.active) atomicSub(count, 1);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const double *partials, long stride,
                                                  long nblk, const double *bnorm2, double tol, int maxiter,
-                                                 int *done) {
+                                                 int *count) {
     __shared__ double lds[16];
     int any = 0;
     for (int r = 0; r < nrhs; ++r) {
@@ -289,6 +299,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const 
             c.target = tol * tol * bnorm2[r];
             c.iter = 0;
             c.maxiter = maxiter;
+            c.leaving = 0;
             if (!isfinite(s)) {
                 c.status = WL_BREAKDOWN;
                 c.active = 0;
@@ -302,10 +313,10 @@ __global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const 
                 c.status = WL_NOT_CONVERGED;
                 c.active = 1;
             }
-            any |= c.active;
+            any += c.active;
         }
     }
-    if (threadIdx.x == 0) *done = any ? 0 : 1;
+    if (threadIdx.x == 0) *count = any;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -315,6 +326,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const 
     case WL_F32: hipLaunchKernelGGL((KERNEL<WL_F32 __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break;   \
     case WL_F16N: hipLaunchKernelGGL((KERNEL<WL_F16N __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break; \
     case WL_BF16N: hipLaunchKernelGGL((KERNEL<WL_BF16N __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break; \
+    case WL_I16N: hipLaunchKernelGGL((KERNEL<WL_I16N __VA_ARGS__>), grid, dim3(blas_block()), 0, s, a); break; \
     default: return hipErrorInvalidValue;                                                              \
     }                                                                                                  \
     return hipGetLastError();
@@ -362,6 +374,7 @@ static hipError_t convert_src(int sprec, VecArgs &a, dim3 grid, hipStream_t s) {
     case WL_F32: hipLaunchKernelGGL((k_convert<DP, WL_F32, ACC>), grid, dim3(blas_block()), 0, s, a); break;
     case WL_F16N: hipLaunchKernelGGL((k_convert<DP, WL_F16N, ACC>), grid, dim3(blas_block()), 0, s, a); break;
     case WL_BF16N: hipLaunchKernelGGL((k_convert<DP, WL_BF16N, ACC>), grid, dim3(blas_block()), 0, s, a); break;
+    case WL_I16N: hipLaunchKernelGGL((k_convert<DP, WL_I16N, ACC>), grid, dim3(blas_block()), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -373,6 +386,7 @@ static hipError_t convert_dst(int dprec, int sprec, VecArgs &a, dim3 grid, hipSt
     case WL_F32: return convert_src<WL_F32, ACC>(sprec, a, grid, s);
     case WL_F16N: return convert_src<WL_F16N, ACC>(sprec, a, grid, s);
     case WL_BF16N: return convert_src<WL_BF16N, ACC>(sprec, a, grid, s);
+    case WL_I16N: return convert_src<WL_I16N, ACC>(sprec, a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -388,12 +402,12 @@ hipError_t reduce_partials(const double *partials, long stride, long nblk, int n
 }
 hipError_t cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                     const int *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, sc, nrhs, partials, stride, nblk, flag);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(nrhs), dim3(256), 0, s, sc, partials, stride, nblk, flag);
     return hipGetLastError();
 }
 hipError_t cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *done,
-                   int reset_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, sc, nrhs, partials, stride, nblk, done, reset_max);
+                   int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(nrhs), dim3(256), 0, s, sc, partials, stride, nblk, done, mode);
     return hipGetLastError();
 }
 hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,

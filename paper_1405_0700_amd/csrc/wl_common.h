@@ -66,6 +66,14 @@ template <> struct Half16<WL_BF16N> {
     __device__ static float dec(uint16_t u) { return bf16_to_f32(u); }
     __device__ static uint16_t enc(float f) { return f32_to_bf16(f); }
 };
+// 16-bit fixed point for values in [-1, 1]: q = round(32767 f)
+template <> struct Half16<WL_I16N> {
+    __device__ static float dec(uint16_t u) { return (float)(int16_t)u * (1.0f / 32767.0f); }
+    __device__ static uint16_t enc(float f) {
+        const float q = fminf(fmaxf(rintf(f * 32767.0f), -32767.0f), 32767.0f);
+        return (uint16_t)(int16_t)q;
+    }
+};
 
 // ------------------------------------------------------------------ spinor storage
 // An internal field of one parity holds n = Vh * nrhs "points" (site, rhs),
@@ -214,6 +222,7 @@ template <int P> struct SpinorIO16 {
 };
 template <> struct SpinorIO<WL_F16N> : SpinorIO16<WL_F16N> {};
 template <> struct SpinorIO<WL_BF16N> : SpinorIO16<WL_BF16N> {};
+template <> struct SpinorIO<WL_I16N> : SpinorIO16<WL_I16N> {};
 
 // ------------------------------------------------------------------ link storage
 // Links of one (parity, mu) slab: Vh links in blocks of 64 sites, each block
@@ -326,6 +335,7 @@ template <int P> struct LinkIO16 {
 };
 template <> struct LinkIO<WL_F16N, 12> : LinkIO16<WL_F16N> {};
 template <> struct LinkIO<WL_BF16N, 12> : LinkIO16<WL_BF16N> {};
+template <> struct LinkIO<WL_I16N, 12> : LinkIO16<WL_I16N> {};
 
 // host-side sizes: a field of n points (or a slab of n links) occupies
 // ceil(n / 64) blocks

@@ -20,7 +20,7 @@ struct HopArgs {
     double a, b;          // out = a x + b (H in)   (a ignored without EPI_XPAY)
     double *partials;     // EPI_NORM: per-block, per-rhs partial sums of ||out||^2
     long part_stride;     // distance between the partials of consecutive rhs
-    const int *flag;      // if non-null and *flag != 0 the launch does nothing
+    const int *flag;      // if non-null and *flag == 0 (no system still iterating) the launch does nothing
     int swizzle;          // map consecutive blocks to the same XCD
     int tchunk;           // processing order (see LaunchCfg)
     int chunk_sites;      // sites of a full chunk: tchunk * Lz * (Lx/2) * Ly

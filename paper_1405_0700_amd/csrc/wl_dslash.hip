@@ -257,7 +257,7 @@ __device__ __forceinline__ long logical_block(int swizzle) {
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
     using T = typename SpinorIO<SP>::real;
-    if (a.flag && *a.flag) return;
+    if (a.flag && *a.flag == 0) return;
     const int par = a.out_par0 + blockIdx.y;
     const long lb = logical_block(a.swizzle);
     const long gid = lb * blockDim.x + threadIdx.x;  // position in the processing order
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 __global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
     using T = typename SpinorIO<SP>::real;
-    if (a.flag && *a.flag) return;
+    if (a.flag && *a.flag == 0) return;
     const int par = a.out_par0 + blockIdx.y;
     const long lb = logical_block(a.swizzle);
     const int lane = threadIdx.x & 63;
@@ -452,6 +452,8 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
         return launch_dag<WL_F16N, WL_F16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
     if (prec == WL_BF16N && recon == 12)
         return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
+    if (prec == WL_I16N && recon == 12)
+        return launch_dag<WL_I16N, WL_I16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
     return hipErrorInvalidValue;
 }
 

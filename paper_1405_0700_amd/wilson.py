@@ -23,11 +23,11 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "wilson.h")
 # enums (wilson.h)
 WL_OK, WL_NOT_CONVERGED, WL_BREAKDOWN = 0, 1, 2
 WL_ERR_ARG, WL_ERR_DIMS, WL_ERR_HIP, WL_ERR_NOMEM, WL_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
-WL_F64, WL_F32, WL_F16N, WL_BF16N = 0, 1, 2, 3
+WL_F64, WL_F32, WL_F16N, WL_BF16N, WL_I16N = 0, 1, 2, 3, 4
 WL_EVEN, WL_ODD, WL_FULL = 0, 1, 2
 WL_OP_D, WL_OP_DHAT = 0, 1
 
-PREC = {"f64": WL_F64, "f32": WL_F32, "f16n": WL_F16N, "bf16n": WL_BF16N}
+PREC = {"f64": WL_F64, "f32": WL_F32, "f16n": WL_F16N, "bf16n": WL_BF16N, "i16n": WL_I16N}
 SUBSET = {"even": WL_EVEN, "odd": WL_ODD, "full": WL_FULL}
 OP = {"D": WL_OP_D, "Dhat": WL_OP_DHAT}
 
@@ -49,6 +49,7 @@ class SolverParams(ctypes.Structure):
         ("reliable_every", ctypes.c_int),
         ("reliable_delta", ctypes.c_double),
         ("use_graph", ctypes.c_int),
+        ("ru_restart", ctypes.c_int),
     ]
 
 

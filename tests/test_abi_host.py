@@ -28,6 +28,7 @@ def test_version_and_defaults(lib):
     p = W.wl_solver_params_default()
     assert p.tol == 1e-10 and p.maxiter == 100000 and p.prec == W.WL_F64 and p.recon == 18
     assert p.check_every == 25 and p.reliable_every == 100 and p.reliable_delta == 0.1
+    assert p.use_graph == 0 and p.ru_restart == -1
 
 
 def _create(dims, phases=(1, 0, 1, 0, 1, 0, -1, 0), gauge=True):

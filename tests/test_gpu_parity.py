@@ -8,6 +8,7 @@ Tolerances (relative, normwise over the whole output field):
   FP16 + site norm  4e-3   (unit roundoff 2^-11 = 4.9e-4 on inputs scaled by
                             the per-site maximum, same accumulation depth)
   BF16 + site norm  3e-2   (unit roundoff 2^-8 = 3.9e-3)
+  int16 + site norm 3e-4   (fixed point: half a step of 2^-15 of the site maximum)
 """
 
 import numpy as np
@@ -19,7 +20,7 @@ from paper_1405_0700_amd import wilson as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {W.WL_F64: 1e-13, W.WL_F32: 2e-6, W.WL_F16N: 4e-3, W.WL_BF16N: 3e-2}
+TOL = {W.WL_F64: 1e-13, W.WL_F32: 2e-6, W.WL_F16N: 4e-3, W.WL_BF16N: 3e-2, W.WL_I16N: 3e-4}
 AP = (1, 1, 1, -1)
 
 
@@ -125,7 +126,8 @@ def test_dslash_f64_all_subsets(dims, dagger, recon):
     assert rel(lat.unpack(oo, W.WL_ODD), wo) < TOL[W.WL_F64]
 
 
-@pytest.mark.parametrize("prec,recon", [(W.WL_F32, 18), (W.WL_F32, 12), (W.WL_F16N, 12), (W.WL_BF16N, 12)])
+@pytest.mark.parametrize("prec,recon", [(W.WL_F32, 18), (W.WL_F32, 12), (W.WL_F16N, 12), (W.WL_BF16N, 12),
+                                        (W.WL_I16N, 12)])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_dslash_low_precision(prec, recon, dagger):
     dims = (6, 10, 4, 14)

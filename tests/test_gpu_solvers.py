@@ -51,7 +51,21 @@ def oracle_normal_resid(u, kappa, x_e, rhs):
 
 
 # ------------------------------------------------------------------ mixed precision
-@pytest.mark.parametrize("prec,recon", [(W.WL_F32, 18), (W.WL_F32, 12), (W.WL_F16N, 12), (W.WL_BF16N, 12)])
+def test_fixed_point_storage_roundtrip_error():
+    dims = (4, 4, 4, 4)
+    _, lat = lattice(dims, 0.5, 7)
+    f = synth.gaussian_spinor(dims, seed=5)
+    f[0, 0, 0, 0] = 0
+    back = lat.unpack(lat.pack(f, W.WL_FULL, W.WL_I16N), W.WL_FULL, W.WL_I16N).reshape(f.shape)
+    assert np.all(back[0, 0, 0, 0] == 0)
+    smax = np.max(np.maximum(np.abs(f.real), np.abs(f.imag)), axis=(-1, -2), keepdims=True)
+    err = np.maximum(np.abs((back - f).real), np.abs((back - f).imag))
+    # half a fixed-point step of the site maximum (plus FP32 rounding of the scale)
+    assert np.all(err <= smax * (0.5 / 32767) * 1.001 + smax * 2e-7)
+
+
+@pytest.mark.parametrize("prec,recon", [(W.WL_F32, 18), (W.WL_F32, 12), (W.WL_F16N, 12), (W.WL_BF16N, 12),
+                                        (W.WL_I16N, 12)])
 def test_mixed_precision_cg_reaches_fp64_tolerance(prec, recon):
     dims = (8, 8, 8, 16)
     kappa = 0.135

@@ -85,6 +85,7 @@ typedef enum { WL_EVEN = 0, WL_ODD = 1, WL_FULL = 2 } wl_subset;
 typedef enum { WL_OP_D = 0, WL_OP_DHAT = 1 } wl_op;
 
 typedef struct wl_ctx wl_ctx;
+typedef struct wl_ptc wl_ptc; /* learned preconditioner (see below) */
 
 /* ---------------------------------------------------------------- context */
 
@@ -216,6 +217,8 @@ typedef struct {
     double rel_resid;     /* final iterated relative residual          */
     double true_rel_resid;/* final ||b - A x|| / ||b|| recomputed in FP64 */
     double seconds;       /* wall time of the solve                    */
+    int fallback;         /* FGCR: 1 if it handed over to plain FP64 CG */
+    int fallback_iters;   /* FGCR: iterations of that CG                */
 } wl_solver_info;
 
 /* Fill in defaults: tol 1e-10, maxiter 100000, check_every 25, max_restarts 5,
@@ -235,6 +238,86 @@ void wl_solver_params_default(wl_solver_params *p);
  * Synchronous: returns when done.  info may be NULL (else nrhs entries). */
 wl_status wl_cg_solve(wl_ctx *ctx, void *x, const void *b, wl_op op, double kappa, int nrhs,
                       const wl_solver_params *params, wl_solver_info *info, void *stream);
+
+/* Plain FP64 CG for M x = eta with M = D (FULL fields), through the normal
+ * equations D^+ D x = D^+ eta, stopped on the residual of the system itself:
+ * ||eta - D x|| <= tol ||eta|| (recomputed in FP64; the normal-equation
+ * tolerance is tightened and the CG continued until it holds).  params as for
+ * wl_cg_solve; info->iters counts all CG iterations.  Synchronous. */
+wl_status wl_cgnr_solve(wl_ctx *ctx, void *x, const void *eta, double kappa, const wl_solver_params *params,
+                        wl_solver_info *info, void *stream);
+
+/* Flexible GCR with restarts, right-preconditioned by the PTC network.
+ * One cycle keeps up to `restart` search directions: z = M(r), w = D z,
+ * w and z modified-Gram-Schmidt orthogonalised against the kept pairs,
+ * alpha = <w, r> / <w, w>, x += alpha z, r -= alpha w (FP32 fields and FP32
+ * arithmetic for D and M, FP64 dot products).  After each cycle the correction
+ * is added to the FP64 solution and the residual recomputed in FP64.  Breakdown,
+ * non-finite values, two cycles that reduce ||r|| by less than `stagnation`,
+ * or maxiter hand the solve to plain FP64 CG (wl_cgnr_solve) if `fallback`. */
+typedef struct {
+    double tol;        /* stop when ||b - D x|| <= tol ||b||                       */
+    int maxiter;       /* preconditioned iterations before giving up              */
+    int restart;       /* search directions kept per cycle, 1..64                 */
+    int fallback;      /* finish with plain FP64 CG on failure                    */
+    double stagnation; /* a cycle must reduce ||r|| below this factor             */
+} wl_fgcr_params;
+
+/* tol 1e-10, maxiter 5000, restart 16, fallback 1, stagnation 0.999 */
+void wl_fgcr_params_default(wl_fgcr_params *p);
+
+/* Solve D x = b (FULL FP64 fields; x in: initial guess, out: solution) with
+ * net == NULL meaning no preconditioner (M = 1).  Synchronous. */
+wl_status wl_fgcr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, const wl_ptc *net,
+                        const wl_fgcr_params *params, wl_solver_info *info, void *stream);
+
+/* ---------------------------------------------------------------- learned preconditioner */
+
+/* Parallel-transport convolution (PTC) network, two linear layers without
+ * bias, 1 -> C -> 1 channels (C <= 16):
+ *   out[a](x) = sum_b sum_p W_p^{ab} (T_p in[b])(x),
+ * nine paths p: p = 0 the identity, p = 1 + 2 mu the transport
+ * U_mu(x) psi(x + mu), p = 2 + 2 mu the transport U_mu(x - mu)^+ psi(x - mu),
+ * with the same boundary phases as the Wilson operator; W_p^{ab} are complex
+ * 4x4 spin matrices.  Weights: layer 1 (9, C, 1, 4, 4), layer 2 (9, 1, C, 4, 4)
+ * complex, row-major, (re, im) interleaved.  The network keeps FP32 master
+ * weights (optimised by Adam) and a BF16 copy that its kernels read; fields
+ * are FULL FP32 internal fields; arithmetic is FP32. */
+/* Create a network from host FP64 weights (copied to the device). Synchronous. */
+wl_status wl_ptc_create(int channels, const double *w1, const double *w2, wl_ptc **out);
+wl_status wl_ptc_destroy(wl_ptc *net);
+/* FP32 master weights / accumulated gradients dL/dW* to host FP64 arrays
+ * (either pointer may be NULL).  Synchronous. */
+wl_status wl_ptc_get_weights(const wl_ptc *net, double *w1, double *w2);
+wl_status wl_ptc_get_grads(const wl_ptc *net, double *g1, double *g2);
+
+/* out = M(in): the two layers with the BF16 weights (1-channel FULL FP32 fields). */
+wl_status wl_ptc_apply(wl_ctx *ctx, const wl_ptc *net, void *out, const void *in, void *stream);
+
+/* One layer with explicit FP32 device weights `weights` of shape
+ * (9, cout_f, cin_f, 4, 4): adjoint == 0 computes out (cout channels) from in
+ * (cin channels) with cout_f = cout, cin_f = cin; adjoint != 0 applies the
+ * adjoint map g_in[b] = sum_a sum_p T_p^+ W_p^{ab +} g_out[a] of the layer with
+ * cout_f = cin, cin_f = cout.  cout * cin <= 16. */
+wl_status wl_ptc_layer(wl_ctx *ctx, void *out, const void *in, const float *weights, int cout, int cin,
+                       int adjoint, void *stream);
+
+/* grad (device, complex double, shape (9, cout, cin, 4, 4)) = (or +=, if
+ * accumulate) dL/d conj(W) = sum_x sum_colour g_out[a](x) (T_p in[b])(x)^+ for a
+ * layer with input `in` (cin channels) and output gradient g_out (cout). */
+wl_status wl_ptc_weight_grad(wl_ctx *ctx, double *grad, const void *g_out, const void *in, int cout, int cin,
+                             int accumulate, void *stream);
+
+/* Training: for one (residual r, error e) pair on this context's gauge field,
+ * add inv_npairs * ||M(r) - e||^2 / ||e||^2 to the network's loss and its
+ * gradient to the network's gradient accumulators (forward, loss and backward
+ * kernels; nothing leaves the device). */
+wl_status wl_ptc_accumulate(wl_ctx *ctx, wl_ptc *net, const void *r, const void *e, double inv_npairs,
+                            void *stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, learning rate lr) with the
+ * accumulated gradients; returns the accumulated loss in *loss (may be NULL)
+ * and clears both.  Synchronises the stream. */
+wl_status wl_ptc_step(wl_ptc *net, double lr, double *loss, void *stream);
 
 /* ---------------------------------------------------------------- kernel timing */
 

@@ -16,6 +16,7 @@
 #include "wilson.h"
 #include "wl_blas.h"
 #include "wl_dslash.h"
+#include "wl_ptc.h"
 
 using namespace wl;
 
@@ -45,6 +46,8 @@ enum Slot {
     S_R, S_P, S_Q, S_S, S_TMP,           // solver fields in the inner precision
     S_RHI, S_THI, S_TMPHI,               // FP64 fields for true residuals
     S_PARTIALS, S_SCAL, S_BNORM, S_FLAG,
+    S_PTC_H, S_PTC_GH, S_PTC_O, S_PTC_GO, S_PTC_PART, S_PTC_E2,       // PTC workspace
+    S_GCR_R, S_GCR_X, S_GCR_Z, S_GCR_W, S_GCR_TMP, S_GCR_RHS,          // FGCR workspace
     S_NSLOTS
 };
 }
@@ -1142,4 +1145,513 @@ extern "C" wl_status wl_ctx_get_launch(const wl_ctx *c, wl_prec prec, wl_launch 
     l->tchunk = g.tchunk;
     l->nt = g.nt;
     return WL_OK;
+}
+
+// ------------------------------------------------------------------ PTC preconditioner
+struct wl_ptc {
+    int channels;
+    long n1, n2;          // complex weights of layer 1 (9 x C x 1 x 16) and layer 2 (9 x 1 x C x 16)
+    float *w = nullptr;   // FP32 master weights, layer 1 then layer 2, (re, im) interleaved
+    uint16_t *wb = nullptr;  // BF16 copy used by the kernels
+    double *grad = nullptr;  // dL/dW* accumulated, complex (re, im)
+    float *m = nullptr, *v = nullptr;  // Adam moments per real parameter
+    double *loss = nullptr;  // accumulated loss (device)
+    int t = 0;               // Adam steps taken
+};
+
+extern "C" wl_status wl_ptc_create(int channels, const double *w1, const double *w2, wl_ptc **out) {
+    g_err.clear();
+    if (!w1 || !w2 || !out) return fail(WL_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (channels < 1 || channels > PTC_MAXC) return fail(WL_ERR_ARG, "channels %d not in [1, %d]", channels, PTC_MAXC);
+    wl_ptc *n = new wl_ptc();
+    n->channels = channels;
+    n->n1 = (long)PTC_NPATH * channels * 16;
+    n->n2 = n->n1;
+    const long nr = 2 * (n->n1 + n->n2);  // real parameters
+    std::vector<float> host(nr);
+    for (long k = 0; k < 2 * n->n1; ++k) host[k] = (float)w1[k];
+    for (long k = 0; k < 2 * n->n2; ++k) host[2 * n->n1 + k] = (float)w2[k];
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&n->w, nr * sizeof(float))) != hipSuccess || (e = hipMalloc(&n->wb, nr * sizeof(uint16_t))) != hipSuccess ||
+        (e = hipMalloc(&n->grad, nr * sizeof(double))) != hipSuccess || (e = hipMalloc(&n->m, nr * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&n->v, nr * sizeof(float))) != hipSuccess || (e = hipMalloc(&n->loss, sizeof(double))) != hipSuccess) {
+        (void)hipGetLastError();
+        wl_ptc_destroy(n);
+        return fail(WL_ERR_NOMEM, "hipMalloc of PTC weights failed: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpy(n->w, host.data(), nr * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(n->grad, 0, nr * sizeof(double)));
+    HIP_TRY(hipMemset(n->m, 0, nr * sizeof(float)));
+    HIP_TRY(hipMemset(n->v, 0, nr * sizeof(float)));
+    HIP_TRY(hipMemset(n->loss, 0, sizeof(double)));
+    HIP_TRY(launch_to_bf16(n->w, n->wb, nr, 0));
+    HIP_TRY(hipDeviceSynchronize());
+    *out = n;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ptc_destroy(wl_ptc *n) {
+    if (!n) return WL_OK;
+    (void)hipDeviceSynchronize();
+    if (n->w) (void)hipFree(n->w);
+    if (n->wb) (void)hipFree(n->wb);
+    if (n->grad) (void)hipFree(n->grad);
+    if (n->m) (void)hipFree(n->m);
+    if (n->v) (void)hipFree(n->v);
+    if (n->loss) (void)hipFree(n->loss);
+    delete n;
+    return WL_OK;
+}
+
+static wl_status ptc_download(const wl_ptc *n, const void *src, bool is_double, double *w1, double *w2) {
+    const long nr = 2 * (n->n1 + n->n2);
+    std::vector<double> h(nr);
+    if (is_double) {
+        HIP_TRY(hipMemcpy(h.data(), src, nr * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> f(nr);
+        HIP_TRY(hipMemcpy(f.data(), src, nr * sizeof(float), hipMemcpyDeviceToHost));
+        for (long k = 0; k < nr; ++k) h[k] = f[k];
+    }
+    if (w1) std::memcpy(w1, h.data(), 2 * n->n1 * sizeof(double));
+    if (w2) std::memcpy(w2, h.data() + 2 * n->n1, 2 * n->n2 * sizeof(double));
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ptc_get_weights(const wl_ptc *n, double *w1, double *w2) {
+    g_err.clear();
+    if (!n) return fail(WL_ERR_ARG, "null network");
+    HIP_TRY(hipDeviceSynchronize());
+    return ptc_download(n, n->w, false, w1, w2);
+}
+
+extern "C" wl_status wl_ptc_get_grads(const wl_ptc *n, double *g1, double *g2) {
+    g_err.clear();
+    if (!n) return fail(WL_ERR_ARG, "null network");
+    HIP_TRY(hipDeviceSynchronize());
+    return ptc_download(n, n->grad, true, g1, g2);
+}
+
+static PtcArgs ptc_args(wl_ctx *c, void *out, const void *in, int cout, int cin, const void *w, int adjoint,
+                        wl_status *st) {
+    PtcArgs a;
+    std::memset(&a, 0, sizeof a);
+    const void *gauge = nullptr;
+    size_t slab = 0;
+    *st = get_links(c, WL_F32, 18, &gauge, &slab);
+    a.g = c->g;
+    const size_t ho = half_bytes(c, WL_F32, cout), hi = half_bytes(c, WL_F32, cin);
+    a.out[0] = out;
+    a.out[1] = (char *)out + ho;
+    a.in[0] = in;
+    a.in[1] = (const char *)in + hi;
+    a.gauge = gauge;
+    a.slab_bytes = slab;
+    a.w = w;
+    a.cout = cout;
+    a.cin = cin;
+    a.adjoint = adjoint;
+    a.vh = c->Vh;
+    return a;
+}
+
+// out = M(in) = layer2(layer1(in)) with the BF16 weights; the hidden field is
+// returned in `hidden` (channels C)
+static wl_status ptc_forward(wl_ctx *c, const wl_ptc *n, void *out, const void *in, void *hidden, hipStream_t s) {
+    wl_status st;
+    PtcArgs a1 = ptc_args(c, hidden, in, n->channels, 1, n->wb, 0, &st);
+    if (st) return st;
+    HIP_TRY(launch_ptc_layer(a1, true, s));
+    PtcArgs a2 = ptc_args(c, out, hidden, 1, n->channels, n->wb + 2 * n->n1, 0, &st);
+    if (st) return st;
+    HIP_TRY(launch_ptc_layer(a2, true, s));
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ptc_apply(wl_ctx *c, const wl_ptc *n, void *out, const void *in, void *stream) {
+    g_err.clear();
+    if (!c || !n || !out || !in || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned argument");
+    const size_t hb = half_bytes(c, WL_F32, 1);
+    if (overlap(out, 2 * hb, in, 2 * hb)) return fail(WL_ERR_ARG, "out and in overlap");
+    wl_status st = ensure_buf(c, S_PTC_H, 2 * half_bytes(c, WL_F32, n->channels));
+    if (st) return st;
+    return ptc_forward(c, n, out, in, c->buf[S_PTC_H], (hipStream_t)stream);
+}
+
+extern "C" wl_status wl_ptc_layer(wl_ctx *c, void *out, const void *in, const float *weights, int cout, int cin,
+                                  int adjoint, void *stream) {
+    g_err.clear();
+    if (!c || !out || !in || !weights || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned argument");
+    if (cout < 1 || cin < 1 || cout * cin > PTC_MAXC) return fail(WL_ERR_ARG, "channels %d x %d exceed %d", cout, cin, PTC_MAXC);
+    if (overlap(out, 2 * half_bytes(c, WL_F32, cout), in, 2 * half_bytes(c, WL_F32, cin)))
+        return fail(WL_ERR_ARG, "out and in overlap");
+    wl_status st;
+    PtcArgs a = ptc_args(c, out, in, cout, cin, weights, adjoint ? 1 : 0, &st);
+    if (st) return st;
+    HIP_TRY(launch_ptc_layer(a, false, (hipStream_t)stream));
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ptc_weight_grad(wl_ctx *c, double *grad, const void *gout, const void *in, int cout, int cin,
+                                        int accumulate, void *stream) {
+    g_err.clear();
+    if (!c || !grad || !gout || !in) return fail(WL_ERR_ARG, "null argument");
+    if (cout < 1 || cin < 1 || cout * cin > PTC_MAXC) return fail(WL_ERR_ARG, "bad channel counts");
+    const int ncombo = PTC_NPATH * cout * cin;
+    const int nchunks = std::max(1, std::min(64, (int)(2048 / ncombo)));
+    wl_status st = ensure_buf(c, S_PTC_PART, sizeof(float) * 32 * (size_t)ncombo * nchunks);
+    if (st) return st;
+    const void *gauge;
+    size_t slab;
+    if ((st = get_links(c, WL_F32, 18, &gauge, &slab))) return st;
+    PtcGradArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.g = c->g;
+    const size_t ho = half_bytes(c, WL_F32, cout), hi = half_bytes(c, WL_F32, cin);
+    a.gout[0] = gout;
+    a.gout[1] = (const char *)gout + ho;
+    a.in[0] = in;
+    a.in[1] = (const char *)in + hi;
+    a.gauge = gauge;
+    a.slab_bytes = slab;
+    a.cout = cout;
+    a.cin = cin;
+    a.vh = c->Vh;
+    a.partials = (float *)c->buf[S_PTC_PART];
+    a.nchunks = nchunks;
+    HIP_TRY(launch_ptc_wgrad(a, grad, accumulate, (hipStream_t)stream));
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ptc_accumulate(wl_ctx *c, wl_ptc *n, const void *r, const void *e, double inv_npairs,
+                                       void *stream) {
+    g_err.clear();
+    if (!c || !n || !r || !e || !aligned16(r) || !aligned16(e)) return fail(WL_ERR_ARG, "null or misaligned argument");
+    if (!(inv_npairs > 0.0) || !std::isfinite(inv_npairs)) return fail(WL_ERR_ARG, "bad pair weight");
+    hipStream_t s = (hipStream_t)stream;
+    const int C = n->channels;
+    const size_t h1 = half_bytes(c, WL_F32, 1), hc = half_bytes(c, WL_F32, C);
+    const long stride = part_stride_for(c, 1);
+    wl_status st;
+    if ((st = ensure_buf(c, S_PTC_H, 2 * hc)) || (st = ensure_buf(c, S_PTC_GH, 2 * hc)) ||
+        (st = ensure_buf(c, S_PTC_O, 2 * h1)) || (st = ensure_buf(c, S_PTC_GO, 2 * h1)) ||
+        (st = ensure_buf(c, S_PTC_E2, sizeof(double) * 2)) ||
+        (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * stride)))
+        return st;
+    void *h = c->buf[S_PTC_H], *gh = c->buf[S_PTC_GH], *o = c->buf[S_PTC_O], *go = c->buf[S_PTC_GO];
+    double *e2 = (double *)c->buf[S_PTC_E2];
+    double *partials = (double *)c->buf[S_PARTIALS];
+    // forward
+    if ((st = ptc_forward(c, n, o, r, h, s))) return st;
+    // ||e||^2 on the device
+    VecArgs v = vec_args(c, WL_F32, 1);
+    set_vec(v, 0, e, h1);
+    v.partials = partials;
+    v.part_stride = stride;
+    HIP_TRY(blas_norm2(WL_F32, v, 2, s));
+    HIP_TRY(reduce_partials(partials, stride, blas_blocks(v.n) * 2, 1, e2, s));
+    // loss and dL/d conj(out)
+    HIP_TRY(launch_ptc_loss(o, e, go, c->Vh, e2, inv_npairs, partials, stride, n->loss, s));
+    // layer 2: weight gradient, then dL/d conj(hidden) through its adjoint
+    double *g1 = n->grad, *g2 = n->grad + 2 * n->n1;
+    if ((st = wl_ptc_weight_grad(c, g2, go, h, 1, C, 1, stream))) return st;
+    PtcArgs a2t = ptc_args(c, gh, go, C, 1, n->wb + 2 * n->n1, 1, &st);
+    if (st) return st;
+    HIP_TRY(launch_ptc_layer(a2t, true, s));
+    // layer 1: weight gradient
+    if ((st = wl_ptc_weight_grad(c, g1, gh, r, C, 1, 1, stream))) return st;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_ptc_step(wl_ptc *n, double lr, double *loss, void *stream) {
+    g_err.clear();
+    if (!n) return fail(WL_ERR_ARG, "null network");
+    if (!(lr > 0.0) || !std::isfinite(lr)) return fail(WL_ERR_ARG, "bad learning rate");
+    hipStream_t s = (hipStream_t)stream;
+    n->t += 1;
+    HIP_TRY(launch_adam(n->w, n->wb, n->grad, n->m, n->v, 2 * (n->n1 + n->n2), lr, 0.9, 0.999, 1e-8, n->t, s));
+    double l = 0.0;
+    HIP_TRY(hipMemcpyAsync(&l, n->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemsetAsync(n->loss, 0, sizeof(double), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss) *loss = l;
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ FGCR and CGNR
+namespace {
+// host-side scalar helpers for the FGCR driver (FULL fields, one rhs)
+struct Fields {
+    wl_ctx *c;
+    hipStream_t s;
+    long stride;
+};
+}  // namespace
+
+static wl_status dot_full(Fields &F, int prec, const void *x, const void *y, double out[2]) {
+    wl_ctx *c = F.c;
+    VecArgs v = vec_args(c, prec, 1);
+    const size_t hb = half_bytes(c, prec, 1);
+    set_vec(v, 0, x, hb);
+    set_vec(v, 1, y, hb);
+    v.partials = (double *)c->buf[S_PARTIALS];
+    v.part_stride = F.stride;
+    HIP_TRY(blas_dot(prec, v, 2, F.s));
+    return reduce_to_host(c, 2, F.stride, blas_blocks(v.n) * 2, out, F.s);
+}
+
+static wl_status norm_full(Fields &F, int prec, const void *x, double *out) {
+    wl_ctx *c = F.c;
+    VecArgs v = vec_args(c, prec, 1);
+    set_vec(v, 0, x, half_bytes(c, prec, 1));
+    v.partials = (double *)c->buf[S_PARTIALS];
+    v.part_stride = F.stride;
+    HIP_TRY(blas_norm2(prec, v, 2, F.s));
+    return reduce_to_host(c, 1, F.stride, blas_blocks(v.n) * 2, out, F.s);
+}
+
+static wl_status caxpy_full(Fields &F, int prec, double ar, double ai, const void *x, void *y) {
+    VecArgs v = vec_args(F.c, prec, 1);
+    const size_t hb = half_bytes(F.c, prec, 1);
+    set_vec(v, 0, x, hb);
+    set_vec(v, 1, y, hb);
+    v.a = ar;
+    v.b = ai;
+    HIP_TRY(blas_caxpy(prec, v, 2, F.s));
+    return WL_OK;
+}
+
+// r = b - D x in FP64 (t: FP64 FULL temporary); *rn2 = ||r||^2
+static wl_status system_residual(Fields &F, double kappa, const void *x, const void *b, void *r, void *t, double *rn2) {
+    wl_ctx *c = F.c;
+    wl_status st = apply_m(c, WL_OP_D, false, kappa, WL_F64, 18, 1, t, x, nullptr, nullptr, 0, nullptr, F.s, nullptr);
+    if (st) return st;
+    VecArgs v = vec_args(c, WL_F64, 1);
+    const size_t hb = half_bytes(c, WL_F64, 1);
+    set_vec(v, 0, b, hb);
+    set_vec(v, 1, t, hb);
+    set_vec(v, 2, r, hb);
+    v.partials = (double *)c->buf[S_PARTIALS];
+    v.part_stride = F.stride;
+    HIP_TRY(blas_residual(WL_F64, v, 2, F.s));
+    return reduce_to_host(c, 1, F.stride, blas_blocks(v.n) * 2, rn2, F.s);
+}
+
+extern "C" void wl_fgcr_params_default(wl_fgcr_params *p) {
+    if (!p) return;
+    p->tol = 1e-10;
+    p->maxiter = 5000;
+    p->restart = 16;
+    p->fallback = 1;
+    p->stagnation = 0.999;
+}
+
+extern "C" wl_status wl_cgnr_solve(wl_ctx *c, void *x, const void *eta, double kappa, const wl_solver_params *params,
+                                   wl_solver_info *info, void *stream) {
+    g_err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    wl_status st = check_field_args(c, WL_FULL, WL_F64, 1);
+    if (st) return st;
+    if (!x || !eta || !aligned16(x) || !aligned16(eta)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    wl_solver_params P;
+    wl_solver_params_default(&P);
+    if (params) P = *params;
+    if (!(P.tol > 0.0)) return fail(WL_ERR_ARG, "tolerance must be positive");
+    Fields F{c, (hipStream_t)stream, part_stride_for(c, 1)};
+    const size_t full = 2 * half_bytes(c, WL_F64, 1);
+    if (overlap(x, full, eta, full)) return fail(WL_ERR_ARG, "x and eta overlap");
+    if ((st = ensure_buf(c, S_GCR_R, full)) || (st = ensure_buf(c, S_GCR_TMP, full)) ||
+        (st = ensure_buf(c, S_GCR_RHS, full)) || (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * F.stride)))
+        return st;
+    // rhs = D^+ eta
+    if ((st = apply_m(c, WL_OP_D, true, kappa, WL_F64, 18, 1, c->buf[S_GCR_RHS], eta, nullptr, nullptr, 0, nullptr, F.s,
+                      nullptr)))
+        return st;
+    double e2 = 0.0;
+    if ((st = norm_full(F, WL_F64, eta, &e2))) return st;
+    wl_solver_info acc{};
+    double tol_n = P.tol;
+    wl_status result = WL_NOT_CONVERGED;
+    int rounds = 0;
+    double rel = 0.0;
+    for (;;) {
+        wl_solver_params Q = P;
+        Q.tol = tol_n;
+        Q.maxiter = P.maxiter - acc.iters;
+        wl_solver_info inf{};
+        wl_status cs = wl_cg_solve(c, x, c->buf[S_GCR_RHS], WL_OP_D, kappa, 1, &Q, &inf, stream);
+        if (cs < 0) return cs;
+        acc.iters += inf.iters;
+        acc.reliable_updates += inf.reliable_updates;
+        acc.restarts += inf.restarts;
+        double r2 = 0.0;
+        if ((st = system_residual(F, kappa, x, eta, c->buf[S_GCR_R], c->buf[S_GCR_TMP], &r2))) return st;
+        rel = e2 > 0 ? std::sqrt(r2 / e2) : 0.0;
+        ++rounds;
+        if (rel <= P.tol) {
+            result = WL_OK;
+            break;
+        }
+        if (cs == WL_BREAKDOWN) {
+            result = WL_BREAKDOWN;
+            break;
+        }
+        if (acc.iters >= P.maxiter || rounds > 8) break;
+        // the normal-equation residual was met but the system residual was not: tighten
+        tol_n *= std::max(1e-3, std::min(0.5, 0.5 * P.tol / rel));
+    }
+    acc.rel_resid = rel;
+    acc.true_rel_resid = rel;
+    acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = acc;
+    if (result == WL_NOT_CONVERGED) fail(WL_NOT_CONVERGED, "CGNR did not reach the system tolerance");
+    return result;
+}
+
+extern "C" wl_status wl_fgcr_solve(wl_ctx *c, void *x, const void *b, double kappa, const wl_ptc *net,
+                                   const wl_fgcr_params *params, wl_solver_info *info, void *stream) {
+    g_err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    wl_status st = check_field_args(c, WL_FULL, WL_F64, 1);
+    if (st) return st;
+    if (!x || !b || !aligned16(x) || !aligned16(b)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    wl_fgcr_params P;
+    wl_fgcr_params_default(&P);
+    if (params) P = *params;
+    if (!(P.tol > 0.0) || P.restart < 1 || P.restart > 64 || P.maxiter < 1) return fail(WL_ERR_ARG, "bad FGCR parameters");
+    if (!std::isfinite(kappa)) return fail(WL_ERR_ARG, "non-finite kappa");
+    const int m = P.restart;
+    Fields F{c, (hipStream_t)stream, part_stride_for(c, 1)};
+    const size_t full_hi = 2 * half_bytes(c, WL_F64, 1), full_lo = 2 * half_bytes(c, WL_F32, 1);
+    if (overlap(x, full_hi, b, full_hi)) return fail(WL_ERR_ARG, "x and b overlap");
+    if ((st = ensure_buf(c, S_GCR_R, full_hi)) || (st = ensure_buf(c, S_GCR_TMP, full_hi)) ||
+        (st = ensure_buf(c, S_GCR_X, 2 * full_lo)) || (st = ensure_buf(c, S_GCR_Z, (size_t)m * full_lo)) ||
+        (st = ensure_buf(c, S_GCR_W, (size_t)m * full_lo)) ||
+        (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * F.stride)))
+        return st;
+    if (net && (st = ensure_buf(c, S_PTC_H, 2 * half_bytes(c, WL_F32, net->channels)))) return st;
+    char *rlo = (char *)c->buf[S_GCR_X], *xc = rlo + full_lo;
+    char *Z = (char *)c->buf[S_GCR_Z], *Wv = (char *)c->buf[S_GCR_W];
+    void *rhi = c->buf[S_GCR_R], *thi = c->buf[S_GCR_TMP];
+    double b2 = 0.0;
+    if ((st = norm_full(F, WL_F64, b, &b2))) return st;
+    wl_solver_info out{};
+    if (!(b2 > 0.0)) {
+        VecArgs v = vec_args(c, WL_F64, 1);
+        set_vec(v, 0, x, half_bytes(c, WL_F64, 1));
+        HIP_TRY(blas_zero(WL_F64, v, 2, F.s));
+        HIP_TRY(hipStreamSynchronize(F.s));
+        if (info) *info = out;
+        return WL_OK;
+    }
+    double rn2 = 0.0;
+    if ((st = system_residual(F, kappa, x, b, rhi, thi, &rn2))) return st;
+    const double target2 = P.tol * P.tol * b2;
+    int total = 0, cycles = 0, stagnant = 0;
+    bool failed = false;
+    std::vector<double> ww(m);
+    double rlo2 = rn2;
+    while (rn2 > target2) {
+        if (total >= P.maxiter || !std::isfinite(rn2)) {
+            failed = true;
+            break;
+        }
+        // inner cycle in FP32 on the correction: D e = r
+        {
+            VecArgs v = vec_args(c, WL_F32, 1);
+            const size_t hb = half_bytes(c, WL_F32, 1);
+            set_vec(v, 0, rhi, half_bytes(c, WL_F64, 1));
+            set_vec(v, 1, rlo, hb);
+            HIP_TRY(blas_convert(WL_F32, WL_F64, false, v, 2, F.s));
+            set_vec(v, 0, xc, hb);
+            HIP_TRY(blas_zero(WL_F32, v, 2, F.s));
+        }
+        bool breakdown = false;
+        for (int k = 0; k < m && total < P.maxiter; ++k) {
+            void *zk = Z + (size_t)k * full_lo, *wk = Wv + (size_t)k * full_lo;
+            if (net) {
+                if ((st = ptc_forward(c, net, zk, rlo, c->buf[S_PTC_H], F.s))) return st;
+            } else {
+                VecArgs v = vec_args(c, WL_F32, 1);
+                const size_t hb = half_bytes(c, WL_F32, 1);
+                set_vec(v, 0, rlo, hb);
+                set_vec(v, 1, zk, hb);
+                HIP_TRY(blas_convert(WL_F32, WL_F32, false, v, 2, F.s));
+            }
+            if ((st = apply_m(c, WL_OP_D, false, kappa, WL_F32, 18, 1, wk, zk, nullptr, nullptr, 0, nullptr, F.s, nullptr)))
+                return st;
+            // modified Gram-Schmidt of w_k against the kept w_j (same combination on z_k)
+            for (int j = 0; j < k; ++j) {
+                void *zj = Z + (size_t)j * full_lo, *wj = Wv + (size_t)j * full_lo;
+                double d[2];
+                if ((st = dot_full(F, WL_F32, wj, wk, d))) return st;
+                const double br = d[0] / ww[j], bi = d[1] / ww[j];
+                if ((st = caxpy_full(F, WL_F32, -br, -bi, wj, wk)) || (st = caxpy_full(F, WL_F32, -br, -bi, zj, zk)))
+                    return st;
+            }
+            if ((st = norm_full(F, WL_F32, wk, &ww[k]))) return st;
+            if (!(ww[k] > 0.0) || !std::isfinite(ww[k])) {
+                breakdown = true;
+                break;
+            }
+            double d[2];
+            if ((st = dot_full(F, WL_F32, wk, rlo, d))) return st;
+            const double ar = d[0] / ww[k], ai = d[1] / ww[k];
+            if ((st = caxpy_full(F, WL_F32, ar, ai, zk, xc)) || (st = caxpy_full(F, WL_F32, -ar, -ai, wk, rlo))) return st;
+            if ((st = norm_full(F, WL_F32, rlo, &rlo2))) return st;
+            ++total;
+            if (!std::isfinite(rlo2)) {
+                breakdown = true;
+                break;
+            }
+            // the FP32 iterated residual cannot certify the tolerance: leave the
+            // cycle a little below it and let the FP64 residual decide
+            if (rlo2 <= 0.25 * target2) break;
+        }
+        // x += correction (FP64), then the FP64 residual
+        {
+            VecArgs v = vec_args(c, WL_F64, 1);
+            set_vec(v, 0, xc, half_bytes(c, WL_F32, 1));
+            set_vec(v, 1, x, half_bytes(c, WL_F64, 1));
+            HIP_TRY(blas_convert(WL_F64, WL_F32, true, v, 2, F.s));
+        }
+        double prev = rn2;
+        if ((st = system_residual(F, kappa, x, b, rhi, thi, &rn2))) return st;
+        ++cycles;
+        if (breakdown || !std::isfinite(rn2)) {
+            failed = true;
+            break;
+        }
+        if (rn2 > P.stagnation * P.stagnation * prev) {
+            if (++stagnant >= 2) {
+                failed = true;
+                break;
+            }
+        } else {
+            stagnant = 0;
+        }
+    }
+    out.iters = total;
+    out.restarts = cycles;
+    out.rel_resid = std::sqrt(rlo2 / b2);
+    out.true_rel_resid = std::sqrt(rn2 / b2);
+    wl_status result = failed ? WL_NOT_CONVERGED : WL_OK;
+    if (failed && P.fallback) {
+        // plain FP64 CG on the normal equations, from the current x, judged on the same system residual
+        wl_solver_params Q;
+        wl_solver_params_default(&Q);
+        Q.tol = P.tol;
+        wl_solver_info fi{};
+        wl_status fs = wl_cgnr_solve(c, x, b, kappa, &Q, &fi, stream);
+        if (fs < 0) return fs;
+        out.fallback = 1;
+        out.fallback_iters = fi.iters;
+        out.true_rel_resid = fi.true_rel_resid;
+        result = fs;
+    }
+    out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = out;
+    if (result == WL_NOT_CONVERGED) fail(WL_NOT_CONVERGED, "FGCR did not reach the tolerance");
+    return result;
 }

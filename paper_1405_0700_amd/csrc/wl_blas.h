@@ -43,6 +43,8 @@ hipError_t cg_update_xr(int prec, int xprec, VecArgs &a, int nhalves, hipStream_
 hipError_t cg_update_p(int prec, VecArgs &a, int nhalves, hipStream_t s);
 // v1 (prec dprec) = v0 (prec sprec), or v1 += v0 if accumulate
 hipError_t blas_convert(int dprec, int sprec, bool accumulate, VecArgs &a, int nhalves, hipStream_t s);
+// v1 += (a + i b) v0
+hipError_t blas_caxpy(int prec, VecArgs &a, int nhalves, hipStream_t s);
 // r = b - v  (v2 = r output, v0 = b, v1 = v), ||r||^2 partials: used for true residuals
 hipError_t blas_residual(int prec, VecArgs &a, int nhalves, hipStream_t s);
 

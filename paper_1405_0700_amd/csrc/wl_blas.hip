@@ -174,6 +174,24 @@ __global__ void __launch_bounds__(256) k_convert(const VecArgs a) {
     }
 }
 
+// y += (a + i b) x  (complex scalar, real a/b in the args)
+template <int SP>
+__global__ void __launch_bounds__(256) k_caxpy(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < a.n) {
+        cpx<T> x[12], y[12];
+        SpinorIO<SP>::load(a.v[0][h], gid, x);
+        SpinorIO<SP>::load(a.v[1][h], gid, y);
+        const cpx<T> s = {(T)a.a, (T)a.b};
+#pragma unroll
+        for (int k = 0; k < 12; ++k) y[k] = cfma(s, x[k], y[k]);
+        SpinorIO<SP>::store(a.v[1][h], gid, y);
+    }
+}
+
 // r = b - v, partial ||r||^2
 template <int SP>
 __global__ void __launch_bounds__(256) k_residual(const VecArgs a) {
@@ -361,6 +379,10 @@ hipError_t cg_update_xr(int prec, int xprec, VecArgs &a, int nh, hipStream_t s) 
 hipError_t cg_update_p(int prec, VecArgs &a, int nh, hipStream_t s) {
     dim3 grid = vgrid(a, nh);
     WL_DISPATCH_PREC(prec, k_cg_p)
+}
+hipError_t blas_caxpy(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_caxpy)
 }
 hipError_t blas_residual(int prec, VecArgs &a, int nh, hipStream_t s) {
     dim3 grid = vgrid(a, nh);

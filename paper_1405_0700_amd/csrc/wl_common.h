@@ -339,7 +339,7 @@ template <> struct LinkIO<WL_I16N, 12> : LinkIO16<WL_I16N> {};
 
 // host-side sizes: a field of n points (or a slab of n links) occupies
 // ceil(n / 64) blocks
-inline long padded(long n) { return (n + 63) / 64 * 64; }
+__host__ __device__ inline long padded(long n) { return (n + 63) / 64 * 64; }
 inline size_t spinor_point_bytes(int prec) {
     switch (prec) {
     case WL_F64: return 192;

@@ -1,0 +1,60 @@
+// Kernels of the parallel-transport convolution (PTC) preconditioner.
+#pragma once
+
+#include "wl_common.h"
+
+namespace wl {
+
+constexpr int PTC_NPATH = 9;
+constexpr int PTC_MAXC = 16;  // most channels of a layer
+
+// One PTC layer on FULL FP32 fields whose points are (site, channel), channel
+// fastest:  out[a](x) = sum_b sum_p W_p^{ab} (T_p in[b])(x),  or its adjoint
+// g_in[b] = sum_a sum_p T_p^+ W_p^{ab +} g_out[a]  (adjoint != 0; then
+// `cout`/`cin` are the channel counts of the adjoint map and the weights keep
+// the layout of the forward layer).
+struct PtcArgs {
+    Geom g;
+    const void *in[2];
+    void *out[2];
+    const void *gauge;  // FP32 18-real links
+    size_t slab_bytes;
+    const void *w;      // [9][cout_f][cin_f][4][4] complex, FP32 or BF16 (re, im interleaved)
+    int cout, cin;      // channels of this launch's output / input
+    int adjoint;
+    long vh;
+};
+
+hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16_weights, hipStream_t s);
+
+// Weight gradient dL/d conj(W_p^{ab}) = sum_x sum_colour g[a](x) (T_p in[b])(x)^+
+// for all (p, a, b): per-chunk FP32 partials, then an FP64 sum over chunks that
+// is stored to (or added to) grad[p][a][b][4][4] (complex double).
+struct PtcGradArgs {
+    Geom g;
+    const void *gout[2];  // cout channels
+    const void *in[2];    // cin channels
+    const void *gauge;
+    size_t slab_bytes;
+    int cout, cin;
+    long vh;
+    float *partials;      // [combo][chunk][32]
+    int nchunks;
+};
+hipError_t launch_ptc_wgrad(const PtcGradArgs &a, double *grad, int accumulate, hipStream_t s);
+
+// Loss of one pair: d = out - e, g = scale * d with scale = inv_n / ||e||^2,
+// loss += scale * ||d||^2 (all on the device).  e2 must hold ||e||^2.
+hipError_t launch_ptc_loss(const void *out, const void *e, void *g, long npts_half, const double *e2,
+                           double inv_n, double *partials, long stride, double *loss, hipStream_t s);
+
+// Adam on n real parameters (complex weights as (re, im)); grad_c is the
+// complex dL/dW* (double), the real-parameter gradient is 2 grad_c.  Writes the
+// FP32 master weights and their BF16 copy, then clears grad_c.
+hipError_t launch_adam(float *w, uint16_t *wb, double *grad_c, float *m, float *v, long n, double lr, double b1,
+                       double b2, double eps, int t, hipStream_t s);
+
+// FP32 -> BF16 copy of n floats
+hipError_t launch_to_bf16(const float *w, uint16_t *wb, long n, hipStream_t s);
+
+}  // namespace wl

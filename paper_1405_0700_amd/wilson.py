@@ -61,10 +61,22 @@ class SolverInfo(ctypes.Structure):
         ("rel_resid", ctypes.c_double),
         ("true_rel_resid", ctypes.c_double),
         ("seconds", ctypes.c_double),
+        ("fallback", ctypes.c_int),
+        ("fallback_iters", ctypes.c_int),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FgcrParams(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int),
+        ("restart", ctypes.c_int),
+        ("fallback", ctypes.c_int),
+        ("stagnation", ctypes.c_double),
+    ]
 
 
 _vp = ctypes.c_void_p
@@ -93,6 +105,20 @@ _SIGS = {
                                    ctypes.POINTER(SolverParams), ctypes.POINTER(SolverInfo), _vp]),
     "wl_ctx_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_void_p]),
     "wl_ctx_get_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_void_p]),
+    "wl_cgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(SolverParams),
+                                     ctypes.POINTER(SolverInfo), _vp]),
+    "wl_fgcr_params_default": (None, [ctypes.POINTER(FgcrParams)]),
+    "wl_fgcr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(FgcrParams),
+                                     ctypes.POINTER(SolverInfo), _vp]),
+    "wl_ptc_create": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.POINTER(_vp)]),
+    "wl_ptc_destroy": (ctypes.c_int, [_vp]),
+    "wl_ptc_get_weights": (ctypes.c_int, [_vp, _dp, _dp]),
+    "wl_ptc_get_grads": (ctypes.c_int, [_vp, _dp, _dp]),
+    "wl_ptc_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "wl_ptc_layer": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_ptc_weight_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_ptc_accumulate": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, _vp]),
+    "wl_ptc_step": (ctypes.c_int, [_vp, ctypes.c_double, _dp, _vp]),
     "wl_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wl_timing_read": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _dp]),
     "wl_last_error": (ctypes.c_char_p, []),
@@ -252,6 +278,88 @@ class Launch(ctypes.Structure):
 
     def as_tuple(self):
         return (self.block, self.swizzle, self.tps, self.tchunk, self.nt)
+
+
+def wl_cgnr_solve(ctx, x, eta, kappa, params: SolverParams | None = None, stream=None):
+    """Plain FP64 CG for D x = eta stopped on ||eta - D x|| <= tol ||eta||. Returns (status, info dict)."""
+    p = params if params is not None else wl_solver_params_default()
+    info = SolverInfo()
+    st = _check(lib().wl_cgnr_solve(ctx, _ptr(x), _ptr(eta), float(kappa), ctypes.byref(p), ctypes.byref(info),
+                                    _stream(stream)))
+    return st, info.as_dict()
+
+
+def wl_fgcr_params_default() -> FgcrParams:
+    p = FgcrParams()
+    lib().wl_fgcr_params_default(ctypes.byref(p))
+    return p
+
+
+def wl_fgcr_solve(ctx, x, b, kappa, net=None, params: FgcrParams | None = None, stream=None):
+    """FGCR on D x = b preconditioned by the PTC network `net` (None: no preconditioner)."""
+    p = params if params is not None else wl_fgcr_params_default()
+    info = SolverInfo()
+    st = _check(lib().wl_fgcr_solve(ctx, _ptr(x), _ptr(b), float(kappa), net, ctypes.byref(p), ctypes.byref(info),
+                                    _stream(stream)))
+    return st, info.as_dict()
+
+
+def _cplx_flat(w):
+    a = np.ascontiguousarray(np.asarray(w, dtype=np.complex128))
+    return a, a.view(np.float64).ctypes.data_as(_dp)
+
+
+def wl_ptc_create(w1, w2) -> int:
+    """w1: (9, C, 1, 4, 4), w2: (9, 1, C, 4, 4) complex host arrays."""
+    a1, p1 = _cplx_flat(w1)
+    a2, p2 = _cplx_flat(w2)
+    assert a1.shape[0] == 9 and a1.shape[2] == 1 and a2.shape[1] == 1 and a2.shape[2] == a1.shape[1]
+    out = _vp()
+    _check(lib().wl_ptc_create(int(a1.shape[1]), p1, p2, ctypes.byref(out)))
+    return out.value
+
+
+def wl_ptc_destroy(net):
+    return _check(lib().wl_ptc_destroy(net))
+
+
+def _ptc_pair(fn, net, channels):
+    a = np.zeros((9, channels, 1, 4, 4), dtype=np.complex128)
+    b = np.zeros((9, 1, channels, 4, 4), dtype=np.complex128)
+    _check(fn(net, a.view(np.float64).ctypes.data_as(_dp), b.view(np.float64).ctypes.data_as(_dp)))
+    return a, b
+
+
+def wl_ptc_get_weights(net, channels):
+    return _ptc_pair(lib().wl_ptc_get_weights, net, channels)
+
+
+def wl_ptc_get_grads(net, channels):
+    return _ptc_pair(lib().wl_ptc_get_grads, net, channels)
+
+
+def wl_ptc_apply(ctx, net, out, inp, stream=None):
+    return _check(lib().wl_ptc_apply(ctx, net, _ptr(out), _ptr(inp), _stream(stream)))
+
+
+def wl_ptc_layer(ctx, out, inp, weights, cout, cin, adjoint=False, stream=None):
+    return _check(lib().wl_ptc_layer(ctx, _ptr(out), _ptr(inp), _ptr(weights), int(cout), int(cin),
+                                     int(bool(adjoint)), _stream(stream)))
+
+
+def wl_ptc_weight_grad(ctx, grad, g_out, inp, cout, cin, accumulate=False, stream=None):
+    return _check(lib().wl_ptc_weight_grad(ctx, _ptr(grad), _ptr(g_out), _ptr(inp), int(cout), int(cin),
+                                           int(bool(accumulate)), _stream(stream)))
+
+
+def wl_ptc_accumulate(ctx, net, r, e, inv_npairs, stream=None):
+    return _check(lib().wl_ptc_accumulate(ctx, net, _ptr(r), _ptr(e), float(inv_npairs), _stream(stream)))
+
+
+def wl_ptc_step(net, lr, stream=None) -> float:
+    loss = ctypes.c_double()
+    _check(lib().wl_ptc_step(net, float(lr), ctypes.byref(loss), _stream(stream)))
+    return loss.value
 
 
 def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=0, nt=-1):

@@ -1,0 +1,246 @@
+"""GPU parity of the PTC preconditioner kernels and of the FGCR / CGNR solvers.
+
+PTC kernels run in FP32 with FP32 accumulation; they are compared with the FP64
+oracle fed the same weights (for the BF16 kernels: the same BF16-rounded
+weights).  Tolerance 2e-5 relative: FP32 unit roundoff 6e-8 times the ~9 x 8
+paths x channels and the 3-term colour / 4-term spin sums of one output.
+Solvers are judged by the oracle-restated residual ||b - D x|| / ||b||.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from oracle import ptc
+from paper_1405_0700_amd import synth
+from paper_1405_0700_amd import wilson as W
+
+pytestmark = pytest.mark.gpu
+AP = (1, 1, 1, -1)
+TOL32 = 2e-5
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[gpu case] %s" % request.node.nodeid, flush=True)
+    yield
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def random_phases(seed):
+    rng = np.random.default_rng(seed)
+    return tuple(np.exp(1j * rng.uniform(0, 2 * np.pi, 4)))
+
+
+def random_weights(cout, cin, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((9, cout, cin, 4, 4, 2)) * scale
+    return z[..., 0] + 1j * z[..., 1]
+
+
+def dev_weights(w):
+    """complex weights -> FP32 device tensor (re, im interleaved) and the FP32-rounded complex copy"""
+    f = np.stack([w.real, w.imag], -1).astype(np.float32)
+    return torch.as_tensor(np.ascontiguousarray(f)).cuda(), (f[..., 0] + 1j * f[..., 1]).astype(np.complex128)
+
+
+def bf16_round(w):
+    """FP64 -> FP32 -> BF16 (round to nearest even) -> value, per real component"""
+    def r(x):
+        b = np.ascontiguousarray(x.astype(np.float32)).view(np.uint32).astype(np.uint64)
+        b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+        return b.astype(np.uint32).view(np.float32).astype(np.float64)
+    return r(w.real) + 1j * r(w.imag)
+
+
+def f32(x):
+    return np.asarray(x).astype(np.complex64).astype(np.complex128)
+
+
+_cache = {}
+
+
+def lattice(dims, seed, phases=AP, eps=0.5):
+    key = (dims, seed, phases, eps)
+    if key not in _cache:
+        u = synth.su3_links(dims, eps, seed)
+        _cache[key] = (u, W.Lattice.create(u, phases))
+    return _cache[key]
+
+
+def channels(lat, fields):
+    """list of canonical fields -> internal FULL FP32 field with len(fields) channels"""
+    n = len(fields)
+    stack = np.stack([f32(f).reshape(-1, 4, 3) for f in fields])
+    return lat.pack(stack, W.WL_FULL, W.WL_F32, n)
+
+
+def unchannels(lat, internal, n, dims):
+    a = lat.unpack(internal, W.WL_FULL, W.WL_F32, n)
+    lx, ly, lz, lt = dims
+    if n == 1:
+        return [a.reshape(lt, lz, ly, lx, 4, 3)]
+    return [a[k].reshape(lt, lz, ly, lx, 4, 3) for k in range(n)]
+
+
+DIMS = (4, 6, 4, 8)
+
+
+@pytest.mark.parametrize("cout,cin", [(8, 1), (1, 8), (3, 2)])
+def test_layer_forward_and_adjoint(cout, cin):
+    ph = random_phases(1)
+    u, lat = lattice(DIMS, 2, ph)
+    w = random_weights(cout, cin, 3, 0.3)
+    wd, w32 = dev_weights(w)
+    ins = [synth.gaussian_spinor(DIMS, seed=10 + b) for b in range(cin)]
+    out = lat.new(W.WL_FULL, W.WL_F32, cout)
+    W.wl_ptc_layer(lat.ctx, out, channels(lat, ins), wd, cout, cin)
+    want = ptc.layer([f32(f) for f in ins], w32, u, ph)
+    got = unchannels(lat, out, cout, DIMS)
+    assert rel(np.stack(got), np.stack(want)) < TOL32
+    # adjoint: cout_f = cout, cin_f = cin; the adjoint launch maps cout -> cin channels
+    gs = [synth.gaussian_spinor(DIMS, seed=20 + a) for a in range(cout)]
+    gin = lat.new(W.WL_FULL, W.WL_F32, cin)
+    W.wl_ptc_layer(lat.ctx, gin, channels(lat, gs), wd, cin, cout, adjoint=True)
+    want = ptc.layer_adjoint([f32(g) for g in gs], w32, u, ph)
+    assert rel(np.stack(unchannels(lat, gin, cin, DIMS)), np.stack(want)) < TOL32
+
+
+@pytest.mark.parametrize("cout,cin", [(8, 1), (1, 8)])
+def test_weight_gradient(cout, cin):
+    ph = random_phases(4)
+    u, lat = lattice(DIMS, 5, ph)
+    gs = [synth.gaussian_spinor(DIMS, seed=30 + a) for a in range(cout)]
+    ins = [synth.gaussian_spinor(DIMS, seed=40 + b) for b in range(cin)]
+    grad = torch.zeros((9, cout, cin, 4, 4, 2), dtype=torch.float64, device="cuda")
+    W.wl_ptc_weight_grad(lat.ctx, grad, channels(lat, gs), channels(lat, ins), cout, cin)
+    W.wl_ptc_weight_grad(lat.ctx, grad, channels(lat, gs), channels(lat, ins), cout, cin, accumulate=True)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy()
+    got = g[..., 0] + 1j * g[..., 1]
+    want = ptc.weight_grad([f32(x) for x in gs], [f32(x) for x in ins], u, ph)
+    assert rel(got, 2 * want) < TOL32
+
+
+def test_special_weights_give_the_hopping_term():
+    ph = random_phases(6)
+    u, lat = lattice(DIMS, 7, ph)
+    w = np.zeros((9, 1, 1, 4, 4), dtype=np.complex128)
+    for mu in range(4):
+        g = orc.gamma(mu)
+        w[1 + 2 * mu, 0, 0] = np.eye(4) - g
+        w[2 + 2 * mu, 0, 0] = np.eye(4) + g
+    wd, _ = dev_weights(w)
+    phi = synth.gaussian_spinor(DIMS, seed=8)
+    out = lat.new(W.WL_FULL, W.WL_F32)
+    W.wl_ptc_layer(lat.ctx, out, channels(lat, [phi]), wd, 1, 1)
+    h = lat.new(W.WL_FULL, W.WL_F32)
+    W.wl_dslash_apply(lat.ctx, h, lat.pack(phi, W.WL_FULL, W.WL_F32), W.WL_FULL, W.WL_F32, 18)
+    want = orc.hop(phi, u, ph)
+    got = unchannels(lat, out, 1, DIMS)[0]
+    assert rel(got, want) < TOL32
+    assert rel(got, lat.unpack(h, W.WL_FULL, W.WL_F32).reshape(want.shape)) < TOL32
+
+
+def test_network_apply_uses_bf16_weights():
+    ph = random_phases(9)
+    u, lat = lattice(DIMS, 10, ph)
+    w1, w2 = ptc.init_weights(8, seed=530)
+    w1 = w1 + random_weights(8, 1, 11, 0.05)
+    net = W.wl_ptc_create(w1, w2)
+    r = synth.gaussian_spinor(DIMS, seed=12)
+    out = lat.new(W.WL_FULL, W.WL_F32)
+    W.wl_ptc_apply(lat.ctx, net, out, channels(lat, [r]))
+    want, _ = ptc.net_apply(f32(r), bf16_round(w1), bf16_round(w2), u, ph)
+    assert rel(unchannels(lat, out, 1, DIMS)[0], want) < TOL32
+    W.wl_ptc_destroy(net)
+
+
+def test_training_gradients_loss_and_adam_step():
+    ph = random_phases(13)
+    u, lat = lattice(DIMS, 14, ph)
+    w1, w2 = ptc.init_weights(4, seed=15)
+    w1 = w1 + random_weights(4, 1, 16, 0.05)
+    w2 = w2 + random_weights(1, 4, 17, 0.05)
+    net = W.wl_ptc_create(w1, w2)
+    pairs = [(synth.gaussian_spinor(DIMS, seed=20 + i), synth.gaussian_spinor(DIMS, seed=30 + i)) for i in range(3)]
+    for r, e in pairs:
+        W.wl_ptc_accumulate(lat.ctx, net, channels(lat, [r]), channels(lat, [e]), 1.0 / len(pairs))
+    g1, g2 = W.wl_ptc_get_grads(net, 4)
+    w1b, w2b = bf16_round(w1), bf16_round(w2)
+    loss_o, g1o, g2o = ptc.loss_and_grads([(f32(r), f32(e)) for r, e in pairs], w1b, w2b, u, ph)
+    assert rel(g1, g1o) < 1e-4 and rel(g2, g2o) < 1e-4
+    m1, m2 = W.wl_ptc_get_weights(net, 4)
+    loss = W.wl_ptc_step(net, 1e-3)
+    assert abs(loss - loss_o) < 1e-5 * loss_o
+    n1, n2 = W.wl_ptc_get_weights(net, 4)
+    # first Adam step: every real parameter with a non-negligible gradient moves by lr against its sign
+    for w_old, w_new, g in ((m1, n1, g1o), (m2, n2, g2o)):
+        d = w_new - w_old
+        big = np.abs(g.real) > 1e-3 * np.abs(g).max()
+        assert np.allclose(d.real[big], -1e-3 * np.sign(g.real[big]), atol=2e-6)
+        big = np.abs(g.imag) > 1e-3 * np.abs(g).max()
+        assert np.allclose(d.imag[big], -1e-3 * np.sign(g.imag[big]), atol=2e-6)
+    # gradients were cleared by the step
+    c1, c2 = W.wl_ptc_get_grads(net, 4)
+    assert not np.any(c1) and not np.any(c2)
+    W.wl_ptc_destroy(net)
+
+
+# ------------------------------------------------------------------ solvers
+def system_resid(u, kappa, x, b):
+    return float(np.linalg.norm(orc.dirac(x, u, kappa, AP) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("use_net", [False, True])
+def test_fgcr_solves_the_system(use_net):
+    dims = (4, 4, 4, 8)
+    kappa = 0.12
+    u, lat = lattice(dims, 50, AP)
+    b = synth.gaussian_spinor(dims, seed=51)
+    net = W.wl_ptc_create(*ptc.init_weights(8, seed=530)) if use_net else None
+    x = lat.new(W.WL_FULL)
+    p = W.wl_fgcr_params_default()
+    p.fallback = 0
+    st, info = W.wl_fgcr_solve(lat.ctx, x, lat.pack(b), kappa, net, p)
+    r = system_resid(u, kappa, lat.unpack(x).reshape(b.shape), b)
+    print("net", use_net, info, "oracle residual", r)
+    assert st == W.WL_OK and info["fallback"] == 0
+    assert r <= 1.05e-10
+    if net:
+        W.wl_ptc_destroy(net)
+
+
+def test_cgnr_stops_on_the_system_residual():
+    dims = (4, 4, 4, 8)
+    kappa = 0.12
+    u, lat = lattice(dims, 52, AP)
+    b = synth.gaussian_spinor(dims, seed=53)
+    x = lat.new(W.WL_FULL)
+    st, info = W.wl_cgnr_solve(lat.ctx, x, lat.pack(b), kappa)
+    r = system_resid(u, kappa, lat.unpack(x).reshape(b.shape), b)
+    assert st == W.WL_OK and r <= 1.05e-10 and info["true_rel_resid"] <= 1e-10
+
+
+def test_fgcr_falls_back_to_cg_on_a_broken_network():
+    dims = (4, 4, 4, 8)
+    kappa = 0.12
+    u, lat = lattice(dims, 54, AP)
+    b = synth.gaussian_spinor(dims, seed=55)
+    zero = np.zeros((9, 4, 1, 4, 4), dtype=np.complex128)
+    net = W.wl_ptc_create(zero, np.zeros((9, 1, 4, 4, 4), dtype=np.complex128))  # M = 0
+    x = lat.new(W.WL_FULL)
+    st, info = W.wl_fgcr_solve(lat.ctx, x, lat.pack(b), kappa, net)
+    r = system_resid(u, kappa, lat.unpack(x).reshape(b.shape), b)
+    assert st == W.WL_OK and info["fallback"] == 1 and info["fallback_iters"] > 0
+    assert r <= 1.05e-10
+    p = W.wl_fgcr_params_default()
+    p.fallback = 0
+    st, info = W.wl_fgcr_solve(lat.ctx, lat.new(W.WL_FULL), lat.pack(b), kappa, net, p)
+    assert st == W.WL_NOT_CONVERGED and info["fallback"] == 0
+    W.wl_ptc_destroy(net)

@@ -141,9 +141,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
-    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator"], default="eo-cg",
+    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned"], default="eo-cg",
                     help="eo-cg: the headline (24^3x48 FP64 e/o CG); mixed: 32^3x64 FP64 vs mixed-precision CG; "
-                         "propagator: 12 point sources, multi-RHS vs sequential")
+                         "propagator: 12 point sources, multi-RHS vs sequential; learned: train the PTC "
+                         "preconditioner on 16^3x32 fields and compare FGCR with plain FP64 CG on 32^3x64")
+    ap.add_argument("--epochs", type=int, default=20, help="learned: training epochs")
+    ap.add_argument("--train-fields", type=int, default=8, help="learned: number of 16^3x32 training fields")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -171,6 +174,8 @@ def main():
         return run_mixed(args)
     if args.workload == "propagator":
         return run_propagator(args)
+    if args.workload == "learned":
+        return run_learned(args)
     return run_eo_cg(args)
 
 
@@ -396,6 +401,65 @@ def run_propagator(args):
                       "dslash_12rhs_f32_18": {"us": round(us, 2), "algorithmic_GBps": round(gbs, 1),
                                                "bytes_per_site": 576 + 12 * 192}}))
     lat.close()
+
+
+def run_learned(args):
+    """Train the PTC preconditioner (8 hidden channels) on residual/error pairs from plain
+    CG on 16^3x32 fields (kappa 0.137), then solve on a 32^3x64 field with FGCR + network,
+    FGCR without it, and plain FP64 CG, all to ||eta - D x|| <= 1e-10 ||eta||."""
+    import torch
+    from paper_1405_0700_amd import learned, synth
+    from paper_1405_0700_amd import wilson as W
+    kappa, ph = 0.137, (1, 1, 1, -1)
+    log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sets = []
+    for k in range(args.train_fields):
+        dims = (16, 16, 16, 32)
+        lat = W.Lattice.create(synth.su3_links(dims, 0.2, 501 + k), ph)
+        srcs = [synth.gaussian_spinor(dims, seed=1000 * (511 + k) + j) for j in range(4)]
+        sets.append((lat, learned.harvest(lat, srcs, kappa)))
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    log("harvested %d pairs in %.1f s" % (sum(len(p) for _, p in sets), t_harvest))
+    w1, w2 = synth.ptc_weights(8, 530)
+    net = W.wl_ptc_create(w1, w2)
+    t0 = time.perf_counter()
+    losses = learned.train(sets, net, args.epochs, lr=1e-3, log=log, loss="residual", kappa=kappa)
+    t_train = time.perf_counter() - t0
+    dims = (32, 32, 32, 64)
+    lat = W.Lattice.create(synth.su3_links(dims, 0.2, 520), ph)
+    eta = lat.pack(synth.gaussian_spinor(dims, seed=521), W.WL_FULL)
+    fresh = W.wl_ptc_create(w1, w2)
+    res = {}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, info = fn()
+        torch.cuda.synchronize()
+        return st, info, (time.perf_counter() - t) * 1e3
+
+    for name, m in (("fgcr_trained", net), ("fgcr_initial", fresh), ("fgcr_none", None)):
+        x = lat.new(W.WL_FULL)
+        st, info, ms = timed(lambda: W.wl_fgcr_solve(lat.ctx, x, eta, kappa, m))
+        res[name] = {"status": st, "time_ms": round(ms, 2), "iters": info["iters"], "cycles": info["restarts"],
+                     "fallback": info["fallback"], "true_rel_resid": info["true_rel_resid"]}
+        log("%s %s" % (name, res[name]))
+    x = lat.new(W.WL_FULL)
+    st, info, ms = timed(lambda: W.wl_cgnr_solve(lat.ctx, x, eta, kappa))
+    res["cg_f64"] = {"status": st, "time_ms": round(ms, 2), "iters": info["iters"],
+                     "true_rel_resid": info["true_rel_resid"]}
+    log("cg_f64 %s" % res["cg_f64"])
+    print(json.dumps({"metric": "time-to-1e-10 of D x = eta: FGCR + learned PTC preconditioner vs plain FP64 CG",
+                      "unit": "ms", "higher_is_better": False,
+                      "workload": "train 8 x 16^3x32 (links seeds 501-508, 4 sources each), kappa 0.137; "
+                                  "test 32^3x64 links seed 520, source 521",
+                      "harvest_s": round(t_harvest, 2), "train_s": round(t_train, 2), "epochs": args.epochs,
+                      "loss_first": losses[0], "loss_last": losses[-1], "results": res,
+                      "speedup_trained_vs_cg": round(res["cg_f64"]["time_ms"] / res["fgcr_trained"]["time_ms"], 3)}))
+    W.wl_ptc_destroy(net)
+    W.wl_ptc_destroy(fresh)
 
 
 if __name__ == "__main__":

@@ -314,6 +314,15 @@ wl_status wl_ptc_weight_grad(wl_ctx *ctx, double *grad, const void *g_out, const
  * kernels; nothing leaves the device). */
 wl_status wl_ptc_accumulate(wl_ctx *ctx, wl_ptc *net, const void *r, const void *e, double inv_npairs,
                             void *stream);
+/* Training with the residual-norm loss: for one residual r (FULL FP32, one
+ * channel) add inv_npairs * ||D M(r) - r||^2 / ||r||^2 to the loss and its
+ * gradient to the accumulators, D = 1 - kappa H of Eq. (1) applied in FP32.
+ * For a pair with r = D e this is ||D (M(r) - e)||^2 / ||D e||^2: the pair's
+ * error measured by the residual it leaves, the quantity one step x += M(r) of
+ * a right-preconditioned Krylov method reduces.  The backward pass applies D^+
+ * to the residual and then the adjoint layers. */
+wl_status wl_ptc_accumulate_residual(wl_ctx *ctx, wl_ptc *net, const void *r, double kappa, double inv_npairs,
+                                     void *stream);
 /* One Adam step (beta 0.9, 0.999, eps 1e-8, learning rate lr) with the
  * accumulated gradients; returns the accumulated loss in *loss (may be NULL)
  * and clears both.  Synchronises the stream. */

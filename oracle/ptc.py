@@ -121,6 +121,14 @@ def net_apply(r, w1, w2, gauge, phases):
     return layer(hidden, w2, gauge, phases)[0], hidden
 
 
+def net_backward(g_out, r, hidden, w2, gauge, phases):
+    """Weight gradients of the two-layer network from g_out = dL/d conj(M(r)): (dL/dW1*, dL/dW2*)."""
+    g2 = weight_grad([g_out], hidden, gauge, phases)
+    g_hidden = layer_adjoint([g_out], w2, gauge, phases)
+    g1 = weight_grad(g_hidden, [r], gauge, phases)
+    return g1, g2
+
+
 def loss_and_grads(pairs, w1, w2, gauge, phases):
     """L = (1/N) sum_i ||M(r_i) - e_i||^2 / ||e_i||^2 and its Wirtinger gradients (dL/dW1*, dL/dW2*).
 
@@ -134,28 +142,35 @@ def loss_and_grads(pairs, w1, w2, gauge, phases):
         en = float(np.sum(np.abs(e) ** 2))
         d = out - e
         loss += float(np.sum(np.abs(d) ** 2)) / en / n
-        g_out = d / (en * n)
-        g2 += weight_grad([g_out], hidden, gauge, phases)
-        g_hidden = layer_adjoint([g_out], w2, gauge, phases)
-        g1 += weight_grad(g_hidden, [r], gauge, phases)
+        a, b = net_backward(d / (en * n), r, hidden, w2, gauge, phases)
+        g1 += a
+        g2 += b
     return loss, g1, g2
 
 
-def init_weights(channels: int, seed: int):
-    """Initial weights: entries complex N(0, (0.1 / sqrt(9 C_in))^2); channel 0 passes the input
-    through (layer-1 W_0^{0,0} = 1, layer-2 W_0^{0,0} = 1), so the net starts near the identity."""
-    rng = np.random.default_rng(seed)
+def loss_and_grads_residual(residuals, w1, w2, gauge, phases, kappa):
+    """Residual-norm loss L = (1/N) sum_i ||D M(r_i) - r_i||^2 / ||r_i||^2 and its gradients.
 
-    def draw(cout, cin):
-        sd = 0.1 / np.sqrt(NPATH * cin)
-        z = rng.standard_normal((NPATH, cout, cin, 4, 4, 2)) * sd / np.sqrt(2.0)
-        return z[..., 0] + 1j * z[..., 1]
+    For a training pair (r, e) with r = D e this is ||D (M(r) - e)||^2 / ||D e||^2:
+    the error of M(r) as an estimate of e, measured by the residual it leaves,
+    which is what one step x += M(r) of a right-preconditioned Krylov method
+    reduces.  With y = D M(r) - r, dL/d conj(M(r)) = D^+ y / (N ||r||^2)."""
+    from . import oracle as orc
 
-    w1 = draw(channels, 1)
-    w2 = draw(1, channels)
-    w1[0, 0, 0] = np.eye(4)
-    w2[0, 0, 0] = np.eye(4)
-    return w1, w2
+    n = len(residuals)
+    loss = 0.0
+    g1 = np.zeros_like(w1)
+    g2 = np.zeros_like(w2)
+    for r in residuals:
+        out, hidden = net_apply(r, w1, w2, gauge, phases)
+        rn = float(np.sum(np.abs(r) ** 2))
+        y = orc.dirac(out, gauge, kappa, phases) - r
+        loss += float(np.sum(np.abs(y) ** 2)) / rn / n
+        g_out = orc.dirac(y, gauge, kappa, phases, dagger=True) / (rn * n)
+        a, b = net_backward(g_out, r, hidden, w2, gauge, phases)
+        g1 += a
+        g2 += b
+    return loss, g1, g2
 
 
 def adam_step(w, g_conj, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -1324,44 +1324,83 @@ extern "C" wl_status wl_ptc_weight_grad(wl_ctx *c, double *grad, const void *gou
     return WL_OK;
 }
 
+// back-propagation of go = dL/d conj(M(r)) through both layers into the gradient accumulators
+static wl_status ptc_backward(wl_ctx *c, wl_ptc *n, const void *go, const void *r, const void *h, void *gh,
+                              void *stream) {
+    const int C = n->channels;
+    double *g1 = n->grad, *g2 = n->grad + 2 * n->n1;
+    wl_status st;
+    if ((st = wl_ptc_weight_grad(c, g2, go, h, 1, C, 1, stream))) return st;
+    PtcArgs a2t = ptc_args(c, gh, go, C, 1, n->wb + 2 * n->n1, 1, &st);
+    if (st) return st;
+    HIP_TRY(launch_ptc_layer(a2t, true, (hipStream_t)stream));
+    return wl_ptc_weight_grad(c, g1, gh, r, C, 1, 1, stream);
+}
+
+// ||f||^2 of one FULL FP32 field into the device scalar *dst
+static hipError_t full_norm2_f32(wl_ctx *c, const void *f, double *dst, hipStream_t s) {
+    const long stride = part_stride_for(c, 1);
+    double *partials = (double *)c->buf[S_PARTIALS];
+    VecArgs v = vec_args(c, WL_F32, 1);
+    set_vec(v, 0, f, half_bytes(c, WL_F32, 1));
+    v.partials = partials;
+    v.part_stride = stride;
+    hipError_t e = blas_norm2(WL_F32, v, 2, s);
+    if (e != hipSuccess) return e;
+    return reduce_partials(partials, stride, blas_blocks(v.n) * 2, 1, dst, s);
+}
+
+static wl_status ptc_workspace(wl_ctx *c, int C) {
+    const size_t h1 = half_bytes(c, WL_F32, 1), hc = half_bytes(c, WL_F32, C);
+    wl_status st;
+    if ((st = ensure_buf(c, S_PTC_H, 2 * hc)) || (st = ensure_buf(c, S_PTC_GH, 2 * hc)) ||
+        (st = ensure_buf(c, S_PTC_O, 2 * h1)) || (st = ensure_buf(c, S_PTC_GO, 2 * h1)) ||
+        (st = ensure_buf(c, S_PTC_E2, sizeof(double) * 2)) ||
+        (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * part_stride_for(c, 1))))
+        return st;
+    return WL_OK;
+}
+
 extern "C" wl_status wl_ptc_accumulate(wl_ctx *c, wl_ptc *n, const void *r, const void *e, double inv_npairs,
                                        void *stream) {
     g_err.clear();
     if (!c || !n || !r || !e || !aligned16(r) || !aligned16(e)) return fail(WL_ERR_ARG, "null or misaligned argument");
     if (!(inv_npairs > 0.0) || !std::isfinite(inv_npairs)) return fail(WL_ERR_ARG, "bad pair weight");
     hipStream_t s = (hipStream_t)stream;
-    const int C = n->channels;
-    const size_t h1 = half_bytes(c, WL_F32, 1), hc = half_bytes(c, WL_F32, C);
-    const long stride = part_stride_for(c, 1);
     wl_status st;
-    if ((st = ensure_buf(c, S_PTC_H, 2 * hc)) || (st = ensure_buf(c, S_PTC_GH, 2 * hc)) ||
-        (st = ensure_buf(c, S_PTC_O, 2 * h1)) || (st = ensure_buf(c, S_PTC_GO, 2 * h1)) ||
-        (st = ensure_buf(c, S_PTC_E2, sizeof(double) * 2)) ||
-        (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * stride)))
-        return st;
+    if ((st = ptc_workspace(c, n->channels))) return st;
     void *h = c->buf[S_PTC_H], *gh = c->buf[S_PTC_GH], *o = c->buf[S_PTC_O], *go = c->buf[S_PTC_GO];
     double *e2 = (double *)c->buf[S_PTC_E2];
-    double *partials = (double *)c->buf[S_PARTIALS];
-    // forward
     if ((st = ptc_forward(c, n, o, r, h, s))) return st;
-    // ||e||^2 on the device
-    VecArgs v = vec_args(c, WL_F32, 1);
-    set_vec(v, 0, e, h1);
-    v.partials = partials;
-    v.part_stride = stride;
-    HIP_TRY(blas_norm2(WL_F32, v, 2, s));
-    HIP_TRY(reduce_partials(partials, stride, blas_blocks(v.n) * 2, 1, e2, s));
-    // loss and dL/d conj(out)
-    HIP_TRY(launch_ptc_loss(o, e, go, c->Vh, e2, inv_npairs, partials, stride, n->loss, s));
-    // layer 2: weight gradient, then dL/d conj(hidden) through its adjoint
-    double *g1 = n->grad, *g2 = n->grad + 2 * n->n1;
-    if ((st = wl_ptc_weight_grad(c, g2, go, h, 1, C, 1, stream))) return st;
-    PtcArgs a2t = ptc_args(c, gh, go, C, 1, n->wb + 2 * n->n1, 1, &st);
-    if (st) return st;
-    HIP_TRY(launch_ptc_layer(a2t, true, s));
-    // layer 1: weight gradient
-    if ((st = wl_ptc_weight_grad(c, g1, gh, r, C, 1, 1, stream))) return st;
-    return WL_OK;
+    HIP_TRY(full_norm2_f32(c, e, e2, s));
+    // loss and dL/d conj(out) = (out - e) / (N ||e||^2)
+    HIP_TRY(launch_ptc_loss(o, e, go, c->Vh, e2, inv_npairs, (double *)c->buf[S_PARTIALS], part_stride_for(c, 1),
+                            n->loss, s));
+    return ptc_backward(c, n, go, r, h, gh, stream);
+}
+
+extern "C" wl_status wl_ptc_accumulate_residual(wl_ctx *c, wl_ptc *n, const void *r, double kappa,
+                                                double inv_npairs, void *stream) {
+    g_err.clear();
+    if (!c || !n || !r || !aligned16(r)) return fail(WL_ERR_ARG, "null or misaligned argument");
+    if (!(inv_npairs > 0.0) || !std::isfinite(inv_npairs)) return fail(WL_ERR_ARG, "bad pair weight");
+    if (!std::isfinite(kappa)) return fail(WL_ERR_ARG, "non-finite kappa");
+    hipStream_t s = (hipStream_t)stream;
+    wl_status st;
+    if ((st = ptc_workspace(c, n->channels))) return st;
+    void *h = c->buf[S_PTC_H], *gh = c->buf[S_PTC_GH], *o = c->buf[S_PTC_O], *go = c->buf[S_PTC_GO];
+    double *r2 = (double *)c->buf[S_PTC_E2];
+    if ((st = ptc_forward(c, n, o, r, h, s))) return st;
+    // y = D M(r) in go; then, in place, y <- (y - r) / (N ||r||^2) with the loss summed on the way
+    if ((st = apply_m(c, WL_OP_D, false, kappa, WL_F32, 18, 1, go, o, nullptr, nullptr, 0, nullptr, s, nullptr)))
+        return st;
+    HIP_TRY(full_norm2_f32(c, r, r2, s));
+    HIP_TRY(launch_ptc_loss(go, r, go, c->Vh, r2, inv_npairs, (double *)c->buf[S_PARTIALS], part_stride_for(c, 1),
+                            n->loss, s));
+    // dL/d conj(M(r)) = D^+ of that, written over the network output (no longer needed)
+    if ((st = apply_m(c, WL_OP_D, true, kappa, WL_F32, 18, 1, o, go, nullptr, nullptr, 0, nullptr, s, nullptr)))
+        return st;
+    return ptc_backward(c, n, o, r, h, gh, stream);
 }
 
 extern "C" wl_status wl_ptc_step(wl_ptc *n, double lr, double *loss, void *stream) {

@@ -36,6 +36,7 @@ __all__ = [
     "haar_su3",
     "reunitarise",
     "volume",
+    "ptc_weights",
 ]
 
 
@@ -152,3 +153,24 @@ def haar_su3(shape, seed: int) -> np.ndarray:
     det = np.linalg.det(q)
     q = q / (det ** (1.0 / 3.0))[..., None, None]
     return q
+
+
+def ptc_weights(channels: int, seed: int):
+    """Seeded initial weights of the two-layer PTC network (1 -> channels -> 1).
+
+    Shapes (9, channels, 1, 4, 4) and (9, 1, channels, 4, 4) complex128; every
+    entry complex Gaussian with standard deviation 0.1 / sqrt(9 C_in), except the
+    identity-path matrix of channel 0 in both layers, which is the 4x4 unit
+    matrix (so the network starts close to the identity map)."""
+    rng = np.random.default_rng(seed)
+
+    def draw(cout, cin):
+        sd = 0.1 / np.sqrt(9 * cin)
+        z = rng.standard_normal((9, cout, cin, 4, 4, 2)) * sd / np.sqrt(2.0)
+        return z[..., 0] + 1j * z[..., 1]
+
+    w1 = draw(channels, 1)
+    w2 = draw(1, channels)
+    w1[0, 0, 0] = np.eye(4)
+    w2[0, 0, 0] = np.eye(4)
+    return w1, w2

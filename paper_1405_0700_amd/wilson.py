@@ -118,6 +118,7 @@ _SIGS = {
     "wl_ptc_layer": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_ptc_weight_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_ptc_accumulate": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, _vp]),
+    "wl_ptc_accumulate_residual": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp]),
     "wl_ptc_step": (ctypes.c_int, [_vp, ctypes.c_double, _dp, _vp]),
     "wl_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wl_timing_read": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _dp]),
@@ -354,6 +355,11 @@ def wl_ptc_weight_grad(ctx, grad, g_out, inp, cout, cin, accumulate=False, strea
 
 def wl_ptc_accumulate(ctx, net, r, e, inv_npairs, stream=None):
     return _check(lib().wl_ptc_accumulate(ctx, net, _ptr(r), _ptr(e), float(inv_npairs), _stream(stream)))
+
+
+def wl_ptc_accumulate_residual(ctx, net, r, kappa, inv_npairs, stream=None):
+    return _check(lib().wl_ptc_accumulate_residual(ctx, net, _ptr(r), float(kappa), float(inv_npairs),
+                                                   _stream(stream)))
 
 
 def wl_ptc_step(net, lr, stream=None) -> float:

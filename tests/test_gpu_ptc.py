@@ -150,7 +150,7 @@ def test_special_weights_give_the_hopping_term():
 def test_network_apply_uses_bf16_weights():
     ph = random_phases(9)
     u, lat = lattice(DIMS, 10, ph)
-    w1, w2 = ptc.init_weights(8, seed=530)
+    w1, w2 = synth.ptc_weights(8, seed=530)
     w1 = w1 + random_weights(8, 1, 11, 0.05)
     net = W.wl_ptc_create(w1, w2)
     r = synth.gaussian_spinor(DIMS, seed=12)
@@ -164,7 +164,7 @@ def test_network_apply_uses_bf16_weights():
 def test_training_gradients_loss_and_adam_step():
     ph = random_phases(13)
     u, lat = lattice(DIMS, 14, ph)
-    w1, w2 = ptc.init_weights(4, seed=15)
+    w1, w2 = synth.ptc_weights(4, seed=15)
     w1 = w1 + random_weights(4, 1, 16, 0.05)
     w2 = w2 + random_weights(1, 4, 17, 0.05)
     net = W.wl_ptc_create(w1, w2)
@@ -192,6 +192,25 @@ def test_training_gradients_loss_and_adam_step():
     W.wl_ptc_destroy(net)
 
 
+def test_residual_loss_gradients():
+    ph = random_phases(18)
+    u, lat = lattice(DIMS, 19, ph)
+    kappa = 0.12
+    w1, w2 = synth.ptc_weights(4, seed=21)
+    w1 = w1 + random_weights(4, 1, 22, 0.05)
+    w2 = w2 + random_weights(1, 4, 23, 0.05)
+    net = W.wl_ptc_create(w1, w2)
+    rs = [synth.gaussian_spinor(DIMS, seed=40 + i) for i in range(2)]
+    for r in rs:
+        W.wl_ptc_accumulate_residual(lat.ctx, net, channels(lat, [r]), kappa, 1.0 / len(rs))
+    g1, g2 = W.wl_ptc_get_grads(net, 4)
+    loss_o, g1o, g2o = ptc.loss_and_grads_residual([f32(r) for r in rs], bf16_round(w1), bf16_round(w2), u, ph, kappa)
+    assert rel(g1, g1o) < 1e-4 and rel(g2, g2o) < 1e-4
+    loss = W.wl_ptc_step(net, 1e-3)
+    assert abs(loss - loss_o) < 1e-5 * loss_o
+    W.wl_ptc_destroy(net)
+
+
 # ------------------------------------------------------------------ solvers
 def system_resid(u, kappa, x, b):
     return float(np.linalg.norm(orc.dirac(x, u, kappa, AP) - b) / np.linalg.norm(b))
@@ -203,7 +222,7 @@ def test_fgcr_solves_the_system(use_net):
     kappa = 0.12
     u, lat = lattice(dims, 50, AP)
     b = synth.gaussian_spinor(dims, seed=51)
-    net = W.wl_ptc_create(*ptc.init_weights(8, seed=530)) if use_net else None
+    net = W.wl_ptc_create(*synth.ptc_weights(8, seed=530)) if use_net else None
     x = lat.new(W.WL_FULL)
     p = W.wl_fgcr_params_default()
     p.fallback = 0

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as orc
-from oracle import ptc
+from oracle import dense, ptc
 from paper_1405_0700_amd import synth
 
 AP = (1, 1, 1, -1)
@@ -50,7 +50,7 @@ def test_identity_weights():
     w = np.zeros((ptc.NPATH, 1, 1, 4, 4), dtype=np.complex128)
     w[0, 0, 0] = np.eye(4)
     assert np.array_equal(ptc.layer([phi], w, u, AP)[0], phi)
-    w1, w2 = ptc.init_weights(8, seed=6)
+    w1, w2 = synth.ptc_weights(8, seed=6)
     w1[:, 1:] = 0
     w1[1:, 0] = 0
     w2[:, :, 1:] = 0
@@ -128,6 +128,36 @@ def test_gradients_match_central_finite_differences():
                 assert abs(fd - want) <= 1e-7 * max(1.0, abs(want)), (which, k, part, fd, want)
 
 
+def test_residual_loss_gradients_match_central_finite_differences():
+    dims = (2, 2, 4, 2)
+    u = synth.su3_links(dims, 0.6, seed=44)
+    ph = random_phases(45)
+    w1, w2 = random_weights(2, 1, 46) * 0.3, random_weights(1, 2, 47) * 0.3
+    rs = [synth.gaussian_spinor(dims, seed=70 + i) for i in range(2)]
+    kappa = 0.11
+    loss, g1, g2 = ptc.loss_and_grads_residual(rs, w1, w2, u, ph, kappa)
+    # the loss is the definition written out with the dense matrix of D
+    dm = np.eye(12 * synth.volume(dims)) - kappa * dense.hopping_matrix(u, ph)
+    want = np.mean([np.linalg.norm(dm @ ptc.net_apply(r, w1, w2, u, ph)[0].ravel() - r.ravel()) ** 2
+                    / np.linalg.norm(r) ** 2 for r in rs])
+    assert abs(loss - want) < 1e-12 * want
+    rng = np.random.default_rng(8)
+    eps = 1e-6
+    for which, w, g in (("w1", w1, g1), ("w2", w2, g2)):
+        for _ in range(5):
+            k = tuple(rng.integers(0, n) for n in w.shape)
+            for unit, part in ((1.0, "re"), (1j, "im")):
+                wp, wm = w.copy(), w.copy()
+                wp[k] += unit * eps
+                wm[k] -= unit * eps
+                args_p = (wp, w2) if which == "w1" else (w1, wp)
+                args_m = (wm, w2) if which == "w1" else (w1, wm)
+                fd = (ptc.loss_and_grads_residual(rs, *args_p, u, ph, kappa)[0]
+                      - ptc.loss_and_grads_residual(rs, *args_m, u, ph, kappa)[0]) / (2 * eps)
+                want = 2 * (g[k].real if part == "re" else g[k].imag)
+                assert abs(fd - want) <= 1e-7 * max(1.0, abs(want)), (which, k, part, fd, want)
+
+
 def test_first_adam_step_moves_each_parameter_by_lr():
     rng = np.random.default_rng(3)
     w = rng.standard_normal((5, 4)) + 1j * rng.standard_normal((5, 4))
@@ -142,7 +172,7 @@ def test_first_adam_step_moves_each_parameter_by_lr():
 
 
 def test_init_weights_shapes_and_pass_through():
-    w1, w2 = ptc.init_weights(8, seed=530)
+    w1, w2 = synth.ptc_weights(8, seed=530)
     assert w1.shape == (9, 8, 1, 4, 4) and w2.shape == (9, 1, 8, 4, 4)
     assert np.array_equal(w1[0, 0, 0], np.eye(4)) and np.array_equal(w2[0, 0, 0], np.eye(4))
     sd = np.std(np.concatenate([w1[1:].ravel(), w1[0, 1:].ravel()]))

@@ -425,7 +425,9 @@ def run_learned(args):
     w1, w2 = synth.ptc_weights(8, 530)
     net = W.wl_ptc_create(w1, w2)
     t0 = time.perf_counter()
-    losses = learned.train(sets, net, args.epochs, lr=1e-3, log=log, loss="residual", kappa=kappa)
+    # sum of the error-norm and residual-norm losses: measured best on this workload (the
+    # residual norm alone lets the network shrink the low modes, which ruins D M's conditioning)
+    losses = learned.train(sets, net, args.epochs, lr=1e-3, log=log, loss="both", kappa=kappa)
     t_train = time.perf_counter() - t0
     dims = (32, 32, 32, 64)
     lat = W.Lattice.create(synth.su3_links(dims, 0.2, 520), ph)
@@ -446,18 +448,27 @@ def run_learned(args):
         res[name] = {"status": st, "time_ms": round(ms, 2), "iters": info["iters"], "cycles": info["restarts"],
                      "fallback": info["fallback"], "true_rel_resid": info["true_rel_resid"]}
         log("%s %s" % (name, res[name]))
+    for name, m in (("pcgnr_trained", net), ("pcgnr_initial", fresh), ("pcgnr_none", None)):
+        x = lat.new(W.WL_FULL)
+        pp = W.wl_pcgnr_params_default()
+        pp.maxiter = 2000
+        st, info, ms = timed(lambda: W.wl_pcgnr_solve(lat.ctx, x, eta, kappa, m, pp))
+        res[name] = {"status": st, "time_ms": round(ms, 2), "iters": info["iters"], "cycles": info["restarts"],
+                     "fallback": info["fallback"], "true_rel_resid": info["true_rel_resid"]}
+        log("%s %s" % (name, res[name]))
     x = lat.new(W.WL_FULL)
     st, info, ms = timed(lambda: W.wl_cgnr_solve(lat.ctx, x, eta, kappa))
     res["cg_f64"] = {"status": st, "time_ms": round(ms, 2), "iters": info["iters"],
                      "true_rel_resid": info["true_rel_resid"]}
     log("cg_f64 %s" % res["cg_f64"])
-    print(json.dumps({"metric": "time-to-1e-10 of D x = eta: FGCR + learned PTC preconditioner vs plain FP64 CG",
+    print(json.dumps({"metric": "time-to-1e-10 of D x = eta: learned PTC preconditioner (FGCR, CGNR on D M) vs plain FP64 CG",
                       "unit": "ms", "higher_is_better": False,
                       "workload": "train 8 x 16^3x32 (links seeds 501-508, 4 sources each), kappa 0.137; "
                                   "test 32^3x64 links seed 520, source 521",
                       "harvest_s": round(t_harvest, 2), "train_s": round(t_train, 2), "epochs": args.epochs,
                       "loss_first": losses[0], "loss_last": losses[-1], "results": res,
-                      "speedup_trained_vs_cg": round(res["cg_f64"]["time_ms"] / res["fgcr_trained"]["time_ms"], 3)}))
+                      "speedup_vs_cg_f64": {k: round(res["cg_f64"]["time_ms"] / v["time_ms"], 3)
+                                            for k, v in res.items() if k != "cg_f64"}}))
     W.wl_ptc_destroy(net)
     W.wl_ptc_destroy(fresh)
 

@@ -282,7 +282,8 @@ wl_status wl_fgcr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, const
  * 4x4 spin matrices.  Weights: layer 1 (9, C, 1, 4, 4), layer 2 (9, 1, C, 4, 4)
  * complex, row-major, (re, im) interleaved.  The network keeps FP32 master
  * weights (optimised by Adam) and a BF16 copy that its kernels read; fields
- * are FULL FP32 internal fields; arithmetic is FP32. */
+ * are FULL FP32 internal fields, a field of C channels being C consecutive
+ * single-rhs FULL FP32 fields (channel-major); arithmetic is FP32. */
 /* Create a network from host FP64 weights (copied to the device). Synchronous. */
 wl_status wl_ptc_create(int channels, const double *w1, const double *w2, wl_ptc **out);
 wl_status wl_ptc_destroy(wl_ptc *net);
@@ -327,6 +328,36 @@ wl_status wl_ptc_accumulate_residual(wl_ctx *ctx, wl_ptc *net, const void *r, do
  * accumulated gradients; returns the accumulated loss in *loss (may be NULL)
  * and clears both.  Synchronises the stream. */
 wl_status wl_ptc_step(wl_ptc *net, double lr, double *loss, void *stream);
+
+/* ---------------------------------------------------------------- preconditioned CGNR
+ *
+ * CG on the normal equations of the right-preconditioned system D M y = b,
+ * x = M y, with M the PTC network of `net` (or M = 1 for net == NULL): each
+ * iteration applies D M and its adjoint M^+ D^+, so (D M)^+ (D M) is Hermitian
+ * positive definite whatever the spectrum of D (restarted GCR on D stalls once
+ * D's spectrum surrounds the origin, as it does past the critical kappa).
+ * The inner iteration runs in FP32 (fields, D, the network) with FP64 dot
+ * products, on the correction of the FP64 residual, until that residual has
+ * dropped by inner_tol; then x += M y in FP64 and the residual is recomputed
+ * in FP64 (defect correction).  Two outer cycles that reduce ||b - D x| by
+ * less than the factor `stagnation`, breakdown or maxiter hand the solve to
+ * plain FP64 CG (wl_cgnr_solve) if `fallback`. */
+typedef struct {
+    double tol;        /* stop when ||b - D x|| <= tol ||b||                      */
+    int maxiter;       /* inner iterations in total                              */
+    double inner_tol;  /* residual reduction per outer cycle, in (0, 1)          */
+    int fallback;      /* finish with plain FP64 CG on failure                   */
+    double stagnation; /* an outer cycle must reduce ||r|| below this factor     */
+} wl_pcgnr_params;
+
+/* tol 1e-10, maxiter 20000, inner_tol 1e-5, fallback 1, stagnation 0.5 */
+void wl_pcgnr_params_default(wl_pcgnr_params *p);
+
+/* Solve D x = b (FULL FP64 fields; x in: initial guess, out: solution).
+ * Synchronous; info as for wl_fgcr_solve (iters = inner iterations,
+ * restarts = outer cycles). */
+wl_status wl_pcgnr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, const wl_ptc *net,
+                         const wl_pcgnr_params *params, wl_solver_info *info, void *stream);
 
 /* ---------------------------------------------------------------- kernel timing */
 

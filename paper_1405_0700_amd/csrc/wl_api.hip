@@ -48,6 +48,7 @@ enum Slot {
     S_PARTIALS, S_SCAL, S_BNORM, S_FLAG,
     S_PTC_H, S_PTC_GH, S_PTC_O, S_PTC_GO, S_PTC_PART, S_PTC_E2,       // PTC workspace
     S_GCR_R, S_GCR_X, S_GCR_Z, S_GCR_W, S_GCR_TMP, S_GCR_RHS,          // FGCR workspace
+    S_PCG,                                                             // preconditioned CGNR workspace
     S_NSLOTS
 };
 }
@@ -1233,6 +1234,11 @@ extern "C" wl_status wl_ptc_get_grads(const wl_ptc *n, double *g1, double *g2) {
     return ptc_download(n, n->grad, true, g1, g2);
 }
 
+// bytes of a C-channel PTC field: C consecutive FULL FP32 single-rhs fields
+static size_t ptc_field_bytes(const wl_ctx *c, int channels) {
+    return (size_t)channels * 2 * half_bytes(c, WL_F32, 1);
+}
+
 static PtcArgs ptc_args(wl_ctx *c, void *out, const void *in, int cout, int cin, const void *w, int adjoint,
                         wl_status *st) {
     PtcArgs a;
@@ -1241,11 +1247,10 @@ static PtcArgs ptc_args(wl_ctx *c, void *out, const void *in, int cout, int cin,
     size_t slab = 0;
     *st = get_links(c, WL_F32, 18, &gauge, &slab);
     a.g = c->g;
-    const size_t ho = half_bytes(c, WL_F32, cout), hi = half_bytes(c, WL_F32, cin);
-    a.out[0] = out;
-    a.out[1] = (char *)out + ho;
-    a.in[0] = in;
-    a.in[1] = (const char *)in + hi;
+    (void)cin;
+    a.out = (char *)out;
+    a.in = (const char *)in;
+    a.half = half_bytes(c, WL_F32, 1);
     a.gauge = gauge;
     a.slab_bytes = slab;
     a.w = w;
@@ -1274,7 +1279,7 @@ extern "C" wl_status wl_ptc_apply(wl_ctx *c, const wl_ptc *n, void *out, const v
     if (!c || !n || !out || !in || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned argument");
     const size_t hb = half_bytes(c, WL_F32, 1);
     if (overlap(out, 2 * hb, in, 2 * hb)) return fail(WL_ERR_ARG, "out and in overlap");
-    wl_status st = ensure_buf(c, S_PTC_H, 2 * half_bytes(c, WL_F32, n->channels));
+    wl_status st = ensure_buf(c, S_PTC_H, ptc_field_bytes(c, n->channels));
     if (st) return st;
     return ptc_forward(c, n, out, in, c->buf[S_PTC_H], (hipStream_t)stream);
 }
@@ -1284,7 +1289,7 @@ extern "C" wl_status wl_ptc_layer(wl_ctx *c, void *out, const void *in, const fl
     g_err.clear();
     if (!c || !out || !in || !weights || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned argument");
     if (cout < 1 || cin < 1 || cout * cin > PTC_MAXC) return fail(WL_ERR_ARG, "channels %d x %d exceed %d", cout, cin, PTC_MAXC);
-    if (overlap(out, 2 * half_bytes(c, WL_F32, cout), in, 2 * half_bytes(c, WL_F32, cin)))
+    if (overlap(out, ptc_field_bytes(c, cout), in, ptc_field_bytes(c, cin)))
         return fail(WL_ERR_ARG, "out and in overlap");
     wl_status st;
     PtcArgs a = ptc_args(c, out, in, cout, cin, weights, adjoint ? 1 : 0, &st);
@@ -1308,11 +1313,9 @@ extern "C" wl_status wl_ptc_weight_grad(wl_ctx *c, double *grad, const void *gou
     PtcGradArgs a;
     std::memset(&a, 0, sizeof a);
     a.g = c->g;
-    const size_t ho = half_bytes(c, WL_F32, cout), hi = half_bytes(c, WL_F32, cin);
-    a.gout[0] = gout;
-    a.gout[1] = (const char *)gout + ho;
-    a.in[0] = in;
-    a.in[1] = (const char *)in + hi;
+    a.gout = (const char *)gout;
+    a.in = (const char *)in;
+    a.half = half_bytes(c, WL_F32, 1);
     a.gauge = gauge;
     a.slab_bytes = slab;
     a.cout = cout;
@@ -1351,9 +1354,9 @@ static hipError_t full_norm2_f32(wl_ctx *c, const void *f, double *dst, hipStrea
 }
 
 static wl_status ptc_workspace(wl_ctx *c, int C) {
-    const size_t h1 = half_bytes(c, WL_F32, 1), hc = half_bytes(c, WL_F32, C);
+    const size_t h1 = half_bytes(c, WL_F32, 1), fc = ptc_field_bytes(c, C);
     wl_status st;
-    if ((st = ensure_buf(c, S_PTC_H, 2 * hc)) || (st = ensure_buf(c, S_PTC_GH, 2 * hc)) ||
+    if ((st = ensure_buf(c, S_PTC_H, fc)) || (st = ensure_buf(c, S_PTC_GH, fc)) ||
         (st = ensure_buf(c, S_PTC_O, 2 * h1)) || (st = ensure_buf(c, S_PTC_GO, 2 * h1)) ||
         (st = ensure_buf(c, S_PTC_E2, sizeof(double) * 2)) ||
         (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * part_stride_for(c, 1))))
@@ -1548,6 +1551,202 @@ extern "C" wl_status wl_cgnr_solve(wl_ctx *c, void *x, const void *eta, double k
     return result;
 }
 
+// M^+ of the two-layer network: layer-2 adjoint (1 -> C channels), then layer-1 adjoint (C -> 1)
+static wl_status ptc_adjoint_apply(wl_ctx *c, const wl_ptc *n, void *out, const void *in, void *hidden,
+                                   hipStream_t s) {
+    wl_status st;
+    PtcArgs a2 = ptc_args(c, hidden, in, n->channels, 1, n->wb + 2 * n->n1, 1, &st);
+    if (st) return st;
+    HIP_TRY(launch_ptc_layer(a2, true, s));
+    PtcArgs a1 = ptc_args(c, out, hidden, 1, n->channels, n->wb, 1, &st);
+    if (st) return st;
+    HIP_TRY(launch_ptc_layer(a1, true, s));
+    return WL_OK;
+}
+
+extern "C" void wl_pcgnr_params_default(wl_pcgnr_params *p) {
+    if (!p) return;
+    p->tol = 1e-10;
+    p->maxiter = 20000;
+    p->inner_tol = 1e-5;
+    p->fallback = 1;
+    p->stagnation = 0.5;
+}
+
+extern "C" wl_status wl_pcgnr_solve(wl_ctx *c, void *x, const void *b, double kappa, const wl_ptc *net,
+                                    const wl_pcgnr_params *params, wl_solver_info *info, void *stream) {
+    g_err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    wl_status st = check_field_args(c, WL_FULL, WL_F64, 1);
+    if (st) return st;
+    if (!x || !b || !aligned16(x) || !aligned16(b)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    wl_pcgnr_params P;
+    wl_pcgnr_params_default(&P);
+    if (params) P = *params;
+    if (!(P.tol > 0.0) || P.maxiter < 1 || !(P.inner_tol > 0.0 && P.inner_tol < 1.0) ||
+        !(P.stagnation > 0.0 && P.stagnation <= 1.0))
+        return fail(WL_ERR_ARG, "bad preconditioned CGNR parameters");
+    if (!std::isfinite(kappa)) return fail(WL_ERR_ARG, "non-finite kappa");
+    Fields F{c, (hipStream_t)stream, part_stride_for(c, 1)};
+    const size_t full_hi = 2 * half_bytes(c, WL_F64, 1), full_lo = 2 * half_bytes(c, WL_F32, 1);
+    const size_t hb_lo = half_bytes(c, WL_F32, 1), hb_hi = half_bytes(c, WL_F64, 1);
+    if (overlap(x, full_hi, b, full_hi)) return fail(WL_ERR_ARG, "x and b overlap");
+    if ((st = ensure_buf(c, S_GCR_R, full_hi)) || (st = ensure_buf(c, S_GCR_TMP, full_hi)) ||
+        (st = ensure_buf(c, S_PCG, 6 * full_lo)) || (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * F.stride)))
+        return st;
+    if (net && (st = ensure_buf(c, S_PTC_H, ptc_field_bytes(c, net->channels)))) return st;
+    char *base = (char *)c->buf[S_PCG];
+    void *y = base, *p = base + full_lo, *rho = base + 2 * full_lo, *sv = base + 3 * full_lo,
+         *q = base + 4 * full_lo, *t = base + 5 * full_lo;
+    void *rhi = c->buf[S_GCR_R], *thi = c->buf[S_GCR_TMP], *hid = net ? c->buf[S_PTC_H] : nullptr;
+    // field-wide FP32 helpers (both parities)
+    auto axpby = [&](double a, const void *v0, double bb, void *v1, double *n2) -> wl_status {
+        VecArgs v = vec_args(c, WL_F32, 1);
+        set_vec(v, 0, v0, hb_lo);
+        set_vec(v, 1, v1, hb_lo);
+        v.a = a;
+        v.b = bb;
+        v.partials = (double *)c->buf[S_PARTIALS];
+        v.part_stride = F.stride;
+        HIP_TRY(blas_axpby(WL_F32, v, 2, n2 != nullptr, F.s));
+        if (n2) return reduce_to_host(c, 1, F.stride, blas_blocks(v.n) * 2, n2, F.s);
+        return WL_OK;
+    };
+    auto copy_lo = [&](void *dst, const void *src) -> wl_status {
+        VecArgs v = vec_args(c, WL_F32, 1);
+        set_vec(v, 0, src, hb_lo);
+        set_vec(v, 1, dst, hb_lo);
+        HIP_TRY(blas_convert(WL_F32, WL_F32, false, v, 2, F.s));
+        return WL_OK;
+    };
+    // out = M in (the network, or a copy when there is none)
+    auto apply_net = [&](void *out, const void *in, bool adjoint) -> wl_status {
+        if (!net) return copy_lo(out, in);
+        return adjoint ? ptc_adjoint_apply(c, net, out, in, hid, F.s) : ptc_forward(c, net, out, in, hid, F.s);
+    };
+    double b2 = 0.0;
+    if ((st = norm_full(F, WL_F64, b, &b2))) return st;
+    wl_solver_info out{};
+    if (!(b2 > 0.0)) {
+        VecArgs v = vec_args(c, WL_F64, 1);
+        set_vec(v, 0, x, hb_hi);
+        HIP_TRY(blas_zero(WL_F64, v, 2, F.s));
+        HIP_TRY(hipStreamSynchronize(F.s));
+        if (info) *info = out;
+        return WL_OK;
+    }
+    double rn2 = 0.0;
+    if ((st = system_residual(F, kappa, x, b, rhi, thi, &rn2))) return st;
+    const double target2 = P.tol * P.tol * b2;
+    int total = 0, cycles = 0, stagnant = 0;
+    bool failed = false;
+    double rho2 = rn2;
+    while (rn2 > target2) {
+        if (total >= P.maxiter || !std::isfinite(rn2)) {
+            failed = true;
+            break;
+        }
+        // inner CG on the normal equations of (D M) y = r, FP32 fields, from y = 0
+        {
+            VecArgs v = vec_args(c, WL_F32, 1);
+            set_vec(v, 0, rhi, hb_hi);
+            set_vec(v, 1, rho, hb_lo);
+            HIP_TRY(blas_convert(WL_F32, WL_F64, false, v, 2, F.s));
+            set_vec(v, 0, y, hb_lo);
+            HIP_TRY(blas_zero(WL_F32, v, 2, F.s));
+        }
+        const double start2 = rn2, stop2 = std::max(P.inner_tol * P.inner_tol * start2, 0.25 * target2);
+        // s = M^+ D^+ rho, p = s
+        if ((st = apply_m(c, WL_OP_D, true, kappa, WL_F32, 18, 1, t, rho, nullptr, nullptr, 0, nullptr, F.s, nullptr)) ||
+            (st = apply_net(sv, t, true)) || (st = copy_lo(p, sv)))
+            return st;
+        double gam = 0.0;
+        if ((st = norm_full(F, WL_F32, sv, &gam))) return st;
+        bool breakdown = !(gam > 0.0) || !std::isfinite(gam);
+        rho2 = start2;
+        while (!breakdown && total < P.maxiter) {
+            // q = D M p, ||q||^2 fused into the operator's epilogue
+            if ((st = apply_net(t, p, false))) return st;
+            double q2 = 0.0;
+            {
+                long nblk = 0;
+                if ((st = apply_m(c, WL_OP_D, false, kappa, WL_F32, 18, 1, q, t, nullptr, (double *)c->buf[S_PARTIALS],
+                                  F.stride, nullptr, F.s, &nblk)))
+                    return st;
+                if ((st = reduce_to_host(c, 1, F.stride, nblk, &q2, F.s))) return st;
+            }
+            if (!(q2 > 0.0) || !std::isfinite(q2)) {
+                breakdown = true;
+                break;
+            }
+            const double alpha = gam / q2;
+            if ((st = axpby(alpha, p, 1.0, y, nullptr)) || (st = axpby(-alpha, q, 1.0, rho, &rho2))) return st;
+            ++total;
+            if (!std::isfinite(rho2)) {
+                breakdown = true;
+                break;
+            }
+            if (rho2 <= stop2) break;
+            if ((st = apply_m(c, WL_OP_D, true, kappa, WL_F32, 18, 1, t, rho, nullptr, nullptr, 0, nullptr, F.s,
+                              nullptr)) ||
+                (st = apply_net(sv, t, true)))
+                return st;
+            double gam1 = 0.0;
+            if ((st = norm_full(F, WL_F32, sv, &gam1))) return st;
+            if (!std::isfinite(gam1)) {
+                breakdown = true;
+                break;
+            }
+            if ((st = axpby(1.0, sv, gam1 / gam, p, nullptr))) return st;
+            gam = gam1;
+        }
+        // x += M y in FP64, then the FP64 residual
+        if ((st = apply_net(t, y, false))) return st;
+        {
+            VecArgs v = vec_args(c, WL_F64, 1);
+            set_vec(v, 0, t, hb_lo);
+            set_vec(v, 1, x, hb_hi);
+            HIP_TRY(blas_convert(WL_F64, WL_F32, true, v, 2, F.s));
+        }
+        const double prev = rn2;
+        if ((st = system_residual(F, kappa, x, b, rhi, thi, &rn2))) return st;
+        ++cycles;
+        if (breakdown || !std::isfinite(rn2)) {
+            failed = rn2 > target2 || !std::isfinite(rn2);
+            break;
+        }
+        if (rn2 > P.stagnation * P.stagnation * prev) {
+            if (++stagnant >= 2) {
+                failed = true;
+                break;
+            }
+        } else {
+            stagnant = 0;
+        }
+    }
+    out.iters = total;
+    out.restarts = cycles;
+    out.rel_resid = std::sqrt(rho2 / b2);
+    out.true_rel_resid = std::sqrt(rn2 / b2);
+    wl_status result = failed ? WL_NOT_CONVERGED : WL_OK;
+    if (failed && P.fallback) {
+        wl_solver_params Q;
+        wl_solver_params_default(&Q);
+        Q.tol = P.tol;
+        wl_solver_info fi{};
+        wl_status fs = wl_cgnr_solve(c, x, b, kappa, &Q, &fi, stream);
+        if (fs < 0) return fs;
+        out.fallback = 1;
+        out.fallback_iters = fi.iters;
+        out.true_rel_resid = fi.true_rel_resid;
+        result = fs;
+    }
+    out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = out;
+    if (result == WL_NOT_CONVERGED) fail(WL_NOT_CONVERGED, "preconditioned CGNR did not reach the tolerance");
+    return result;
+}
+
 extern "C" wl_status wl_fgcr_solve(wl_ctx *c, void *x, const void *b, double kappa, const wl_ptc *net,
                                    const wl_fgcr_params *params, wl_solver_info *info, void *stream) {
     g_err.clear();
@@ -1569,7 +1768,7 @@ extern "C" wl_status wl_fgcr_solve(wl_ctx *c, void *x, const void *b, double kap
         (st = ensure_buf(c, S_GCR_W, (size_t)m * full_lo)) ||
         (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * F.stride)))
         return st;
-    if (net && (st = ensure_buf(c, S_PTC_H, 2 * half_bytes(c, WL_F32, net->channels)))) return st;
+    if (net && (st = ensure_buf(c, S_PTC_H, ptc_field_bytes(c, net->channels)))) return st;
     char *rlo = (char *)c->buf[S_GCR_X], *xc = rlo + full_lo;
     char *Z = (char *)c->buf[S_GCR_Z], *Wv = (char *)c->buf[S_GCR_W];
     void *rhi = c->buf[S_GCR_R], *thi = c->buf[S_GCR_TMP];

@@ -8,15 +8,19 @@ namespace wl {
 constexpr int PTC_NPATH = 9;
 constexpr int PTC_MAXC = 16;  // most channels of a layer
 
-// One PTC layer on FULL FP32 fields whose points are (site, channel), channel
-// fastest:  out[a](x) = sum_b sum_p W_p^{ab} (T_p in[b])(x),  or its adjoint
+// One PTC layer on FULL FP32 fields.  A field of C channels is C consecutive
+// single-rhs FULL fields (channel-major: channel b, parity par starts at byte
+// (2 b + par) * half), so the threads of a wave, one per site, read and write
+// consecutive points of each channel.
+//   out[a](x) = sum_b sum_p W_p^{ab} (T_p in[b])(x),  or its adjoint
 // g_in[b] = sum_a sum_p T_p^+ W_p^{ab +} g_out[a]  (adjoint != 0; then
 // `cout`/`cin` are the channel counts of the adjoint map and the weights keep
 // the layout of the forward layer).
 struct PtcArgs {
     Geom g;
-    const void *in[2];
-    void *out[2];
+    const char *in;
+    char *out;
+    size_t half;        // bytes of one parity of one channel
     const void *gauge;  // FP32 18-real links
     size_t slab_bytes;
     const void *w;      // [9][cout_f][cin_f][4][4] complex, FP32 or BF16 (re, im interleaved)
@@ -29,11 +33,13 @@ hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16_weights, hipStream_t s);
 
 // Weight gradient dL/d conj(W_p^{ab}) = sum_x sum_colour g[a](x) (T_p in[b])(x)^+
 // for all (p, a, b): per-chunk FP32 partials, then an FP64 sum over chunks that
-// is stored to (or added to) grad[p][a][b][4][4] (complex double).
+// is stored to (or added to) grad[p][a][b][4][4] (complex double).  Channel-major
+// fields as for the layer.
 struct PtcGradArgs {
     Geom g;
-    const void *gout[2];  // cout channels
-    const void *in[2];    // cin channels
+    const char *gout;     // cout channels
+    const char *in;       // cin channels
+    size_t half;
     const void *gauge;
     size_t slab_bytes;
     int cout, cin;

@@ -6,7 +6,8 @@
 // followed by a complex 4x4 spin matrix per (output, input) channel pair.  The
 // spin matrices commute with the transports, so a thread first mixes the input
 // channels at the neighbour site and then transports the mixed spinor once per
-// path.  Fields are FP32 (points = (site, channel), channel fastest); weights
+// path.  Fields are FP32, channel-major (each channel a FULL field, so a
+// wave's threads, one per site, read consecutive points of a channel); weights
 // are read from BF16 (or FP32) and staged as FP32 in LDS; accumulation is FP32.
 #include "wl_ptc.h"
 
@@ -95,38 +96,47 @@ __device__ __forceinline__ float2 ptc_weight(const void *w, long idx) {
 
 template <bool BF16W>
 __global__ void __launch_bounds__(256) k_ptc_layer(const PtcArgs a) {
-    // weights of the whole layer in LDS (at most 9 x 16 x 16 matrices is too
-    // many; layers here have cout * cin <= PTC_MAXC)
+    // the 9 x cin spin matrices of this block's output channel, as FP32 in LDS
     __shared__ float2 wl[PTC_NPATH * PTC_MAXC * 16];
-    const int nw = PTC_NPATH * a.cout * a.cin * 16;
-    for (int k = threadIdx.x; k < nw; k += blockDim.x) wl[k] = ptc_weight<BF16W>(a.w, k);
+    const int o = blockIdx.z, par = blockIdx.y;
+    const int nw = PTC_NPATH * a.cin * 16;
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) {
+        const int q = k / (a.cin * 16), rem = k - q * a.cin * 16, b = rem >> 4, st = rem & 15;
+        // spin matrix M[s][t] of (path q, input b): forward W_q^{ob}; adjoint (W_p^{bo})^+ with p the
+        // reverse path, stored here already transposed and conjugated
+        float2 e;
+        if (a.adjoint) {
+            const int s_ = st >> 2, t_ = st & 3;
+            e = ptc_weight<BF16W>(a.w, ((long)(ptc_reverse(q) * a.cin + b) * a.cout + o) * 16 + 4 * t_ + s_);
+            e.y = -e.y;
+        } else {
+            e = ptc_weight<BF16W>(a.w, ((long)(q * a.cout + o) * a.cin + b) * 16 + st);
+        }
+        wl[k] = e;
+    }
     __syncthreads();
-    const int par = blockIdx.y;
-    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= a.vh * a.cout) return;
-    const int i = (int)(gid / a.cout), o = (int)(gid - (long)i * a.cout);
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.vh) return;
     int c[4];
-    eo_coords(a.g, i, par, c);
+    eo_coords(a.g, (int)i, par, c);
     cpx<float> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
     for (int q = 0; q < PTC_NPATH; ++q) {
-        const PathHop h = ptc_hop(a.g, i, par, c, q);
+        const PathHop h = ptc_hop(a.g, (int)i, par, c, q);
         cpx<float> chi[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) chi[k] = {0.f, 0.f};
         for (int b = 0; b < a.cin; ++b) {
             cpx<float> v[12];
-            SpinorIO<WL_F32>::load(a.in[h.npar], (long)h.j * a.cin + b, v);
-            // spin matrix M[s][t]: forward W_q^{ob}; adjoint (W_p^{bo})^+ with p the reverse path
-            const float2 *m = a.adjoint ? &wl[((ptc_reverse(q) * a.cin + b) * a.cout + o) * 16]
-                                        : &wl[((q * a.cout + o) * a.cin + b) * 16];
+            SpinorIO<WL_F32>::load(a.in + (2 * (size_t)b + h.npar) * a.half, h.j, v);
+            const float2 *m = &wl[(q * a.cin + b) * 16];
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const float2 e = a.adjoint ? m[4 * t + s] : m[4 * s + t];
-                    const cpx<float> ms = {e.x, a.adjoint ? -e.y : e.y};
+                    const float2 e = m[4 * s + t];
+                    const cpx<float> ms = {e.x, e.y};
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) chi[3 * s + cc] = cfma(ms, v[3 * t + cc], chi[3 * s + cc]);
                 }
@@ -136,12 +146,12 @@ __global__ void __launch_bounds__(256) k_ptc_layer(const PtcArgs a) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = acc[k] + t[k];
     }
-    SpinorIO<WL_F32>::store(a.out[par], gid, acc);
+    SpinorIO<WL_F32>::store(a.out + (2 * (size_t)o + par) * a.half, i, acc);
 }
 
 hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16, hipStream_t s) {
     if (a.cout < 1 || a.cin < 1 || a.cout * a.cin > PTC_MAXC) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((a.vh * a.cout + 255) / 256), 2);
+    dim3 grid((unsigned)((a.vh + 255) / 256), 2, (unsigned)a.cout);
     if (bf16) hipLaunchKernelGGL(k_ptc_layer<true>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_ptc_layer<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
@@ -166,9 +176,9 @@ __global__ void __launch_bounds__(256) k_ptc_wgrad(const PtcGradArgs a) {
         eo_coords(a.g, i, par, c);
         const PathHop h = ptc_hop(a.g, i, par, c, p);
         cpx<float> v[12], t[12], gg[12];
-        SpinorIO<WL_F32>::load(a.in[h.npar], (long)h.j * a.cin + b, v);
+        SpinorIO<WL_F32>::load(a.in + (2 * (size_t)b + h.npar) * a.half, h.j, v);
         ptc_transport(a.g, a.gauge, a.slab_bytes, h, v, t);
-        SpinorIO<WL_F32>::load(a.gout[par], (long)i * a.cout + ao, gg);
+        SpinorIO<WL_F32>::load(a.gout + (2 * (size_t)ao + par) * a.half, i, gg);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll

@@ -62,11 +62,12 @@ def harvest(lat, sources, kappa, snapshots=SNAPSHOTS, tol=1e-12):
 
 def train(sets, net, epochs, lr=1e-3, log=None, loss="residual", kappa=None):
     """sets: list of (lattice, pairs).  One Adam step per lattice per epoch (its
-    pairs form the batch).  loss: "residual" (needs kappa) or "error".
+    pairs form the batch).  loss: "residual" (needs kappa), "error", or "both"
+    (their sum).
     Returns the loss of every step."""
-    if loss not in ("residual", "error"):
-        raise ValueError("loss must be 'residual' or 'error'")
-    if loss == "residual" and kappa is None:
+    if loss not in ("residual", "error", "both"):
+        raise ValueError("loss must be 'residual', 'error' or 'both'")
+    if loss != "error" and kappa is None:
         raise ValueError("the residual-norm loss needs kappa")
     losses = []
     t0 = time.perf_counter()
@@ -74,9 +75,9 @@ def train(sets, net, epochs, lr=1e-3, log=None, loss="residual", kappa=None):
         for lat, pairs in sets:
             inv = 1.0 / len(pairs)
             for r, e in pairs:
-                if loss == "residual":
+                if loss != "error":
                     W.wl_ptc_accumulate_residual(lat.ctx, net, r, kappa, inv)
-                else:
+                if loss != "residual":
                     W.wl_ptc_accumulate(lat.ctx, net, r, e, inv)
             losses.append(W.wl_ptc_step(net, lr))
         if log is not None and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):

@@ -79,6 +79,16 @@ class FgcrParams(ctypes.Structure):
     ]
 
 
+class PcgnrParams(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int),
+        ("inner_tol", ctypes.c_double),
+        ("fallback", ctypes.c_int),
+        ("stagnation", ctypes.c_double),
+    ]
+
+
 _vp = ctypes.c_void_p
 _ip = ctypes.POINTER(ctypes.c_int)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -108,6 +118,9 @@ _SIGS = {
     "wl_cgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(SolverParams),
                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_params_default": (None, [ctypes.POINTER(FgcrParams)]),
+    "wl_pcgnr_params_default": (None, [ctypes.POINTER(PcgnrParams)]),
+    "wl_pcgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(PcgnrParams),
+                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(FgcrParams),
                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_ptc_create": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.POINTER(_vp)]),
@@ -302,6 +315,21 @@ def wl_fgcr_solve(ctx, x, b, kappa, net=None, params: FgcrParams | None = None, 
     info = SolverInfo()
     st = _check(lib().wl_fgcr_solve(ctx, _ptr(x), _ptr(b), float(kappa), net, ctypes.byref(p), ctypes.byref(info),
                                     _stream(stream)))
+    return st, info.as_dict()
+
+
+def wl_pcgnr_params_default() -> PcgnrParams:
+    p = PcgnrParams()
+    lib().wl_pcgnr_params_default(ctypes.byref(p))
+    return p
+
+
+def wl_pcgnr_solve(ctx, x, b, kappa, net=None, params: PcgnrParams | None = None, stream=None):
+    """CG on the normal equations of D M y = b, x = M y, M the PTC network `net` (None: M = 1)."""
+    p = params if params is not None else wl_pcgnr_params_default()
+    info = SolverInfo()
+    st = _check(lib().wl_pcgnr_solve(ctx, _ptr(x), _ptr(b), float(kappa), net, ctypes.byref(p), ctypes.byref(info),
+                                     _stream(stream)))
     return st, info.as_dict()
 
 

@@ -78,3 +78,23 @@ def test_fgcr_with_the_trained_network(trained):
     assert res["trained"] < res["initial"] and res["trained"] < res["none"]
     W.wl_ptc_destroy(fresh)
     lat.close()
+
+
+def test_preconditioned_cgnr_with_the_trained_network(trained):
+    _, _, net, _ = trained
+    u = synth.su3_links(DIMS, 0.2, 620)
+    lat = W.Lattice.create(u, AP)
+    b = synth.gaussian_spinor(DIMS, seed=621)
+    res = {}
+    for name, m in (("none", None), ("trained", net)):
+        x = lat.new(W.WL_FULL)
+        p = W.wl_pcgnr_params_default()
+        p.fallback = 0
+        st, info = W.wl_pcgnr_solve(lat.ctx, x, lat.pack(b), KAPPA, m, p)
+        xs = lat.unpack(x).reshape(b.shape)
+        r = np.linalg.norm(orc.dirac(xs, u, KAPPA, AP) - b) / np.linalg.norm(b)
+        assert st == W.WL_OK and r <= 1.05e-10, (name, st, r)
+        res[name] = info["iters"]
+    print("preconditioned CGNR iterations:", res)
+    assert res["trained"] < res["none"]
+    lat.close()

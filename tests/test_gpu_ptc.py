@@ -74,18 +74,15 @@ def lattice(dims, seed, phases=AP, eps=0.5):
 
 
 def channels(lat, fields):
-    """list of canonical fields -> internal FULL FP32 field with len(fields) channels"""
-    n = len(fields)
-    stack = np.stack([f32(f).reshape(-1, 4, 3) for f in fields])
-    return lat.pack(stack, W.WL_FULL, W.WL_F32, n)
+    """list of canonical fields -> internal channel-major FP32 field (one FULL field per channel)"""
+    return torch.cat([lat.pack(f32(f), W.WL_FULL, W.WL_F32) for f in fields])
 
 
 def unchannels(lat, internal, n, dims):
-    a = lat.unpack(internal, W.WL_FULL, W.WL_F32, n)
     lx, ly, lz, lt = dims
-    if n == 1:
-        return [a.reshape(lt, lz, ly, lx, 4, 3)]
-    return [a[k].reshape(lt, lz, ly, lx, 4, 3) for k in range(n)]
+    per = internal.numel() // n
+    return [lat.unpack(internal[k * per:(k + 1) * per], W.WL_FULL, W.WL_F32).reshape(lt, lz, ly, lx, 4, 3)
+            for k in range(n)]
 
 
 DIMS = (4, 6, 4, 8)
@@ -98,14 +95,14 @@ def test_layer_forward_and_adjoint(cout, cin):
     w = random_weights(cout, cin, 3, 0.3)
     wd, w32 = dev_weights(w)
     ins = [synth.gaussian_spinor(DIMS, seed=10 + b) for b in range(cin)]
-    out = lat.new(W.WL_FULL, W.WL_F32, cout)
+    out = torch.cat([lat.new(W.WL_FULL, W.WL_F32) for _ in range(cout)])
     W.wl_ptc_layer(lat.ctx, out, channels(lat, ins), wd, cout, cin)
     want = ptc.layer([f32(f) for f in ins], w32, u, ph)
     got = unchannels(lat, out, cout, DIMS)
     assert rel(np.stack(got), np.stack(want)) < TOL32
     # adjoint: cout_f = cout, cin_f = cin; the adjoint launch maps cout -> cin channels
     gs = [synth.gaussian_spinor(DIMS, seed=20 + a) for a in range(cout)]
-    gin = lat.new(W.WL_FULL, W.WL_F32, cin)
+    gin = torch.cat([lat.new(W.WL_FULL, W.WL_F32) for _ in range(cin)])
     W.wl_ptc_layer(lat.ctx, gin, channels(lat, gs), wd, cin, cout, adjoint=True)
     want = ptc.layer_adjoint([f32(g) for g in gs], w32, u, ph)
     assert rel(np.stack(unchannels(lat, gin, cin, DIMS)), np.stack(want)) < TOL32
@@ -263,3 +260,36 @@ def test_fgcr_falls_back_to_cg_on_a_broken_network():
     st, info = W.wl_fgcr_solve(lat.ctx, lat.new(W.WL_FULL), lat.pack(b), kappa, net, p)
     assert st == W.WL_NOT_CONVERGED and info["fallback"] == 0
     W.wl_ptc_destroy(net)
+
+
+@pytest.mark.parametrize("use_net", [False, True])
+@pytest.mark.parametrize("dims,kappa,eps", [((4, 4, 4, 8), 0.12, 0.5), ((8, 8, 8, 8), 0.137, 0.2)])
+def test_preconditioned_cgnr_solves_the_system(use_net, dims, kappa, eps):
+    """CG on the normal equations of D M: converges also at kappa = 0.137 with eps = 0.2
+    links, where D's spectrum surrounds the origin (restarted GCR stalls there)."""
+    u, lat = lattice(dims, 56, AP, eps)
+    b = synth.gaussian_spinor(dims, seed=57)
+    w1, w2 = synth.ptc_weights(8, seed=530)
+    net = W.wl_ptc_create(w1, w2) if use_net else None
+    x = lat.new(W.WL_FULL)
+    p = W.wl_pcgnr_params_default()
+    p.fallback = 0
+    st, info = W.wl_pcgnr_solve(lat.ctx, x, lat.pack(b), kappa, net, p)
+    r = system_resid(u, kappa, lat.unpack(x).reshape(b.shape), b)
+    print("net", use_net, info, "oracle residual", r)
+    assert st == W.WL_OK and info["fallback"] == 0 and info["restarts"] >= 2
+    assert r <= 1.05e-10 and info["true_rel_resid"] <= 1e-10
+    if net:
+        W.wl_ptc_destroy(net)
+
+
+def test_preconditioned_cgnr_zero_source_and_bad_parameters():
+    u, lat = lattice((4, 4, 4, 8), 58, AP)
+    x = lat.pack(synth.gaussian_spinor((4, 4, 4, 8), seed=59))
+    st, info = W.wl_pcgnr_solve(lat.ctx, x, lat.new(W.WL_FULL), 0.12)
+    assert st == W.WL_OK and not torch.any(x != 0)
+    p = W.wl_pcgnr_params_default()
+    p.inner_tol = 1.5
+    with pytest.raises(W.WilsonError):
+        W.wl_pcgnr_solve(lat.ctx, lat.new(W.WL_FULL), lat.pack(synth.gaussian_spinor((4, 4, 4, 8), seed=60)), 0.12,
+                         None, p)

@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
-    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned"], default="eo-cg",
+    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch"], default="eo-cg",
                     help="eo-cg: the headline (24^3x48 FP64 e/o CG); mixed: 32^3x64 FP64 vs mixed-precision CG; "
                          "propagator: 12 point sources, multi-RHS vs sequential; learned: train the PTC "
                          "preconditioner on 16^3x32 fields and compare FGCR with plain FP64 CG on 32^3x64")
@@ -176,6 +176,8 @@ def main():
         return run_propagator(args)
     if args.workload == "learned":
         return run_learned(args)
+    if args.workload == "batch":
+        return run_batch(args)
     return run_eo_cg(args)
 
 
@@ -401,6 +403,126 @@ def run_propagator(args):
                       "dslash_12rhs_f32_18": {"us": round(us, 2), "algorithmic_GBps": round(gbs, 1),
                                                "bytes_per_site": 576 + 12 * 192}}))
     lat.close()
+
+
+def run_batch(args):
+    """Uneven batch: 16^3x32, 24^3x48 and 32^3x64 (links exp(0.2iH), seeds 411-413), 4 Gaussian
+    right-hand sides each (seeds 421-423), kappa 0.135, e/o CG on the normal equations to 1e-10,
+    FP32 inner with FP64 reliable updates and a graph-captured iteration: all three systems in
+    one batched solve (one persistent launch per hopping stage) vs the three solved one after
+    another; plus the persistent D_hat launch over all three against three separate launches."""
+    import numpy as np
+    import torch
+    from paper_1405_0700_amd import synth
+    from paper_1405_0700_amd import wilson as W
+    kappa, nrhs, ph = 0.135, 4, (1, 1, 1, -1)
+    sysdims = [(16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
+    log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    lats, etas = [], []
+    for k, dims in enumerate(sysdims):
+        lats.append(W.Lattice.create(synth.su3_links(dims, 0.2, 411 + k), ph))
+        stack = np.stack([synth.gaussian_spinor(dims, seed=1000 * (421 + k) + r).reshape(-1, 4, 3)
+                          for r in range(nrhs)])
+        etas.append(lats[-1].pack(stack, W.WL_FULL, W.WL_F64, nrhs))
+    log("inputs ready")
+    batch = W.wl_batch_create([l.ctx for l in lats])
+    singles = [EoSolver(l, e, kappa, 1e-10, nrhs=nrhs) for l, e in zip(lats, etas)]
+    for s_ in singles:
+        s_.set_precision(W.WL_F32, 18)
+        s_.params.use_graph = 1
+    params = W.wl_solver_params_default()
+    params.prec, params.recon, params.use_graph, params.tol = W.WL_F32, 18, 1, 1e-10
+
+    def batched():
+        for s_ in singles:
+            s_.xe.zero_()
+            W.wl_eo_prepare(s_.lat.ctx, s_.bhat, s_.Be, s_.Bo, kappa, nrhs=nrhs)
+            W.wl_dirac_apply(s_.lat.ctx, s_.rhs, s_.bhat, W.WL_OP_DHAT, True, kappa, nrhs=nrhs)
+        st, info = W.wl_batch_cg_solve(batch, [s_.xe for s_ in singles], [s_.rhs for s_ in singles],
+                                       W.WL_OP_DHAT, [kappa] * 3, nrhs, params)
+        for s_ in singles:
+            W.wl_eo_reconstruct(s_.lat.ctx, s_.xo, s_.xe, s_.Bo, kappa, nrhs=nrhs)
+        return st, info
+
+    def sequential():
+        return [s_.step() for s_ in singles]
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / args.steps, out
+
+    def true_resid():
+        """largest over the systems of ||eta - D x|| / ||eta|| (FP64, all right-hand sides of a system together)"""
+        worst = 0.0
+        for s_, e in zip(singles, etas):
+            x = torch.cat([s_.xe, s_.xo])
+            d = s_.lat.new(W.WL_FULL, W.WL_F64, nrhs)
+            W.wl_dirac_apply(s_.lat.ctx, d, x, W.WL_OP_D, False, kappa, nrhs=nrhs)
+            W.wl_blas_axpy(s_.lat.ctx, -1.0, e, d, W.WL_FULL, W.WL_F64, nrhs)
+            rn = W.wl_blas_norm2(s_.lat.ctx, d, W.WL_FULL, W.WL_F64, nrhs)
+            bn = W.wl_blas_norm2(s_.lat.ctx, e, W.WL_FULL, W.WL_F64, nrhs)
+            worst = max(worst, float(np.sqrt(rn / bn)))
+        return worst
+
+    res = {}
+    ms_seq, out_seq = timed(sequential)
+    res["sequential_ms"] = round(ms_seq, 2)
+    res["sequential_iters"] = [[i["iters"] for i in info] for _, info in out_seq]
+    res["sequential_worst_true_resid"] = true_resid()
+    log("sequential %.1f ms" % ms_seq)
+    default_launch = W.wl_batch_get_launch(batch)
+    ms_b, (st, info) = timed(batched)
+    res["batched_default_ms"] = round(ms_b, 2)
+    res["batched_default_launch"] = default_launch
+    res["batched_iters"] = [[i["iters"] for i in s] for s in info]
+    res["batched_worst_true_resid"] = true_resid()
+    log("batched (default launch %s) %.1f ms" % (default_launch, ms_b))
+    tuned, tuned_us, _ = W.wl_batch_autotune(batch, W.WL_F32, 18, nrhs)
+    ms_t, _ = timed(batched)
+    res["batched_tuned_ms"] = round(ms_t, 2)
+    res["batched_tuned_launch"] = tuned
+    res["batched_worst_true_resid_tuned"] = true_resid()
+    log("batched (tuned launch %s) %.1f ms" % (tuned, ms_t))
+    # the persistent D_hat over all three systems against three separate D_hat applications
+    ins = [l.new(W.WL_EVEN, W.WL_F32, nrhs) for l in lats]
+    for t_ in ins:
+        t_.copy_(torch.zeros_like(t_))
+    outs = [l.new(W.WL_EVEN, W.WL_F32, nrhs) for l in lats]
+    vhs = [l.volume // 2 for l in lats]
+    bytes_apply = sum(v * (2 * 576 + nrhs * (192 + 288)) for v in vhs)
+
+    def persistent():
+        W.wl_batch_dirac_apply(batch, outs, ins, W.WL_OP_DHAT, False, [kappa] * 3, W.WL_F32, 18, nrhs)
+
+    def separate():
+        for l, o, i_ in zip(lats, outs, ins):
+            W.wl_dirac_apply(l.ctx, o, i_, W.WL_OP_DHAT, False, kappa, W.WL_F32, 18, nrhs)
+
+    for name, fn in (("persistent", persistent), ("separate", separate)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 20 * 1e3
+        res["dhat_apply_" + name] = {"us": round(us, 2), "algorithmic_GBps": round(bytes_apply / us / 1e3, 1)}
+        log("%s D_hat over the three systems: %.1f us" % (name, us))
+    res["dhat_apply_bytes"] = bytes_apply
+    print(json.dumps({"metric": "uneven batch (16^3x32 + 24^3x48 + 32^3x64, 4 RHS each): batched vs sequential "
+                                "time-to-1e-10", "unit": "ms", "higher_is_better": False, "kappa": kappa,
+                      "precision": "FP32 inner, FP64 reliable updates, graph-captured iteration",
+                      "results": res, "speedup_tuned_vs_sequential": round(ms_seq / ms_t, 3)}))
+    W.wl_batch_destroy(batch)
 
 
 def run_learned(args):

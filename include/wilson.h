@@ -86,6 +86,7 @@ typedef enum { WL_OP_D = 0, WL_OP_DHAT = 1 } wl_op;
 
 typedef struct wl_ctx wl_ctx;
 typedef struct wl_ptc wl_ptc; /* learned preconditioner (see below) */
+typedef struct wl_batch wl_batch; /* several contexts solved together (see below) */
 
 /* ---------------------------------------------------------------- context */
 
@@ -120,7 +121,11 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *           keep the single-use link stream from evicting re-read spinors from
  *           L2, but also bypass the Infinity Cache); 0: off; -1: on when the
  *           launch's links and spinor fields exceed 200 MB
- * Results do not depend on block, swizzle, tchunk or nt; tps changes the
+ *   rpt     right-hand sides per thread: 1, 2, 3 or 4.  With rpt > 1 (and
+ *           tps = 1) a thread computes rpt consecutive right-hand sides of one
+ *           site and applies each link it loads to all of them; a launch whose
+ *           nrhs is not a multiple of rpt uses one point per thread.
+ * Results do not depend on block, swizzle, tchunk, nt or rpt; tps changes the
  * summation order of the 8 hops (rounding only).  Defaults are chosen per
  * precision by measurement (see wl_ctx_get_launch). */
 typedef struct {
@@ -129,6 +134,7 @@ typedef struct {
     int tps;
     int tchunk;
     int nt;
+    int rpt;
 } wl_launch;
 wl_status wl_ctx_set_launch(wl_ctx *ctx, wl_prec prec, const wl_launch *cfg);
 wl_status wl_ctx_get_launch(const wl_ctx *ctx, wl_prec prec, wl_launch *cfg);
@@ -358,6 +364,73 @@ void wl_pcgnr_params_default(wl_pcgnr_params *p);
  * restarts = outer cycles). */
 wl_status wl_pcgnr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, const wl_ptc *net,
                          const wl_pcgnr_params *params, wl_solver_info *info, void *stream);
+
+/* ---------------------------------------------------------------- batches of systems
+ *
+ * A batch groups 1..8 contexts on one device (lattices of any, also different,
+ * sizes, each with its own gauge field).  Their hopping-term launches are
+ * merged into ONE persistent launch per operator stage: the blocks of points
+ * of all systems form one work list, split into eight contiguous ranges (one
+ * per XCD, so that an XCD's L2 sees neighbouring tiles of one lattice), which
+ * a fixed grid of resident workgroups drains through atomic counters; the
+ * counters are left at zero for the next launch, so the launch can be
+ * replayed inside a graph.  The batch owns a non-blocking stream used for
+ * graph capture and a few bytes of device memory; it does not own the
+ * contexts, which must outlive it.  Calls on one batch are not thread-safe. */
+wl_status wl_batch_create(wl_ctx *const *ctxs, int nsys, wl_batch **out);
+wl_status wl_batch_destroy(wl_batch *batch);
+/* Persistent workgroups (a multiple of 8; default 3 per compute unit), points
+ * per tile (64..256, a multiple of 64; default 256) and non-temporal hints (1
+ * on, 0 off, -1 by working-set size, the default). */
+wl_status wl_batch_set_launch(wl_batch *batch, int workgroups, int block, int nt);
+wl_status wl_batch_get_launch(const wl_batch *batch, int *workgroups, int *block, int *nt);
+
+/* out[k] = M_k in[k] (M_k^+ if dagger) for every system k of the batch, M = D
+ * (FULL fields) or D_hat (EVEN fields), kappa[k] per system, all fields in
+ * precision prec with nrhs right-hand sides (same for every system).
+ * Asynchronous on `stream`. */
+wl_status wl_batch_dirac_apply(wl_batch *batch, void *const *out, const void *const *in, wl_op op, int dagger,
+                               const double *kappa, wl_prec prec, int recon, int nrhs, void *stream);
+
+/* CG on the normal equations M_k^+ M_k x[k] = b[k] of every system together
+ * (the independent solves of each system's nrhs right-hand sides run in
+ * lockstep: one persistent launch per hopping stage of an iteration, the
+ * scalar and vector steps per system).  Parameters as for wl_cg_solve (inner
+ * precision, FP64 reliable updates, use_graph: the lockstep iteration is
+ * captured in one graph on the batch's own stream and replayed).  A system
+ * whose right-hand sides have all converged drops out of the persistent
+ * launches.  info: nsys * nrhs entries, system-major.  Synchronous. */
+wl_status wl_batch_cg_solve(wl_batch *batch, void *const *x, const void *const *b, wl_op op, const double *kappa,
+                            int nrhs, const wl_solver_params *params, wl_solver_info *info, void *stream);
+
+/* Event timing of the batch's persistent launches (as wl_timing_enable /
+ * wl_timing_read for a context, all launches of the batch together). */
+wl_status wl_batch_timing_enable(wl_batch *batch, int enable);
+wl_status wl_batch_timing_read(wl_batch *batch, int *count, double *total_ms);
+
+/* ---------------------------------------------------------------- autotuner
+ *
+ * Times the hopping-term launch the solvers use (out = x - kappa H in over
+ * both parities, on scratch fields the call allocates and frees) for every
+ * launch shape of the sweep -- block 64/128/256, one or two threads per point
+ * (FP64/FP32 storage) or 2-4 right-hand sides per thread (when nrhs allows),
+ * XCD swizzle off/on, processing order by e/o index or by chunks of 2 or 4
+ * time slices, non-temporal hints off/on -- with HIP
+ * events (average of 5 launches after a warm-up), picks the fastest and makes
+ * it the context's launch configuration for `prec`.  Results are cached in
+ * the process and, if cache_path is not NULL, appended to that text file
+ * (one line per key: GPU architecture, extents, prec, recon, nrhs); a later
+ * call with a cached key applies the entry without timing (*from_cache = 1).
+ * chosen, best_us (microseconds per launch) and from_cache may be NULL.
+ * Synchronous. */
+wl_status wl_autotune(wl_ctx *ctx, wl_prec prec, int recon, int nrhs, const char *cache_path, wl_launch *chosen,
+                      double *best_us, int *from_cache);
+/* The same for a batch: persistent workgroups (1..8 per compute unit, scaled
+ * by 256 / block), points per tile 64/128/256 and non-temporal hints, timed on
+ * the persistent launch of D over every system; the result becomes the
+ * batch's launch configuration. */
+wl_status wl_batch_autotune(wl_batch *batch, wl_prec prec, int recon, int nrhs, const char *cache_path,
+                            int *workgroups, int *block, int *nt, double *best_us, int *from_cache);
 
 /* ---------------------------------------------------------------- kernel timing */
 

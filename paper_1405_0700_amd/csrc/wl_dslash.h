@@ -35,6 +35,8 @@ struct LaunchCfg {
                        // slices, each walked with z slowest
     int nt = -1;       // non-temporal link loads / output stores: 1 on, 0 off,
                        // -1 on when the launch's working set exceeds 200 MB
+    int rpt = 1;       // right-hand sides per thread (each link load reused for all
+                       // of them); used when nrhs % rpt == 0 and tps == 1
 };
 
 // whether a launch uses the non-temporal hints
@@ -45,10 +47,41 @@ bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int npari
 hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int nparity,
                       const LaunchCfg &cfg, hipStream_t stream);
 
+// Persistent launch over the tiles of several systems (one-thread-per-point
+// body).  sys[k] is filled like a single launch's HopArgs (out_par0 = first
+// output parity); tiles of system k: per_par[k] blocks of `block` points per
+// output parity, np[k] parities; start[k] = first tile of system k in the
+// concatenated list, start[nsys] = ntiles.  counter: 9 ints, each on its own
+// 128-byte line (stride 32), zero before the first launch; the kernel leaves
+// them zero.
+constexpr int BATCH_MAX = 8;
+struct BatchArgs {
+    HopArgs sys[BATCH_MAX];
+    long start[BATCH_MAX + 1];
+    long per_par[BATCH_MAX];
+    int nsys;
+    long ntiles;
+    int *counter;
+};
+// nwg: persistent workgroups (a multiple of 8); epi without EPI_NORM alone
+hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, BatchArgs &B, int nwg, int block,
+                            hipStream_t stream);
+
 // threads per point actually used for a storage precision
 int effective_tps(int prec, const LaunchCfg &cfg);
 
 // number of blocks per parity for a given configuration
 inline long hop_blocks(long npts, int block, int tps = 1) { return (npts * tps + block - 1) / block; }
+
+// right-hand sides per thread a launch of nrhs right-hand sides actually uses
+inline int effective_rpt(const LaunchCfg &cfg, int nrhs, int tps) {
+    return cfg.rpt > 1 && tps == 1 && nrhs % cfg.rpt == 0 ? cfg.rpt : 1;
+}
+
+// blocks per parity of a hopping launch (npts points of nrhs right-hand sides)
+inline long hop_launch_blocks(int tps, const LaunchCfg &cfg, long npts, int nrhs) {
+    const int r = effective_rpt(cfg, nrhs, tps);
+    return r > 1 ? hop_blocks(npts / r, cfg.block, 1) : hop_blocks(npts, cfg.block, tps);
+}
 
 }  // namespace wl

@@ -1,0 +1,594 @@
+// Device code of the hopping-term kernels (included by the translation units
+// that instantiate them).
+#pragma once
+
+#include "wl_dslash.h"
+
+
+namespace wl {
+
+// -i a
+template <typename T> __device__ __forceinline__ cpx<T> mi(cpx<T> a) { return {a.im, -a.re}; }
+
+// h = upper + S * A_mu * lower for both upper spin rows, colour c.
+// A_x = -i s1, A_y = -i s2, A_z = -i s3, A_t = -1.
+template <typename T, int MU, int S>
+__device__ __forceinline__ void project(const cpx<T> f[12], cpx<T> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> u0 = f[c], u1 = f[3 + c], l0 = f[6 + c], l1 = f[9 + c];
+        if constexpr (MU == 0) {  // A lo = (-i l1, -i l0)
+            h[c] = S > 0 ? u0 + mi(l1) : u0 - mi(l1);
+            h[3 + c] = S > 0 ? u1 + mi(l0) : u1 - mi(l0);
+        } else if constexpr (MU == 1) {  // A lo = (-l1, l0)
+            h[c] = S > 0 ? u0 - l1 : u0 + l1;
+            h[3 + c] = S > 0 ? u1 + l0 : u1 - l0;
+        } else if constexpr (MU == 2) {  // A lo = (-i l0, i l1)
+            h[c] = S > 0 ? u0 + mi(l0) : u0 - mi(l0);
+            h[3 + c] = S > 0 ? u1 + ti(l1) : u1 - ti(l1);
+        } else {  // A lo = (-l0, -l1)
+            h[c] = S > 0 ? u0 - l0 : u0 + l0;
+            h[3 + c] = S > 0 ? u1 - l1 : u1 + l1;
+        }
+    }
+}
+
+// acc_up += v ; acc_lo += S * A_mu^+ v.
+// A_x^+ v = (i v1, i v0), A_y^+ v = (v1, -v0), A_z^+ v = (i v0, -i v1), A_t^+ v = -v.
+template <typename T, int MU, int S>
+__device__ __forceinline__ void accumulate(cpx<T> acc[12], const cpx<T> v[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> v0 = v[c], v1 = v[3 + c];
+        acc[c] = acc[c] + v0;
+        acc[3 + c] = acc[3 + c] + v1;
+        cpx<T> w0, w1;
+        if constexpr (MU == 0) {
+            w0 = ti(v1);
+            w1 = ti(v0);
+        } else if constexpr (MU == 1) {
+            w0 = v1;
+            w1 = -v0;
+        } else if constexpr (MU == 2) {
+            w0 = ti(v0);
+            w1 = mi(v1);
+        } else {
+            w0 = -v0;
+            w1 = -v1;
+        }
+        if constexpr (S > 0) {
+            acc[6 + c] = acc[6 + c] + w0;
+            acc[9 + c] = acc[9 + c] + w1;
+        } else {
+            acc[6 + c] = acc[6 + c] - w0;
+            acc[9 + c] = acc[9 + c] - w1;
+        }
+    }
+}
+
+// v = U h (FWD) or U^+ h (backward), both spin rows
+template <typename T, bool FWD>
+__device__ __forceinline__ void su3_mul2(const cpx<T> u[9], const cpx<T> h[6], cpx<T> v[6]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cpx<T> r;
+            if constexpr (FWD) {
+                r = cmul(u[3 * i], h[3 * s]);
+                r = cfma(u[3 * i + 1], h[3 * s + 1], r);
+                r = cfma(u[3 * i + 2], h[3 * s + 2], r);
+            } else {
+                r = cjmul(u[i], h[3 * s]);
+                r = cjfma(u[3 + i], h[3 * s + 1], r);
+                r = cjfma(u[6 + i], h[3 * s + 2], r);
+            }
+            v[3 * s + i] = r;
+        }
+}
+
+template <int SP, int GP, int RECON, bool DAG, bool NT, int MU, bool FWD>
+__device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs,
+                                    cpx<typename SpinorIO<SP>::real> acc[12]) {
+    using T = typename SpinorIO<SP>::real;
+    const Geom &g = a.g;
+    int j;
+    bool wrap;
+    if constexpr (MU == 0) {
+        int x = c[0] + (FWD ? 1 : -1);
+        wrap = FWD ? (x == g.L[0]) : (x < 0);
+        if (wrap) x = FWD ? 0 : g.L[0] - 1;
+        j = (i - xh) + (x >> 1);
+    } else {
+        const int stride = MU == 1 ? g.sy : (MU == 2 ? g.sz : g.st);
+        wrap = FWD ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
+        j = FWD ? i + stride : i - stride;
+        if (wrap) j += FWD ? -g.L[MU] * stride : g.L[MU] * stride;
+    }
+    // Forward hop (H): (1 - gamma) -> S = -1; backward: (1 + gamma) -> S = +1; H^+ swaps them.
+    constexpr int S = (FWD != DAG) ? -1 : 1;
+    cpx<T> f[12], h[6], u[9], v[6];
+    SpinorIO<SP>::load(a.in[1 - par], (long)j * a.nrhs + rhs, f);
+    const int lpar = FWD ? par : 1 - par;
+    const char *slab = (const char *)a.gauge + (size_t)(lpar * 4 + MU) * a.slab_bytes;
+    LinkIO<GP, RECON>::template load<NT>(slab, FWD ? i : j, u);
+    project<T, MU, S>(f, h);
+    su3_mul2<T, FWD>(u, h, v);
+    if (wrap && ((g.phase_mask >> MU) & 1)) {
+        const cpx<T> z = {(T)g.zr[MU], FWD ? (T)g.zi[MU] : -(T)g.zi[MU]};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = cmul(z, v[k]);
+    }
+    accumulate<T, MU, S>(acc, v);
+}
+
+// The same hop for R consecutive right-hand sides of one site: the link is
+// loaded (and reconstructed) once and applied to all R neighbour spinors.
+template <int SP, int GP, int RECON, bool DAG, bool NT, int MU, bool FWD, int R>
+__device__ __forceinline__ void hop_r(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs0,
+                                      cpx<typename SpinorIO<SP>::real> (&acc)[R][12]) {
+    using T = typename SpinorIO<SP>::real;
+    const Geom &g = a.g;
+    int j;
+    bool wrap;
+    if constexpr (MU == 0) {
+        int x = c[0] + (FWD ? 1 : -1);
+        wrap = FWD ? (x == g.L[0]) : (x < 0);
+        if (wrap) x = FWD ? 0 : g.L[0] - 1;
+        j = (i - xh) + (x >> 1);
+    } else {
+        const int stride = MU == 1 ? g.sy : (MU == 2 ? g.sz : g.st);
+        wrap = FWD ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
+        j = FWD ? i + stride : i - stride;
+        if (wrap) j += FWD ? -g.L[MU] * stride : g.L[MU] * stride;
+    }
+    constexpr int S = (FWD != DAG) ? -1 : 1;
+    cpx<T> u[9];
+    const int lpar = FWD ? par : 1 - par;
+    const char *slab = (const char *)a.gauge + (size_t)(lpar * 4 + MU) * a.slab_bytes;
+    LinkIO<GP, RECON>::template load<NT>(slab, FWD ? i : j, u);
+    const bool ph = wrap && ((g.phase_mask >> MU) & 1);
+    const cpx<T> z = {(T)g.zr[MU], FWD ? (T)g.zi[MU] : -(T)g.zi[MU]};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        cpx<T> f[12], h[6], v[6];
+        SpinorIO<SP>::load(a.in[1 - par], (long)j * a.nrhs + rhs0 + r, f);
+        project<T, MU, S>(f, h);
+        su3_mul2<T, FWD>(u, h, v);
+        if (ph) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) v[k] = cmul(z, v[k]);
+        }
+        accumulate<T, MU, S>(acc[r], v);
+    }
+}
+
+// ---- split variant: the direction of the hop (forward / backward) is a
+// per-lane runtime value, so that both halves of a wavefront run the same
+// instruction stream; the projector sign becomes a runtime +-1 and the
+// backward link is transposed and conjugated by selects.
+
+// h = upper + s * A_mu * lower
+template <typename T, int MU>
+__device__ __forceinline__ void project_rt(const cpx<T> f[12], T s, cpx<T> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> u0 = f[c], u1 = f[3 + c], l0 = f[6 + c], l1 = f[9 + c];
+        cpx<T> a0, a1;
+        if constexpr (MU == 0) {
+            a0 = mi(l1);
+            a1 = mi(l0);
+        } else if constexpr (MU == 1) {
+            a0 = -l1;
+            a1 = l0;
+        } else if constexpr (MU == 2) {
+            a0 = mi(l0);
+            a1 = ti(l1);
+        } else {
+            a0 = -l0;
+            a1 = -l1;
+        }
+        h[c] = {fma(s, a0.re, u0.re), fma(s, a0.im, u0.im)};
+        h[3 + c] = {fma(s, a1.re, u1.re), fma(s, a1.im, u1.im)};
+    }
+}
+
+// acc_up += v ; acc_lo += s * A_mu^+ v
+template <typename T, int MU>
+__device__ __forceinline__ void accumulate_rt(cpx<T> acc[12], const cpx<T> v[6], T s) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<T> v0 = v[c], v1 = v[3 + c];
+        acc[c] = acc[c] + v0;
+        acc[3 + c] = acc[3 + c] + v1;
+        cpx<T> w0, w1;
+        if constexpr (MU == 0) {
+            w0 = ti(v1);
+            w1 = ti(v0);
+        } else if constexpr (MU == 1) {
+            w0 = v1;
+            w1 = -v0;
+        } else if constexpr (MU == 2) {
+            w0 = ti(v0);
+            w1 = mi(v1);
+        } else {
+            w0 = -v0;
+            w1 = -v1;
+        }
+        acc[6 + c] = {fma(s, w0.re, acc[6 + c].re), fma(s, w0.im, acc[6 + c].im)};
+        acc[9 + c] = {fma(s, w1.re, acc[9 + c].re), fma(s, w1.im, acc[9 + c].im)};
+    }
+}
+
+template <int SP, int GP, int RECON, bool DAG, bool NT, int MU>
+__device__ __forceinline__ void hop_rt(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs, bool fwd,
+                                       cpx<typename SpinorIO<SP>::real> acc[12]) {
+    using T = typename SpinorIO<SP>::real;
+    const Geom &g = a.g;
+    int j;
+    bool wrap;
+    if constexpr (MU == 0) {
+        int x = c[0] + (fwd ? 1 : -1);
+        wrap = fwd ? (x == g.L[0]) : (x < 0);
+        if (wrap) x = fwd ? 0 : g.L[0] - 1;
+        j = (i - xh) + (x >> 1);
+    } else {
+        const int stride = MU == 1 ? g.sy : (MU == 2 ? g.sz : g.st);
+        wrap = fwd ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
+        j = fwd ? i + stride : i - stride;
+        if (wrap) j += fwd ? -g.L[MU] * stride : g.L[MU] * stride;
+    }
+    const T s = (fwd != DAG) ? T(-1) : T(1);
+    cpx<T> f[12], h[6], u[9], w[9], v[6];
+    SpinorIO<SP>::load(a.in[1 - par], (long)j * a.nrhs + rhs, f);
+    const int lpar = fwd ? par : 1 - par;
+    const char *slab = (const char *)a.gauge + (size_t)(lpar * 4 + MU) * a.slab_bytes;
+    LinkIO<GP, RECON>::template load<NT>(slab, fwd ? i : j, u);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) w[3 * r + q] = fwd ? u[3 * r + q] : conjg(u[3 * q + r]);
+    project_rt<T, MU>(f, s, h);
+    su3_mul2<T, true>(w, h, v);
+    if (wrap && ((g.phase_mask >> MU) & 1)) {
+        const cpx<T> z = {(T)g.zr[MU], fwd ? (T)g.zi[MU] : -(T)g.zi[MU]};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = cmul(z, v[k]);
+    }
+    accumulate_rt<T, MU>(acc, v, s);
+}
+
+// e/o index of the site at position ps of the processing order
+__device__ __forceinline__ int site_of(const HopArgs &a, long ps) {
+    if (a.tchunk <= 0) return (int)ps;
+    const Geom &g = a.g;
+    const int plane = g.sz;  // (Lx/2) * Ly sites of one (z, t)
+    const long chunk = ps / a.chunk_sites;
+    const int r = (int)(ps - chunk * a.chunk_sites);
+    const int t0 = (int)chunk * a.tchunk;
+    const int trc = min(a.tchunk, g.L[3] - t0);  // the last chunk may be shorter
+    const int yx = r % plane;
+    const int q = r / plane;
+    const int tl = q % trc, z = q / trc;
+    return yx + plane * (z + g.L[2] * (t0 + tl));
+}
+
+__device__ __forceinline__ long logical_block(int swizzle) {
+    const long nb = gridDim.x, bid = blockIdx.x;
+    if (!swizzle || nb < 16) return bid;
+    // hardware dispatches block b to XCD b % 8: give XCD x one contiguous range
+    const long q = nb / 8, r = nb % 8, xcd = bid % 8;
+    return xcd * q + (xcd < r ? xcd : r) + bid / 8;
+}
+
+// The work of one thread of the one-thread-per-point kernels: output point at
+// position gid of the processing order of parity par.  Returns the point's
+// contribution to ||out||^2 (EPI_NORM), else 0.
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__device__ __forceinline__ double hop_point(const HopArgs &a, int par, long gid) {
+    using T = typename SpinorIO<SP>::real;
+    double nrm = 0.0;
+    if (gid >= a.npts) return nrm;
+    const long ps = gid / a.nrhs;
+    const int rhs = (int)(gid - ps * a.nrhs);
+    const int i = site_of(a, ps);
+    const long pt = (long)i * a.nrhs + rhs;
+    int c[4];
+    eo_coords(a.g, i, par, c);
+    const int xh = c[0] >> 1;
+    cpx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    hop<SP, GP, RECON, DAG, NT, 0, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 0, false>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 1, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 1, false>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 2, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 2, false>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 3, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 3, false>(a, par, i, xh, c, rhs, acc);
+    const T b = (T)a.b;
+    if constexpr (EPI & EPI_XPAY) {
+        cpx<T> xv[12];
+        SpinorIO<SP>::load(a.x[par], pt, xv);
+        const T aa = (T)a.a;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            acc[k] = {fma(b, acc[k].re, aa * xv[k].re), fma(b, acc[k].im, aa * xv[k].im)};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = b * acc[k];
+    }
+    SpinorIO<SP>::template store<NT>(a.out[par], pt, acc);
+    if constexpr (EPI & EPI_NORM) {
+        if constexpr (SP == WL_F64) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) nrm += acc[k].re * acc[k].re + acc[k].im * acc[k].im;
+        } else {
+            // the norm of what was stored (after rounding to the storage format)
+            cpx<T> st[12];
+            SpinorIO<SP>::load(a.out[par], pt, st);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) nrm += (double)st[k].re * st[k].re + (double)st[k].im * st[k].im;
+        }
+    }
+    return nrm;
+}
+
+// One thread per output point.
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
+    if (a.flag && *a.flag == 0) return;
+    const int par = a.out_par0 + blockIdx.y;
+    const long lb = logical_block(a.swizzle);
+    const long gid = lb * blockDim.x + threadIdx.x;  // position in the processing order
+    const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, par, gid);
+    if constexpr (EPI & EPI_NORM) {
+        __shared__ double lds[256];
+        const long blk = (long)blockIdx.y * gridDim.x + lb;
+        block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + blk, a.part_stride);
+    }
+}
+
+// R right-hand sides per thread: thread gid takes site position gid / (nrhs / R)
+// and right-hand sides R * (gid % (nrhs / R)) ... + R - 1.
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT, int R>
+__global__ void __launch_bounds__(256) hop_kernel_mr(const HopArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    if (a.flag && *a.flag == 0) return;
+    const int par = a.out_par0 + blockIdx.y;
+    const long lb = logical_block(a.swizzle);
+    const long gid = lb * blockDim.x + threadIdx.x;
+    const int G = a.nrhs / R;
+    const bool active = gid < a.npts / R;
+    double nrm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) nrm[r] = 0.0;
+    const long ps = gid / G;
+    const int rhs0 = (int)(gid - ps * G) * R;
+    if (active) {
+        const int i = site_of(a, ps);
+        int c[4];
+        eo_coords(a.g, i, par, c);
+        const int xh = c[0] >> 1;
+        cpx<T> acc[R][12];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[r][k] = {T(0), T(0)};
+        hop_r<SP, GP, RECON, DAG, NT, 0, true, R>(a, par, i, xh, c, rhs0, acc);
+        hop_r<SP, GP, RECON, DAG, NT, 0, false, R>(a, par, i, xh, c, rhs0, acc);
+        hop_r<SP, GP, RECON, DAG, NT, 1, true, R>(a, par, i, xh, c, rhs0, acc);
+        hop_r<SP, GP, RECON, DAG, NT, 1, false, R>(a, par, i, xh, c, rhs0, acc);
+        hop_r<SP, GP, RECON, DAG, NT, 2, true, R>(a, par, i, xh, c, rhs0, acc);
+        hop_r<SP, GP, RECON, DAG, NT, 2, false, R>(a, par, i, xh, c, rhs0, acc);
+        hop_r<SP, GP, RECON, DAG, NT, 3, true, R>(a, par, i, xh, c, rhs0, acc);
+        hop_r<SP, GP, RECON, DAG, NT, 3, false, R>(a, par, i, xh, c, rhs0, acc);
+        const T b = (T)a.b;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const long pt = (long)i * a.nrhs + rhs0 + r;
+            if constexpr (EPI & EPI_XPAY) {
+                cpx<T> xv[12];
+                SpinorIO<SP>::load(a.x[par], pt, xv);
+                const T aa = (T)a.a;
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    acc[r][k] = {fma(b, acc[r][k].re, aa * xv[k].re), fma(b, acc[r][k].im, aa * xv[k].im)};
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[r][k] = b * acc[r][k];
+            }
+            SpinorIO<SP>::template store<NT>(a.out[par], pt, acc[r]);
+            if constexpr (EPI & EPI_NORM) {
+                if constexpr (SP == WL_F64) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) nrm[r] += acc[r][k].re * acc[r][k].re + acc[r][k].im * acc[r][k].im;
+                } else {
+                    cpx<T> st[12];
+                    SpinorIO<SP>::load(a.out[par], pt, st);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) nrm[r] += (double)st[k].re * st[k].re + (double)st[k].im * st[k].im;
+                }
+            }
+        }
+    }
+    if constexpr (EPI & EPI_NORM) {
+        // per-rhs block sums in a fixed order: entry (thread t, r) belongs to
+        // rhs R * ((gid of t) % G) + r
+        __shared__ double lds[256 * R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[threadIdx.x * R + r] = nrm[r];
+        __syncthreads();
+        const long g0 = lb * blockDim.x;
+        if ((int)threadIdx.x < a.nrhs) {
+            const int want = threadIdx.x, r = want % R, grp = want / R;
+            double s = 0.0;
+            for (int t = 0; t < (int)blockDim.x; ++t)
+                if ((int)((g0 + t) % G) == grp) s += lds[t * R + r];
+            const long blk = (long)blockIdx.y * gridDim.x + lb;
+            a.partials[(long)want * a.part_stride + blk] = s;
+        }
+    }
+}
+
+// Persistent launch over the tiles (blocks of points) of several systems.  The
+// tiles of all systems form one list, cut into eight contiguous ranges, one
+// per XCD (the hardware hands workgroup w to XCD w % 8); the workgroups of an
+// XCD take the tiles of its range in order from that range's atomic counter,
+// so an XCD's L2 sees neighbouring tiles of the same lattice.  After the last
+// workgroup has taken its final (past-the-end) tile it resets the counters, so
+// the launch can be repeated (or replayed in a graph) without clearing them.
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
+    __shared__ long tile_s;
+    __shared__ double lds[256];
+    const int xcd = blockIdx.x % 8;
+    const long r0 = B.ntiles * xcd / 8, r1 = B.ntiles * (xcd + 1) / 8;
+    for (;;) {
+        if (threadIdx.x == 0) tile_s = r0 + atomicAdd(B.counter + xcd * 32, 1);
+        __syncthreads();
+        const long tile = tile_s;
+        __syncthreads();
+        if (tile >= r1) break;
+        int sy = 0;
+        while (sy + 1 < B.nsys && tile >= B.start[sy + 1]) ++sy;
+        const HopArgs &a = B.sys[sy];
+        if (a.flag && *a.flag == 0) continue;
+        const long local = tile - B.start[sy];
+        const int py = (int)(local / B.per_par[sy]);
+        const long lb = local - (long)py * B.per_par[sy];
+        const long gid = lb * blockDim.x + threadIdx.x;
+        const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, gid);
+        if constexpr (EPI & EPI_NORM) block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + local, a.part_stride);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(B.counter + 8 * 32, 1) == (int)gridDim.x - 1) {
+            for (int k = 0; k <= 8; ++k) atomicExch(B.counter + k * 32, 0);
+            __threadfence();
+        }
+    }
+}
+
+// Two threads per output point: lanes 0-31 of a wavefront take the forward
+// hops of 32 consecutive points, lanes 32-63 the backward hops of the same
+// points; the partial sums are exchanged across the halves and each half
+// finishes and stores two of the four spin components.
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    if (a.flag && *a.flag == 0) return;
+    const int par = a.out_par0 + blockIdx.y;
+    const long lb = logical_block(a.swizzle);
+    const int lane = threadIdx.x & 63;
+    const bool fwd = lane < 32;
+    const int hf = fwd ? 0 : 1;  // spin half this lane stores
+    const long gid = ((lb * blockDim.x + threadIdx.x) >> 6) * 32 + (lane & 31);
+    long pt = 0;
+    const bool active = gid < a.npts;
+    cpx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    if (active) {
+        const long ps = gid / a.nrhs;
+        const int rhs = (int)(gid - ps * a.nrhs);
+        const int i = site_of(a, ps);
+        pt = (long)i * a.nrhs + rhs;
+        int c[4];
+        eo_coords(a.g, i, par, c);
+        const int xh = c[0] >> 1;
+        hop_rt<SP, GP, RECON, DAG, NT, 0>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, NT, 1>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, NT, 2>(a, par, i, xh, c, rhs, fwd, acc);
+        hop_rt<SP, GP, RECON, DAG, NT, 3>(a, par, i, xh, c, rhs, fwd, acc);
+    }
+    // every lane takes part in the exchange
+    cpx<T> res[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const cpx<T> send = fwd ? acc[6 + k] : acc[k];
+        const cpx<T> own = fwd ? acc[k] : acc[6 + k];
+        const cpx<T> recv = {__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
+        res[k] = own + recv;
+    }
+    double nrm = 0.0;
+    if (active) {
+        const T b = (T)a.b;
+        if constexpr (EPI & EPI_XPAY) {
+            cpx<T> xv[6];
+            SpinorIO<SP>::load_half(a.x[par], pt, hf, xv);
+            const T aa = (T)a.a;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                res[k] = {fma(b, res[k].re, aa * xv[k].re), fma(b, res[k].im, aa * xv[k].im)};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) res[k] = b * res[k];
+        }
+        SpinorIO<SP>::template store_half<NT>(a.out[par], pt, hf, res);
+        if constexpr (EPI & EPI_NORM) {
+            if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(a.out[par], pt, hf, res);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
+        }
+    }
+    if constexpr (EPI & EPI_NORM) {
+        __shared__ double lds[256];
+        __shared__ int lrhs[256];
+        const long blk = (long)blockIdx.y * gridDim.x + lb;
+        block_sum_by_rhs(nrm, (int)(gid % a.nrhs), a.nrhs, lds, lrhs, a.partials + blk, a.part_stride);
+    }
+}
+
+
+// Launch of the R-right-hand-sides-per-thread kernel for every storage format,
+// dagger, epilogue and non-temporal choice; instantiated once per R in its own
+// translation unit (wl_dslash_r2/3/4.hip) to keep compile times short.
+template <int SP, int GP, int RECON, bool DAG, bool NT, int R>
+static hipError_t launch_r_epi(int epi, const HopArgs &a, dim3 grid, dim3 blk, hipStream_t s) {
+    switch (epi) {
+    case 0: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, 0, NT, R>), grid, blk, 0, s, a); break;
+    case EPI_XPAY: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_XPAY, NT, R>), grid, blk, 0, s, a); break;
+    case EPI_NORM: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_NORM, NT, R>), grid, blk, 0, s, a); break;
+    case EPI_XPAY | EPI_NORM:
+        hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM, NT, R>), grid, blk, 0, s, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int SP, int GP, int RECON, int R>
+static hipError_t launch_r_dag(bool dag, bool nt, int epi, const HopArgs &a, dim3 grid, dim3 blk, hipStream_t s) {
+    if (nt)
+        return dag ? launch_r_epi<SP, GP, RECON, true, true, R>(epi, a, grid, blk, s)
+                   : launch_r_epi<SP, GP, RECON, false, true, R>(epi, a, grid, blk, s);
+    return dag ? launch_r_epi<SP, GP, RECON, true, false, R>(epi, a, grid, blk, s)
+               : launch_r_epi<SP, GP, RECON, false, false, R>(epi, a, grid, blk, s);
+}
+
+template <int R>
+static hipError_t launch_hop_r_impl(int prec, int recon, bool dag, bool nt, int epi, const HopArgs &a, dim3 grid,
+                                    dim3 blk, hipStream_t s) {
+    if (prec == WL_F64)
+        return recon == 12 ? launch_r_dag<WL_F64, WL_F64, 12, R>(dag, nt, epi, a, grid, blk, s)
+                           : launch_r_dag<WL_F64, WL_F64, 18, R>(dag, nt, epi, a, grid, blk, s);
+    if (prec == WL_F32)
+        return recon == 12 ? launch_r_dag<WL_F32, WL_F32, 12, R>(dag, nt, epi, a, grid, blk, s)
+                           : launch_r_dag<WL_F32, WL_F32, 18, R>(dag, nt, epi, a, grid, blk, s);
+    if (prec == WL_F16N && recon == 12) return launch_r_dag<WL_F16N, WL_F16N, 12, R>(dag, nt, epi, a, grid, blk, s);
+    if (prec == WL_BF16N && recon == 12) return launch_r_dag<WL_BF16N, WL_BF16N, 12, R>(dag, nt, epi, a, grid, blk, s);
+    if (prec == WL_I16N && recon == 12) return launch_r_dag<WL_I16N, WL_I16N, 12, R>(dag, nt, epi, a, grid, blk, s);
+    return hipErrorInvalidValue;
+}
+
+// defined in wl_dslash_r2.hip, wl_dslash_r3.hip, wl_dslash_r4.hip
+hipError_t launch_hop_r2(int prec, int recon, bool dag, bool nt, int epi, const HopArgs &a, dim3 grid, dim3 blk,
+                         hipStream_t s);
+hipError_t launch_hop_r3(int prec, int recon, bool dag, bool nt, int epi, const HopArgs &a, dim3 grid, dim3 blk,
+                         hipStream_t s);
+hipError_t launch_hop_r4(int prec, int recon, bool dag, bool nt, int epi, const HopArgs &a, dim3 grid, dim3 blk,
+                         hipStream_t s);
+
+}  // namespace wl

@@ -119,6 +119,19 @@ _SIGS = {
                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_params_default": (None, [ctypes.POINTER(FgcrParams)]),
     "wl_pcgnr_params_default": (None, [ctypes.POINTER(PcgnrParams)]),
+    "wl_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]),
+    "wl_batch_destroy": (ctypes.c_int, [_vp]),
+    "wl_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "wl_batch_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "wl_batch_dirac_apply": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
+                                            _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_batch_cg_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _dp, ctypes.c_int,
+                                         ctypes.POINTER(SolverParams), ctypes.POINTER(SolverInfo), _vp]),
+    "wl_batch_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "wl_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, _vp, _dp, _ip]),
+    "wl_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip,
+                                         _dp, _ip]),
+    "wl_batch_timing_read": (ctypes.c_int, [_vp, _ip, _dp]),
     "wl_pcgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(PcgnrParams),
                                       ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(FgcrParams),
@@ -288,10 +301,10 @@ def wl_cg_solve(ctx, x, b, op, kappa, nrhs=1, params: SolverParams | None = None
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("swizzle", ctypes.c_int), ("tps", ctypes.c_int), ("tchunk", ctypes.c_int),
-                ("nt", ctypes.c_int)]
+                ("nt", ctypes.c_int), ("rpt", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.block, self.swizzle, self.tps, self.tchunk, self.nt)
+        return (self.block, self.swizzle, self.tps, self.tchunk, self.nt, self.rpt)
 
 
 def wl_cgnr_solve(ctx, x, eta, kappa, params: SolverParams | None = None, stream=None):
@@ -316,6 +329,79 @@ def wl_fgcr_solve(ctx, x, b, kappa, net=None, params: FgcrParams | None = None, 
     st = _check(lib().wl_fgcr_solve(ctx, _ptr(x), _ptr(b), float(kappa), net, ctypes.byref(p), ctypes.byref(info),
                                     _stream(stream)))
     return st, info.as_dict()
+
+
+def _ptr_array(items):
+    return (_vp * len(items))(*[_ptr(t) for t in items])
+
+
+def wl_batch_create(ctxs):
+    arr = (_vp * len(ctxs))(*ctxs)
+    out = _vp()
+    _check(lib().wl_batch_create(arr, len(ctxs), ctypes.byref(out)))
+    return out.value
+
+
+def wl_batch_destroy(batch):
+    return _check(lib().wl_batch_destroy(batch))
+
+
+def wl_batch_set_launch(batch, workgroups, block=256, nt=-1):
+    return _check(lib().wl_batch_set_launch(batch, int(workgroups), int(block), int(nt)))
+
+
+def wl_batch_get_launch(batch):
+    w, b, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().wl_batch_get_launch(batch, ctypes.byref(w), ctypes.byref(b), ctypes.byref(n)))
+    return w.value, b.value, n.value
+
+
+def wl_batch_dirac_apply(batch, outs, ins, op, dagger, kappas, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    k = (ctypes.c_double * len(kappas))(*[float(v) for v in kappas])
+    return _check(lib().wl_batch_dirac_apply(batch, _ptr_array(outs), _ptr_array(ins), int(op), int(bool(dagger)), k,
+                                             int(prec), int(recon), int(nrhs), _stream(stream)))
+
+
+def wl_batch_cg_solve(batch, xs, bs, op, kappas, nrhs=1, params: SolverParams | None = None, stream=None):
+    """Returns (status, [[info per rhs] per system])."""
+    p = params if params is not None else wl_solver_params_default()
+    n = len(xs)
+    k = (ctypes.c_double * n)(*[float(v) for v in kappas])
+    info = (SolverInfo * (n * nrhs))()
+    st = _check(lib().wl_batch_cg_solve(batch, _ptr_array(xs), _ptr_array(bs), int(op), k, int(nrhs),
+                                        ctypes.byref(p), info, _stream(stream)))
+    return st, [[info[s * nrhs + r].as_dict() for r in range(nrhs)] for s in range(n)]
+
+
+def wl_batch_timing_enable(batch, enable=True):
+    return _check(lib().wl_batch_timing_enable(batch, int(bool(enable))))
+
+
+def wl_batch_timing_read(batch):
+    n, ms = ctypes.c_int(), ctypes.c_double()
+    _check(lib().wl_batch_timing_read(batch, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def wl_autotune(ctx, prec=WL_F64, recon=18, nrhs=1, cache_path=None):
+    """Sweep the hopping-kernel launch shapes; returns (Launch tuple, microseconds per launch, from_cache)."""
+    cfg = Launch()
+    us = ctypes.c_double()
+    fc = ctypes.c_int()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().wl_autotune(ctx, int(prec), int(recon), int(nrhs), path, ctypes.addressof(cfg), ctypes.byref(us),
+                             ctypes.byref(fc)))
+    return cfg.as_tuple(), us.value, bool(fc.value)
+
+
+def wl_batch_autotune(batch, prec=WL_F32, recon=18, nrhs=1, cache_path=None):
+    """Sweep persistent workgroups / tile size / non-temporal hints; returns ((workgroups, block, nt), us, from_cache)."""
+    w, b, n, fc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    us = ctypes.c_double()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().wl_batch_autotune(batch, int(prec), int(recon), int(nrhs), path, ctypes.byref(w), ctypes.byref(b),
+                                   ctypes.byref(n), ctypes.byref(us), ctypes.byref(fc)))
+    return (w.value, b.value, n.value), us.value, bool(fc.value)
 
 
 def wl_pcgnr_params_default() -> PcgnrParams:
@@ -396,13 +482,13 @@ def wl_ptc_step(net, lr, stream=None) -> float:
     return loss.value
 
 
-def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=0, nt=-1):
-    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt))
+def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=0, nt=-1, rpt=1):
+    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt), int(rpt))
     return _check(lib().wl_ctx_set_launch(ctx, prec, ctypes.addressof(cfg)))
 
 
 def wl_ctx_get_launch(ctx, prec):
-    """-> (block, swizzle, tps, tchunk, nt)"""
+    """-> (block, swizzle, tps, tchunk, nt, rpt)"""
     cfg = Launch()
     _check(lib().wl_ctx_get_launch(ctx, prec, ctypes.addressof(cfg)))
     return cfg.as_tuple()

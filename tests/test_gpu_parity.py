@@ -13,6 +13,7 @@ Tolerances (relative, normwise over the whole output field):
 
 import numpy as np
 import pytest
+import torch
 
 from oracle import oracle as orc
 from paper_1405_0700_amd import synth
@@ -369,7 +370,7 @@ def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
     saved = W.wl_ctx_get_launch(lat.ctx, prec)
     W.wl_ctx_set_launch(lat.ctx, prec, block, swizzle, tps, tchunk, nt)
     try:
-        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk, nt)
+        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk, nt, 1)
         phi = synth.gaussian_spinor(dims, seed=79)
         for dagger in (False, True):
             want = orc.hop(phi, u, ph, dagger=dagger)
@@ -398,9 +399,51 @@ def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
         W.wl_ctx_set_launch(lat.ctx, prec, *saved)
 
 
+@pytest.mark.parametrize("prec,recon", [(W.WL_F64, 18), (W.WL_F32, 12), (W.WL_F16N, 12)])
+@pytest.mark.parametrize("nrhs,rpt", [(12, 2), (12, 3), (12, 4), (4, 4), (6, 3)])
+def test_rhs_per_thread_matches_one_point_per_thread(prec, recon, nrhs, rpt):
+    """rpt > 1 applies each loaded link to rpt right-hand sides; every output point is computed
+    with the same operations in the same order, so the fields agree bit for bit."""
+    dims = (6, 4, 4, 8)
+    kappa = 0.12
+    ph = random_phases(81)
+    u, lat = setup(dims, seed=82, phases=ph)
+    stack = np.stack([synth.gaussian_spinor(dims, seed=90 + r).reshape(-1, 4, 3) for r in range(nrhs)])
+    saved = W.wl_ctx_get_launch(lat.ctx, prec)
+    outs = {}
+    try:
+        for r_ in (1, rpt):
+            W.wl_ctx_set_launch(lat.ctx, prec, 128, 1, 1, 0, -1, r_)
+            inp = lat.pack(stack, W.WL_FULL, prec, nrhs)
+            o1 = lat.new(W.WL_FULL, prec, nrhs)
+            W.wl_dslash_dagger_apply(lat.ctx, o1, inp, W.WL_FULL, prec, recon, nrhs)
+            o2 = lat.new(W.WL_FULL, prec, nrhs)
+            W.wl_dirac_apply(lat.ctx, o2, inp, W.WL_OP_D, False, kappa, prec, recon, nrhs)
+            torch.cuda.synchronize()
+            outs[r_] = (o1, o2)
+        assert torch.equal(outs[1][0], outs[rpt][0]) and torch.equal(outs[1][1], outs[rpt][1])
+        if prec == W.WL_F64:
+            # the fused-norm epilogue inside CG: iterates of every rhs still match the oracle
+            W.wl_ctx_set_launch(lat.ctx, prec, 128, 1, 1, 0, -1, rpt)
+            p = W.wl_solver_params_default()
+            p.tol, p.maxiter, p.max_restarts = 0.0, 10, 0
+            x = lat.new(W.WL_FULL, W.WL_F64, nrhs)
+            W.wl_cg_solve(lat.ctx, x, lat.pack(stack, W.WL_FULL, W.WL_F64, nrhs), W.WL_OP_D, kappa, nrhs=nrhs,
+                          params=p)
+            got = lat.unpack(x, W.WL_FULL, W.WL_F64, nrhs)
+            m = lambda v: orc.dirac(v, u, kappa, ph)
+            md = lambda v: orc.dirac(v, u, kappa, ph, dagger=True)
+            for r in (0, nrhs - 1):
+                x_orc, _ = orc.cg_normal(m, md, stack[r].reshape(dims[::-1] + (4, 3)), fixed_iters=10)
+                assert rel(got[r].reshape(x_orc.shape), x_orc) < 1e-13
+    finally:
+        W.wl_ctx_set_launch(lat.ctx, prec, *saved)
+
+
 def test_launch_config_rejects_bad_values():
     _, lat = setup((4, 4, 4, 4))
-    for args in [(W.WL_F64, 32, 0, 1), (W.WL_F64, 320, 0, 1), (W.WL_F64, 256, 0, 3), (W.WL_F64, 256, 0, 1, -1), (W.WL_F64, 256, 0, 1, 0, 2)]:
+    for args in [(W.WL_F64, 32, 0, 1), (W.WL_F64, 320, 0, 1), (W.WL_F64, 256, 0, 3), (W.WL_F64, 256, 0, 1, -1),
+                 (W.WL_F64, 256, 0, 1, 0, 2), (W.WL_F64, 256, 0, 1, 0, 0, 5), (W.WL_F64, 256, 0, 2, 0, 0, 2)]:
         with pytest.raises(W.WilsonError) as e:
             W.wl_ctx_set_launch(lat.ctx, *args)
         assert e.value.status == W.WL_ERR_ARG

@@ -125,8 +125,9 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *           tps = 1) a thread computes rpt consecutive right-hand sides of one
  *           site and applies each link it loads to all of them; a launch whose
  *           nrhs is not a multiple of rpt uses one point per thread.
- * Results do not depend on block, swizzle, tchunk, nt or rpt; tps changes the
- * summation order of the 8 hops (rounding only).  Defaults are chosen per
+ * Results do not depend on block, swizzle, tchunk or nt; tps changes the
+ * summation order of the 8 hops and rpt the compiler's contraction of
+ * multiply-adds (rounding only).  Defaults are chosen per
  * precision by measurement (see wl_ctx_get_launch). */
 typedef struct {
     int block;

@@ -796,7 +796,9 @@ static wl_status cg_finish_iteration(CGRun &R, bool reliable) {
     v.flag = R.done;
     HIP_TRY(cg_update_xr(R.prec, WL_F64, v, R.nh, R.s));
     if (reliable) {
-        // replace the iterated residual by the FP64 one before the step length of p is formed
+        // replace the iterated residual by the FP64 one before the step length of p is
+        // formed; its norm is kept first (the beta step compares the two)
+        HIP_TRY(cg_stash_rho(R.sc, R.nrhs, R.partials, R.stride, R.nblk_blas, R.done, R.s));
         wl_status st = true_residual(R);
         if (st) return st;
         VecArgs w = vec_args(R.c, R.prec, R.nrhs);
@@ -989,7 +991,9 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
         // mixed precision the same decay rate predicts the iteration at which
         // ||r|| will have dropped by reliable_delta, and the FP64 refresh is
         // scheduled there.
-        int block = std::max(1, std::min(P.check_every, remaining));
+        // in mixed precision the first block is short, so that the decay rate (and with
+        // it the first refresh) is known before the residual has fallen far
+        int block = std::max(1, std::min(mixed ? std::min(4, P.check_every) : P.check_every, remaining));
         int ru_in = P.reliable_every > 0 ? P.reliable_every : INT32_MAX;  // iterations until the next refresh
         std::vector<double> prev_rho(nrhs, -1.0);
         std::vector<int> prev_it(nrhs, 0);
@@ -1463,20 +1467,26 @@ extern "C" wl_status wl_batch_cg_solve(wl_batch *B, void *const *x, const void *
                             R[k].done, s));
             if ((st = load_residual(R[k]))) return st;
         }
+        // refresh schedule and host-check blocks as in wl_cg_solve, per system: a short
+        // first block, then blocks and refreshes predicted from the observed decay
         std::vector<int> since(n, 0), ru_in(n, ru_every);
-        int block = std::max(1, std::min(P.check_every, remaining));
+        std::vector<char> live(n, 1);
+        std::vector<std::vector<double>> prev_rho(n, std::vector<double>(nrhs, -1.0));
+        std::vector<std::vector<int>> prev_it(n, std::vector<int>(nrhs, 0));
+        int block = std::max(1, std::min(mixed ? std::min(4, P.check_every) : P.check_every, remaining));
         for (;;) {
             for (int j = 0; j < block; ++j) {
                 std::vector<char> ru(n, 0);
                 bool any_ru = false;
                 if (mixed)
                     for (int k = 0; k < n; ++k)
-                        if (++since[k] >= ru_in[k]) {
+                        if (live[k] && ++since[k] >= ru_in[k]) {
                             ru[k] = 1;
                             any_ru = true;
                             since[k] = 0;
                             ru_in[k] = ru_every;
-                            for (int r = 0; r < nrhs; ++r) relu[k][r]++;
+                            for (int r = 0; r < nrhs; ++r)
+                                if (hsc[k][r].active || prev_rho[k][r] < 0.0) relu[k][r]++;
                         }
                 if (graph && !any_ru) {
                     if ((st = ensure_batch_graph(B, R))) return st;
@@ -1485,24 +1495,46 @@ extern "C" wl_status wl_batch_cg_solve(wl_batch *B, void *const *x, const void *
                     return st;
                 }
             }
-            bool any = false;
-            for (int k = 0; k < n; ++k) {
-                wl_ctx *c = R[k].c;
-                HIP_TRY(hipMemcpyAsync(c->host_pinned, R[k].sc, sizeof(CGScalars) * nrhs, hipMemcpyDeviceToHost, s));
-            }
+            for (int k = 0; k < n; ++k)
+                HIP_TRY(hipMemcpyAsync(R[k].c->host_pinned, R[k].sc, sizeof(CGScalars) * nrhs, hipMemcpyDeviceToHost,
+                                       s));
             HIP_TRY(hipStreamSynchronize(s));
+            bool any = false;
+            int next = 1;
             for (int k = 0; k < n; ++k) {
                 std::memcpy(hsc[k].data(), R[k].c->host_pinned, sizeof(CGScalars) * nrhs);
+                int ru_pred = INT32_MAX;
+                bool sys_live = false;
                 for (int r = 0; r < nrhs; ++r) {
                     const CGScalars &h = hsc[k][r];
-                    any |= h.active != 0;
-                    // schedule the FP64 refresh of a system once its residual has dropped by reliable_delta
-                    if (mixed && h.active && h.rho < P.reliable_delta * P.reliable_delta * h.rho_max)
-                        ru_in[k] = std::min(ru_in[k], since[k] + 1);
+                    if (!h.active) continue;
+                    sys_live = true;
+                    int est = P.check_every;
+                    if (prev_rho[k][r] > 0.0 && h.rho < prev_rho[k][r] && h.iter > prev_it[k][r]) {
+                        const double rate = std::log(h.rho / prev_rho[k][r]) / (h.iter - prev_it[k][r]);
+                        if (h.target > 0.0) {
+                            const double left = std::log(h.target / h.rho) / rate;
+                            if (std::isfinite(left)) est = (int)std::floor(0.8 * left);
+                        }
+                        if (mixed) {
+                            const double drop = P.reliable_delta * P.reliable_delta * h.rho_max;
+                            const double until = h.rho <= drop ? 0.0 : std::log(drop / h.rho) / rate;
+                            if (std::isfinite(until)) ru_pred = std::min(ru_pred, std::max(1, (int)std::ceil(until)));
+                        }
+                    } else if (mixed && h.rho < P.reliable_delta * P.reliable_delta * h.rho_max) {
+                        ru_pred = 1;
+                    }
+                    prev_rho[k][r] = h.rho;
+                    prev_it[k][r] = h.iter;
+                    next = std::max(next, std::min(est, P.check_every));
                 }
+                live[k] = sys_live;
+                any |= sys_live;
+                if (mixed && sys_live && ru_pred != INT32_MAX)
+                    ru_in[k] = since[k] + std::max(1, std::min(ru_pred, ru_every - since[k]));
             }
             if (!any) break;
-            block = std::max(1, std::min(P.check_every, remaining));
+            block = std::max(1, next);
         }
         int maxit = 0;
         bool breakdown = false, all_ok = true;

@@ -18,6 +18,7 @@ struct CGScalars {
     int status;      // WL_OK / WL_NOT_CONVERGED / WL_BREAKDOWN
     int maxiter;
     int leaving;     // stopped at the alpha step; leaves the active count at the beta step
+    double rho_iter; // ||r||^2 of the iterated residual just before an FP64 refresh
 };
 
 struct VecArgs {
@@ -62,10 +63,15 @@ hipError_t reduce_partials(const double *partials, long stride, long nblk, int n
 // system; a system that stops decrements it)
 hipError_t cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                     const int *flag, hipStream_t s);
-//   mode 1: the residual was just refreshed in FP64 (restart the rho_max record);
-//   mode 2: also restart the search direction (beta = 0)
+//   mode 1: the residual was just refreshed in FP64 (restart the rho_max record;
+//           the search direction is restarted too if the refreshed ||r|| is more
+//           than twice the iterated one, rho_iter, recorded by cg_stash_rho);
+//   mode 2: always restart the search direction (beta = 0)
 hipError_t cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *done,
                    int mode, hipStream_t s);
+// rho_iter = sum(partials) for every active rhs (before an FP64 refresh overwrites them)
+hipError_t cg_stash_rho(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, const int *flag,
+                        hipStream_t s);
 // initialise: rho = sum(partials) (||r0||^2), target = tol^2 * bnorm2[r]; active if rho > target
 hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                    const double *bnorm2, double tol, int maxiter, int *done, hipStream_t s);

@@ -284,8 +284,13 @@ __global__ void __launch_bounds__(256) k_cg_beta(CGScalars *sc, const double *pa
             c.active = 0;
         } else {
             // mode 0: plain step; 1: the residual was just refreshed in FP64 (restart
-            // the rho_max record); 2: also restart the search direction
-            c.beta = mode == 2 ? 0.0 : s / c.rho;
+            // the rho_max record); 2: also restart the search direction.  In mode 1 a
+            // refresh that finds the true residual more than twice the iterated one
+            // (the iterated residual had drifted far below it) restarts the direction
+            // as well: the old direction then says nothing about the new residual, and
+            // beta = rho'/rho would be large and let it dominate.
+            const bool restart = mode == 2 || (mode == 1 && s > 4.0 * c.rho_iter);
+            c.beta = restart ? 0.0 : s / c.rho;
             c.rho = s;
             c.rho_max = mode ? s : fmax(c.rho_max, s);
             if (s <= c.target) {
@@ -298,6 +303,17 @@ __global__ void __launch_bounds__(256) k_cg_beta(CGScalars *sc, const double *pa
         }
         if (!c.active) atomicSub(count, 1);
     }
+}
+
+__global__ void __launch_bounds__(256) k_cg_stash(CGScalars *sc, const double *partials, long stride, long nblk,
+                                                  const int *count) {
+    if (count && *count == 0) return;
+    __shared__ double lds[16];
+    const int r = blockIdx.x;
+    CGScalars &c = sc[r];
+    if (!c.active) return;
+    const double s = sum_partials(partials + (long)r * stride, nblk, lds);
+    if (threadIdx.x == 0) c.rho_iter = s;
 }
 
 __global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const double *partials, long stride,
@@ -318,6 +334,7 @@ __global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const 
             c.iter = 0;
             c.maxiter = maxiter;
             c.leaving = 0;
+            c.rho_iter = s;
             if (!isfinite(s)) {
                 c.status = WL_BREAKDOWN;
                 c.active = 0;
@@ -430,6 +447,11 @@ hipError_t cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride
 hipError_t cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *done,
                    int mode, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_beta, dim3(nrhs), dim3(256), 0, s, sc, partials, stride, nblk, done, mode);
+    return hipGetLastError();
+}
+hipError_t cg_stash_rho(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, const int *flag,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_stash, dim3(nrhs), dim3(256), 0, s, sc, partials, stride, nblk, flag);
     return hipGetLastError();
 }
 hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,

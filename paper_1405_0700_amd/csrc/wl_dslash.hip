@@ -91,7 +91,8 @@ static hipError_t launch_batch_t(bool dag, bool nt, int epi, const BatchArgs &B,
 
 hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, BatchArgs &B, int nwg, int block,
                             hipStream_t stream) {
-    if (B.nsys < 1 || B.nsys > BATCH_MAX || block <= 0 || block > 256 || block % 64 || nwg < 8 || nwg % 8)
+    if (B.nsys < 1 || B.nsys > BATCH_MAX || block <= 0 || block > 256 || block % 64 || nwg < 8 || nwg % 8 ||
+        B.ntiles >= (1L << 30))
         return hipErrorInvalidValue;
     for (int k = 0; k < B.nsys; ++k) {
         HopArgs &a = B.sys[k];

@@ -439,28 +439,40 @@ __global__ void __launch_bounds__(256) hop_kernel_mr(const HopArgs a) {
 // so an XCD's L2 sees neighbouring tiles of the same lattice.  After the last
 // workgroup has taken its final (past-the-end) tile it resets the counters, so
 // the launch can be repeated (or replayed in a graph) without clearing them.
+// Next tile of this workgroup's XCD range, the same value in every lane: the
+// barriers before and after the slot keep it from being overwritten while
+// read, and readfirstlane makes the value (and every branch on it) uniform to
+// the compiler, so that the barriers of the loop body are never under control
+// flow it must treat as divergent.
+__device__ __forceinline__ int next_tile(int *counter, int r0, int *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = r0 + atomicAdd(counter, 1);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 __global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
-    __shared__ long tile_s;
+    __shared__ int slot;
     __shared__ double lds[256];
     const int xcd = blockIdx.x % 8;
-    const long r0 = B.ntiles * xcd / 8, r1 = B.ntiles * (xcd + 1) / 8;
-    for (;;) {
-        if (threadIdx.x == 0) tile_s = r0 + atomicAdd(B.counter + xcd * 32, 1);
-        __syncthreads();
-        const long tile = tile_s;
-        __syncthreads();
-        if (tile >= r1) break;
+    const int r0 = (int)(B.ntiles * xcd / 8), r1 = (int)(B.ntiles * (xcd + 1) / 8);
+    int tile = next_tile(B.counter + xcd * 32, r0, &slot);
+    while (tile < r1) {
         int sy = 0;
         while (sy + 1 < B.nsys && tile >= B.start[sy + 1]) ++sy;
         const HopArgs &a = B.sys[sy];
-        if (a.flag && *a.flag == 0) continue;
-        const long local = tile - B.start[sy];
-        const int py = (int)(local / B.per_par[sy]);
-        const long lb = local - (long)py * B.per_par[sy];
-        const long gid = lb * blockDim.x + threadIdx.x;
-        const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, gid);
-        if constexpr (EPI & EPI_NORM) block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + local, a.part_stride);
+        // tiles of a system that has stopped iterating are skipped
+        const int live = a.flag ? __builtin_amdgcn_readfirstlane(*a.flag) : 1;
+        if (live != 0) {
+            const long local = tile - B.start[sy];
+            const int py = (int)(local / B.per_par[sy]);
+            const long lb = local - (long)py * B.per_par[sy];
+            const long gid = lb * blockDim.x + threadIdx.x;
+            const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, gid);
+            if constexpr (EPI & EPI_NORM) block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + local, a.part_stride);
+        }
+        tile = next_tile(B.counter + xcd * 32, r0, &slot);
     }
     if (threadIdx.x == 0) {
         __threadfence();

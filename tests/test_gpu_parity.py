@@ -402,8 +402,9 @@ def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
 @pytest.mark.parametrize("prec,recon", [(W.WL_F64, 18), (W.WL_F32, 12), (W.WL_F16N, 12)])
 @pytest.mark.parametrize("nrhs,rpt", [(12, 2), (12, 3), (12, 4), (4, 4), (6, 3)])
 def test_rhs_per_thread_matches_one_point_per_thread(prec, recon, nrhs, rpt):
-    """rpt > 1 applies each loaded link to rpt right-hand sides; every output point is computed
-    with the same operations in the same order, so the fields agree bit for bit."""
+    """rpt > 1 applies each loaded link to rpt right-hand sides.  The arithmetic per output point
+    is the same up to the compiler's FMA contraction, so the fields agree to rounding: a few
+    units in the last place of the arithmetic (FP64, FP32), or one storage step (FP16 + norm)."""
     dims = (6, 4, 4, 8)
     kappa = 0.12
     ph = random_phases(81)
@@ -421,7 +422,11 @@ def test_rhs_per_thread_matches_one_point_per_thread(prec, recon, nrhs, rpt):
             W.wl_dirac_apply(lat.ctx, o2, inp, W.WL_OP_D, False, kappa, prec, recon, nrhs)
             torch.cuda.synchronize()
             outs[r_] = (o1, o2)
-        assert torch.equal(outs[1][0], outs[rpt][0]) and torch.equal(outs[1][1], outs[rpt][1])
+        tol = {W.WL_F64: 1e-15, W.WL_F32: 1e-6, W.WL_F16N: 2e-3}[prec]
+        for k in range(2):
+            a = lat.unpack(outs[1][k], W.WL_FULL, prec, nrhs)
+            b = lat.unpack(outs[rpt][k], W.WL_FULL, prec, nrhs)
+            assert rel(b, a) < tol
         if prec == W.WL_F64:
             # the fused-norm epilogue inside CG: iterates of every rhs still match the oracle
             W.wl_ctx_set_launch(lat.ctx, prec, 128, 1, 1, 0, -1, rpt)

@@ -46,7 +46,7 @@ WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.2, gauge_seed=201, src_seed=202, ka
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILE_DIR, "hop_f64_24x24x24x48_traffic.txt")
 KERNEL_SOURCES = ["paper_1405_0700_amd/csrc/wl_dslash.hip", "paper_1405_0700_amd/csrc/wl_dslash.h",
-                  "paper_1405_0700_amd/csrc/wl_common.h"]
+                  "paper_1405_0700_amd/csrc/wl_dslash_kernels.h", "paper_1405_0700_amd/csrc/wl_common.h"]
 
 
 def step_bytes(vh: int, iters: int, restarts: int) -> int:

@@ -899,6 +899,11 @@ static wl_status cg_setup(wl_ctx *c, void *x, const void *b, int op, double kapp
     R.stride = part_stride_for(c, nrhs);
     const size_t flo = R.hb_lo * nh, fhi = R.hb_hi * nh;
     wl_status st;
+    // both link formats exist before anything is enqueued (building one synchronises
+    // the device, which a graph capture of the iteration must not do)
+    const void *lk;
+    size_t sl;
+    if ((st = get_links(c, WL_F64, 18, &lk, &sl)) || (st = get_links(c, P.prec, P.recon, &lk, &sl))) return st;
     if ((st = ensure_buf(c, S_R, flo)) || (st = ensure_buf(c, S_P, flo)) || (st = ensure_buf(c, S_Q, flo)) ||
         (st = ensure_buf(c, S_S, flo)) || (st = ensure_buf(c, S_TMP, R.hb_lo)) || (st = ensure_buf(c, S_RHI, fhi)) ||
         (st = ensure_buf(c, S_THI, fhi)) || (st = ensure_buf(c, S_TMPHI, R.hb_hi)) ||

@@ -207,6 +207,10 @@ template <int P> struct SpinorIO16 {
         float s = 0.f;
 #pragma unroll
         for (int c = 0; c < 12; ++c) s = fmaxf(s, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+        // a point whose largest component is below the smallest normal float is
+        // stored as zero: 1 / s would overflow (such values appear at the edge of
+        // the support of a point-source solve, products of ever smaller terms)
+        if (!(s >= 1.17549435e-38f)) s = 0.f;
         const float inv = s > 0.f ? 1.0f / s : 0.f;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {

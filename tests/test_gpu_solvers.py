@@ -154,7 +154,27 @@ def test_multi_rhs_each_system_stops_on_its_own():
     lat.close()
 
 
-@pytest.mark.parametrize("prec,recon", [(W.WL_F64, 18), (W.WL_F32, 18)])
+@pytest.mark.parametrize("prec", [W.WL_F16N, W.WL_BF16N])
+def test_sixteen_bit_point_source_on_a_large_lattice(prec):
+    """A point source on 24^3x48: the per-site maxima at the edge of the growing support fall
+    below the smallest normal float within two iterations (3e-39 here); such points must be
+    stored as zero, not scaled by an overflowing 1/s (which broke the solve down)."""
+    dims = (24, 24, 24, 48)
+    kappa = 0.135
+    u, lat = lattice(dims, 0.2, 401)
+    eta = synth.point_source(dims, 0, 0)
+    be, _ = orc.eo_split(eta, dims)
+    rhs = lat.new(W.WL_EVEN)
+    W.wl_dirac_apply(lat.ctx, rhs, lat.pack(be, W.WL_EVEN), W.WL_OP_DHAT, True, kappa)
+    p = W.wl_solver_params_default()
+    p.prec, p.recon = prec, 12
+    x = lat.new(W.WL_EVEN)
+    st, info = W.wl_cg_solve(lat.ctx, x, rhs, W.WL_OP_DHAT, kappa, params=p)
+    print("prec", prec, info[0])
+    assert st == W.WL_OK and info[0]["true_rel_resid"] <= 1e-10
+
+
+@pytest.mark.parametrize("prec,recon", [(W.WL_F64, 18), (W.WL_F32, 18), (W.WL_F16N, 12), (W.WL_I16N, 12)])
 def test_point_source_propagator_twelve_rhs(prec, recon):
     """All 12 spin-colour point sources at the origin in one multi-RHS e/o solve."""
     dims = (6, 6, 6, 8)

@@ -380,11 +380,13 @@ wl_status wl_pcgnr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, cons
  * contexts, which must outlive it.  Calls on one batch are not thread-safe. */
 wl_status wl_batch_create(wl_ctx *const *ctxs, int nsys, wl_batch **out);
 wl_status wl_batch_destroy(wl_batch *batch);
-/* Persistent workgroups (a multiple of 8; default 3 per compute unit), points
- * per tile (64..256, a multiple of 64; default 256) and non-temporal hints (1
- * on, 0 off, -1 by working-set size, the default). */
-wl_status wl_batch_set_launch(wl_batch *batch, int workgroups, int block, int nt);
-wl_status wl_batch_get_launch(const wl_batch *batch, int *workgroups, int *block, int *nt);
+/* Persistent workgroups (a multiple of 8; default 3 per compute unit),
+ * threads per tile (64..256, a multiple of 64; default 256), non-temporal
+ * hints (1 on, 0 off, -1 by working-set size, the default) and threads per
+ * output point (1, the default; 2: forward and backward hops in the two halves
+ * of a wavefront, for FP64 / FP32 storage only, measured slower here). */
+wl_status wl_batch_set_launch(wl_batch *batch, int workgroups, int block, int nt, int tps);
+wl_status wl_batch_get_launch(const wl_batch *batch, int *workgroups, int *block, int *nt, int *tps);
 
 /* out[k] = M_k in[k] (M_k^+ if dagger) for every system k of the batch, M = D
  * (FULL fields) or D_hat (EVEN fields), kappa[k] per system, all fields in
@@ -427,11 +429,11 @@ wl_status wl_batch_timing_read(wl_batch *batch, int *count, double *total_ms);
 wl_status wl_autotune(wl_ctx *ctx, wl_prec prec, int recon, int nrhs, const char *cache_path, wl_launch *chosen,
                       double *best_us, int *from_cache);
 /* The same for a batch: persistent workgroups (1..8 per compute unit, scaled
- * by 256 / block), points per tile 64/128/256 and non-temporal hints, timed on
- * the persistent launch of D over every system; the result becomes the
- * batch's launch configuration. */
+ * by 256 / block), threads per tile 64/128/256, non-temporal hints and one or
+ * two threads per point, timed on the persistent launch of D over every
+ * system; the result becomes the batch's launch configuration. */
 wl_status wl_batch_autotune(wl_batch *batch, wl_prec prec, int recon, int nrhs, const char *cache_path,
-                            int *workgroups, int *block, int *nt, double *best_us, int *from_cache);
+                            int *workgroups, int *block, int *nt, int *tps, double *best_us, int *from_cache);
 
 /* ---------------------------------------------------------------- kernel timing */
 

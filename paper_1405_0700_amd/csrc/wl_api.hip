@@ -1132,7 +1132,8 @@ struct wl_batch {
     hipStream_t s = nullptr;              // own non-blocking stream (graph capture)
     hipEvent_t handoff[2] = {nullptr, nullptr};
     int *counter = nullptr;               // 9 work counters, 128 bytes apart
-    int nwg = 0, block = 256, nt = -1;    // persistent workgroups, points per tile, non-temporal
+    int nwg = 0, block = 256, nt = -1;    // persistent workgroups, threads per tile, non-temporal
+    int tps = 1;                          // threads per point (2: FP64 / FP32 storage only)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> key;
@@ -1190,25 +1191,28 @@ extern "C" wl_status wl_batch_destroy(wl_batch *B) {
     return WL_OK;
 }
 
-extern "C" wl_status wl_batch_set_launch(wl_batch *B, int workgroups, int block, int nt) {
+extern "C" wl_status wl_batch_set_launch(wl_batch *B, int workgroups, int block, int nt, int tps) {
     g_err.clear();
     if (!B) return fail(WL_ERR_ARG, "null batch");
     if (workgroups < 8 || workgroups % 8 || workgroups > 65536)
         return fail(WL_ERR_ARG, "workgroups %d: a multiple of 8 in 8..65536", workgroups);
     if (block < 64 || block > 256 || block % 64) return fail(WL_ERR_ARG, "block %d not in {64, 128, 192, 256}", block);
     if (nt < -1 || nt > 1) return fail(WL_ERR_ARG, "nt %d not in {-1, 0, 1}", nt);
+    if (tps != 1 && tps != 2) return fail(WL_ERR_ARG, "tps %d not in {1, 2}", tps);
     B->nwg = workgroups;
     B->block = block;
     B->nt = nt;
+    B->tps = tps;
     return WL_OK;
 }
 
-extern "C" wl_status wl_batch_get_launch(const wl_batch *B, int *workgroups, int *block, int *nt) {
+extern "C" wl_status wl_batch_get_launch(const wl_batch *B, int *workgroups, int *block, int *nt, int *tps) {
     g_err.clear();
-    if (!B || !workgroups || !block || !nt) return fail(WL_ERR_ARG, "null argument");
+    if (!B || !workgroups || !block || !nt || !tps) return fail(WL_ERR_ARG, "null argument");
     *workgroups = B->nwg;
     *block = B->block;
     *nt = B->nt;
+    *tps = B->tps;
     return WL_OK;
 }
 
@@ -1248,6 +1252,7 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
                              const long *stride, int *const *flags, long *nblk, hipStream_t s) {
     const int n = (int)B->ctx.size();
     const int nst = op == WL_OP_D ? 1 : 2;
+    const int tps = (prec == WL_F64 || prec == WL_F32) && B->tps == 2 ? 2 : 1;
     for (int stage = 0; stage < nst; ++stage) {
         BatchArgs A;
         std::memset(&A, 0, sizeof A);
@@ -1275,7 +1280,7 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
                 st = fill_hop_args(c, prec, recon, out[k], tmp[k], in[k], WL_EVEN, nrhs, 1.0, -kappa[k] * kappa[k], pk,
                                    sk, flag, h, &np);
             if (st) return st;
-            A.per_par[k] = hop_blocks(h.npts, B->block, 1);
+            A.per_par[k] = hop_blocks(h.npts, B->block, tps);
             A.start[k] = tiles;
             tiles += A.per_par[k] * np;
             if (nblk && last) nblk[k] = A.per_par[k] * np;
@@ -1298,7 +1303,7 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
             ev = B->timed.back().data();
             HIP_TRY(hipEventRecord(ev[0], s));
         }
-        HIP_TRY(launch_hop_batch(prec, recon, dag, epi, nt, A, B->nwg, B->block, s));
+        HIP_TRY(launch_hop_batch(prec, recon, dag, epi, nt, tps, A, B->nwg, B->block, s));
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     }
     return WL_OK;
@@ -1377,7 +1382,7 @@ static wl_status batch_iteration(wl_batch *B, std::vector<CGRun> &R, const std::
 }
 
 static wl_status ensure_batch_graph(wl_batch *B, std::vector<CGRun> &R) {
-    std::vector<uintptr_t> key{(uintptr_t)B->nwg, (uintptr_t)B->block, (uintptr_t)(B->nt + 1)};
+    std::vector<uintptr_t> key{(uintptr_t)B->nwg, (uintptr_t)B->block, (uintptr_t)(B->nt + 1), (uintptr_t)B->tps};
     for (auto &r : R) {
         std::vector<uintptr_t> k = graph_key(r);
         key.insert(key.end(), k.begin(), k.end());
@@ -1771,7 +1776,8 @@ extern "C" wl_status wl_autotune(wl_ctx *c, wl_prec prec, int recon, int nrhs, c
 }
 
 extern "C" wl_status wl_batch_autotune(wl_batch *B, wl_prec prec, int recon, int nrhs, const char *cache_path,
-                                       int *workgroups, int *block, int *nt, double *best_us, int *from_cache) {
+                                       int *workgroups, int *block, int *nt, int *tps, double *best_us,
+                                       int *from_cache) {
     g_err.clear();
     wl_status st = batch_check(B, prec, recon, nrhs, WL_FULL);
     if (st) return st;
@@ -1784,13 +1790,14 @@ extern "C" wl_status wl_batch_autotune(wl_batch *B, wl_prec prec, int recon, int
                "x" + std::to_string(c->dims[3]);
     key += " prec " + std::to_string((int)prec) + " recon " + std::to_string(recon) + " nrhs " + std::to_string(nrhs);
     std::vector<double> vals;
-    int bw = B->nwg, bb = B->block, bn = B->nt, cached = 0;
+    int bw = B->nwg, bb = B->block, bn = B->nt, bt = B->tps, cached = 0;
     double best_t = 0.0;
-    if (cache_lookup(key, cache_path, vals) && vals.size() >= 4) {
+    if (cache_lookup(key, cache_path, vals) && vals.size() >= 5) {
         bw = (int)vals[0];
         bb = (int)vals[1];
         bn = (int)vals[2];
-        best_t = vals[3];
+        bt = (int)vals[3];
+        best_t = vals[4];
         cached = 1;
     } else {
         std::vector<void *> bufs(n, nullptr), outs(n), ins(n);
@@ -1804,17 +1811,21 @@ extern "C" wl_status wl_batch_autotune(wl_batch *B, wl_prec prec, int recon, int
             ins[k] = bufs[k];
             outs[k] = (char *)bufs[k] + full;
         }
-        const int sw = B->nwg, sb = B->block, sn = B->nt;
+        const int sw = B->nwg, sb = B->block, sn = B->nt, st2 = B->tps;
+        const bool two = prec == WL_F64 || prec == WL_F32;
         const bool saved_timing = B->timing;
         B->timing = false;
         best_t = 1e30;
+        for (int tpv : {1, 2})
         for (int per_cu : {1, 2, 3, 4, 6, 8})
             for (int blk : {64, 128, 256})
                 for (int ntv : {0, 1}) {
                     if (st) break;
+                    if (tpv == 2 && !two) continue;
                     B->nwg = std::max(8, (cus * per_cu * 256 / blk + 7) / 8 * 8);
                     B->block = blk;
                     B->nt = ntv;
+                    B->tps = tpv;
                     double us = 0.0;
                     st = time_launches(
                         [&]() {
@@ -1828,23 +1839,27 @@ extern "C" wl_status wl_batch_autotune(wl_batch *B, wl_prec prec, int recon, int
                         bw = B->nwg;
                         bb = blk;
                         bn = ntv;
+                        bt = tpv;
                     }
                 }
         B->nwg = sw;
         B->block = sb;
         B->nt = sn;
+        B->tps = st2;
         B->timing = saved_timing;
         for (void *p : bufs)
             if (p) (void)hipFree(p);
         if (st) return st;
-        cache_store(key, cache_path, {(double)bw, (double)bb, (double)bn, best_t});
+        cache_store(key, cache_path, {(double)bw, (double)bb, (double)bn, (double)bt, best_t});
     }
     B->nwg = bw;
     B->block = bb;
     B->nt = bn;
+    B->tps = bt;
     if (workgroups) *workgroups = bw;
     if (block) *block = bb;
     if (nt) *nt = bn;
+    if (tps) *tps = bt;
     if (best_us) *best_us = best_t;
     if (from_cache) *from_cache = cached;
     return WL_OK;

@@ -63,9 +63,10 @@ struct BatchArgs {
     long ntiles;
     int *counter;
 };
-// nwg: persistent workgroups (a multiple of 8); epi without EPI_NORM alone
-hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, BatchArgs &B, int nwg, int block,
-                            hipStream_t stream);
+// nwg: persistent workgroups (a multiple of 8); epi without EPI_NORM alone; tps 2
+// (two threads per point, FP64/FP32 storage only): a tile holds block / 2 points
+hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, int tps, BatchArgs &B, int nwg,
+                            int block, hipStream_t stream);
 
 // threads per point actually used for a storage precision
 int effective_tps(int prec, const LaunchCfg &cfg);

@@ -66,9 +66,9 @@ int effective_tps(int prec, const LaunchCfg &cfg) {
     return (prec == WL_F64 || prec == WL_F32) && cfg.tps == 2 ? 2 : 1;
 }
 
-template <int SP, int GP, int RECON>
-static hipError_t launch_batch_t(bool dag, bool nt, int epi, const BatchArgs &B, dim3 grid, dim3 blk, hipStream_t s) {
-#define WL_BATCH_CASE(D, E, N) hipLaunchKernelGGL((hop_batch_kernel<SP, GP, RECON, D, E, N>), grid, blk, 0, s, B)
+template <int SP, int GP, int RECON, int TPS>
+static hipError_t launch_batch_tt(bool dag, bool nt, int epi, const BatchArgs &B, dim3 grid, dim3 blk, hipStream_t s) {
+#define WL_BATCH_CASE(D, E, N) hipLaunchKernelGGL((hop_batch_kernel<SP, GP, RECON, D, E, N, TPS>), grid, blk, 0, s, B)
     const int key = (dag ? 4 : 0) | (nt ? 8 : 0) | epi;
     switch (key) {
     case 0: WL_BATCH_CASE(false, 0, false); break;
@@ -89,8 +89,17 @@ static hipError_t launch_batch_t(bool dag, bool nt, int epi, const BatchArgs &B,
     return hipGetLastError();
 }
 
-hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, BatchArgs &B, int nwg, int block,
-                            hipStream_t stream) {
+template <int SP, int GP, int RECON>
+static hipError_t launch_batch_t(int tps, bool dag, bool nt, int epi, const BatchArgs &B, dim3 grid, dim3 blk,
+                                 hipStream_t s) {
+    if constexpr (SP == WL_F64 || SP == WL_F32) {
+        if (tps == 2) return launch_batch_tt<SP, GP, RECON, 2>(dag, nt, epi, B, grid, blk, s);
+    }
+    return launch_batch_tt<SP, GP, RECON, 1>(dag, nt, epi, B, grid, blk, s);
+}
+
+hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, int tps, BatchArgs &B, int nwg,
+                            int block, hipStream_t stream) {
     if (B.nsys < 1 || B.nsys > BATCH_MAX || block <= 0 || block > 256 || block % 64 || nwg < 8 || nwg % 8 ||
         B.ntiles >= (1L << 30))
         return hipErrorInvalidValue;
@@ -102,15 +111,17 @@ hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, 
     }
     dim3 grid((unsigned)nwg), blk(block);
     if (prec == WL_F64)
-        return recon == 12 ? launch_batch_t<WL_F64, WL_F64, 12>(dagger, nt, epi, B, grid, blk, stream)
-                           : launch_batch_t<WL_F64, WL_F64, 18>(dagger, nt, epi, B, grid, blk, stream);
+        return recon == 12 ? launch_batch_t<WL_F64, WL_F64, 12>(tps, dagger, nt, epi, B, grid, blk, stream)
+                           : launch_batch_t<WL_F64, WL_F64, 18>(tps, dagger, nt, epi, B, grid, blk, stream);
     if (prec == WL_F32)
-        return recon == 12 ? launch_batch_t<WL_F32, WL_F32, 12>(dagger, nt, epi, B, grid, blk, stream)
-                           : launch_batch_t<WL_F32, WL_F32, 18>(dagger, nt, epi, B, grid, blk, stream);
-    if (prec == WL_F16N && recon == 12) return launch_batch_t<WL_F16N, WL_F16N, 12>(dagger, nt, epi, B, grid, blk, stream);
+        return recon == 12 ? launch_batch_t<WL_F32, WL_F32, 12>(tps, dagger, nt, epi, B, grid, blk, stream)
+                           : launch_batch_t<WL_F32, WL_F32, 18>(tps, dagger, nt, epi, B, grid, blk, stream);
+    if (prec == WL_F16N && recon == 12)
+        return launch_batch_t<WL_F16N, WL_F16N, 12>(1, dagger, nt, epi, B, grid, blk, stream);
     if (prec == WL_BF16N && recon == 12)
-        return launch_batch_t<WL_BF16N, WL_BF16N, 12>(dagger, nt, epi, B, grid, blk, stream);
-    if (prec == WL_I16N && recon == 12) return launch_batch_t<WL_I16N, WL_I16N, 12>(dagger, nt, epi, B, grid, blk, stream);
+        return launch_batch_t<WL_BF16N, WL_BF16N, 12>(1, dagger, nt, epi, B, grid, blk, stream);
+    if (prec == WL_I16N && recon == 12)
+        return launch_batch_t<WL_I16N, WL_I16N, 12>(1, dagger, nt, epi, B, grid, blk, stream);
     return hipErrorInvalidValue;
 }
 

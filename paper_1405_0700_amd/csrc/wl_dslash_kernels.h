@@ -439,60 +439,17 @@ __global__ void __launch_bounds__(256) hop_kernel_mr(const HopArgs a) {
 // so an XCD's L2 sees neighbouring tiles of the same lattice.  After the last
 // workgroup has taken its final (past-the-end) tile it resets the counters, so
 // the launch can be repeated (or replayed in a graph) without clearing them.
-// Next tile of this workgroup's XCD range, the same value in every lane: the
-// barriers before and after the slot keep it from being overwritten while
-// read, and readfirstlane makes the value (and every branch on it) uniform to
-// the compiler, so that the barriers of the loop body are never under control
-// flow it must treat as divergent.
-__device__ __forceinline__ int next_tile(int *counter, int r0, int *slot) {
-    __syncthreads();
-    if (threadIdx.x == 0) *slot = r0 + atomicAdd(counter, 1);
-    __syncthreads();
-    return __builtin_amdgcn_readfirstlane(*slot);
-}
-
-template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
-__global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
-    __shared__ int slot;
-    __shared__ double lds[256];
-    const int xcd = blockIdx.x % 8;
-    const int r0 = (int)(B.ntiles * xcd / 8), r1 = (int)(B.ntiles * (xcd + 1) / 8);
-    int tile = next_tile(B.counter + xcd * 32, r0, &slot);
-    while (tile < r1) {
-        int sy = 0;
-        while (sy + 1 < B.nsys && tile >= B.start[sy + 1]) ++sy;
-        const HopArgs &a = B.sys[sy];
-        // tiles of a system that has stopped iterating are skipped
-        const int live = a.flag ? __builtin_amdgcn_readfirstlane(*a.flag) : 1;
-        if (live != 0) {
-            const long local = tile - B.start[sy];
-            const int py = (int)(local / B.per_par[sy]);
-            const long lb = local - (long)py * B.per_par[sy];
-            const long gid = lb * blockDim.x + threadIdx.x;
-            const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, gid);
-            if constexpr (EPI & EPI_NORM) block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + local, a.part_stride);
-        }
-        tile = next_tile(B.counter + xcd * 32, r0, &slot);
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(B.counter + 8 * 32, 1) == (int)gridDim.x - 1) {
-            for (int k = 0; k <= 8; ++k) atomicExch(B.counter + k * 32, 0);
-            __threadfence();
-        }
-    }
-}
 
 // Two threads per output point: lanes 0-31 of a wavefront take the forward
 // hops of 32 consecutive points, lanes 32-63 the backward hops of the same
 // points; the partial sums are exchanged across the halves and each half
-// finishes and stores two of the four spin components.
+// finishes and stores two of the four spin components.  The work of one
+// thread for logical block lb of parity par; *gid_out = the point's position
+// in the processing order.  Returns the thread's share of ||out||^2
+// (EPI_NORM), else 0.  Every lane of the wavefront must call it.
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
-__global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
+__device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, long lb, long *gid_out) {
     using T = typename SpinorIO<SP>::real;
-    if (a.flag && *a.flag == 0) return;
-    const int par = a.out_par0 + blockIdx.y;
-    const long lb = logical_block(a.swizzle);
     const int lane = threadIdx.x & 63;
     const bool fwd = lane < 32;
     const int hf = fwd ? 0 : 1;  // spin half this lane stores
@@ -545,11 +502,74 @@ __global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
             for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
         }
     }
+    *gid_out = gid;
+    return nrm;
+}
+
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
+    if (a.flag && *a.flag == 0) return;
+    const int par = a.out_par0 + blockIdx.y;
+    const long lb = logical_block(a.swizzle);
+    long gid;
+    const double nrm = hop_split_point<SP, GP, RECON, DAG, EPI, NT>(a, par, lb, &gid);
     if constexpr (EPI & EPI_NORM) {
         __shared__ double lds[256];
         __shared__ int lrhs[256];
         const long blk = (long)blockIdx.y * gridDim.x + lb;
         block_sum_by_rhs(nrm, (int)(gid % a.nrhs), a.nrhs, lds, lrhs, a.partials + blk, a.part_stride);
+    }
+}
+
+// Next tile of this workgroup's XCD range, the same value in every lane: the
+// barriers before and after the slot keep it from being overwritten while
+// read, and readfirstlane makes the value (and every branch on it) uniform to
+// the compiler, so that the barriers of the loop body are never under control
+// flow it must treat as divergent.
+__device__ __forceinline__ int next_tile(int *counter, int r0, int *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = r0 + atomicAdd(counter, 1);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT, int TPS>
+__global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
+    __shared__ int slot;
+    __shared__ double lds[256];
+    __shared__ int lrhs[TPS == 2 ? 256 : 1];
+    const int xcd = blockIdx.x % 8;
+    const int r0 = (int)(B.ntiles * xcd / 8), r1 = (int)(B.ntiles * (xcd + 1) / 8);
+    int tile = next_tile(B.counter + xcd * 32, r0, &slot);
+    while (tile < r1) {
+        int sy = 0;
+        while (sy + 1 < B.nsys && tile >= B.start[sy + 1]) ++sy;
+        const HopArgs &a = B.sys[sy];
+        // tiles of a system that has stopped iterating are skipped
+        const int live = a.flag ? __builtin_amdgcn_readfirstlane(*a.flag) : 1;
+        if (live != 0) {
+            const long local = tile - B.start[sy];
+            const int py = (int)(local / B.per_par[sy]);
+            const long lb = local - (long)py * B.per_par[sy];
+            if constexpr (TPS == 2) {
+                long gid;
+                const double nrm = hop_split_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, lb, &gid);
+                if constexpr (EPI & EPI_NORM)
+                    block_sum_by_rhs(nrm, (int)(gid % a.nrhs), a.nrhs, lds, lrhs, a.partials + local, a.part_stride);
+            } else {
+                const long gid = lb * blockDim.x + threadIdx.x;
+                const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, gid);
+                if constexpr (EPI & EPI_NORM) block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + local, a.part_stride);
+            }
+        }
+        tile = next_tile(B.counter + xcd * 32, r0, &slot);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(B.counter + 8 * 32, 1) == (int)gridDim.x - 1) {
+            for (int k = 0; k <= 8; ++k) atomicExch(B.counter + k * 32, 0);
+            __threadfence();
+        }
     }
 }
 

@@ -121,8 +121,8 @@ _SIGS = {
     "wl_pcgnr_params_default": (None, [ctypes.POINTER(PcgnrParams)]),
     "wl_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]),
     "wl_batch_destroy": (ctypes.c_int, [_vp]),
-    "wl_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
-    "wl_batch_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "wl_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "wl_batch_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "wl_batch_dirac_apply": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
                                             _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_batch_cg_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _dp, ctypes.c_int,
@@ -130,7 +130,7 @@ _SIGS = {
     "wl_batch_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wl_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, _vp, _dp, _ip]),
     "wl_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip,
-                                         _dp, _ip]),
+                                         _ip, _dp, _ip]),
     "wl_batch_timing_read": (ctypes.c_int, [_vp, _ip, _dp]),
     "wl_pcgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(PcgnrParams),
                                       ctypes.POINTER(SolverInfo), _vp]),
@@ -346,14 +346,15 @@ def wl_batch_destroy(batch):
     return _check(lib().wl_batch_destroy(batch))
 
 
-def wl_batch_set_launch(batch, workgroups, block=256, nt=-1):
-    return _check(lib().wl_batch_set_launch(batch, int(workgroups), int(block), int(nt)))
+def wl_batch_set_launch(batch, workgroups, block=256, nt=-1, tps=1):
+    return _check(lib().wl_batch_set_launch(batch, int(workgroups), int(block), int(nt), int(tps)))
 
 
 def wl_batch_get_launch(batch):
-    w, b, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(lib().wl_batch_get_launch(batch, ctypes.byref(w), ctypes.byref(b), ctypes.byref(n)))
-    return w.value, b.value, n.value
+    """-> (workgroups, block, nt, tps)"""
+    w, b, n, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().wl_batch_get_launch(batch, ctypes.byref(w), ctypes.byref(b), ctypes.byref(n), ctypes.byref(t)))
+    return w.value, b.value, n.value, t.value
 
 
 def wl_batch_dirac_apply(batch, outs, ins, op, dagger, kappas, prec=WL_F64, recon=18, nrhs=1, stream=None):
@@ -395,13 +396,14 @@ def wl_autotune(ctx, prec=WL_F64, recon=18, nrhs=1, cache_path=None):
 
 
 def wl_batch_autotune(batch, prec=WL_F32, recon=18, nrhs=1, cache_path=None):
-    """Sweep persistent workgroups / tile size / non-temporal hints; returns ((workgroups, block, nt), us, from_cache)."""
-    w, b, n, fc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    """Sweep persistent workgroups / tile size / non-temporal hints / threads per point;
+    returns ((workgroups, block, nt, tps), us, from_cache)."""
+    w, b, n, t, fc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     us = ctypes.c_double()
     path = None if cache_path is None else str(cache_path).encode()
     _check(lib().wl_batch_autotune(batch, int(prec), int(recon), int(nrhs), path, ctypes.byref(w), ctypes.byref(b),
-                                   ctypes.byref(n), ctypes.byref(us), ctypes.byref(fc)))
-    return (w.value, b.value, n.value), us.value, bool(fc.value)
+                                   ctypes.byref(n), ctypes.byref(t), ctypes.byref(us), ctypes.byref(fc)))
+    return (w.value, b.value, n.value, t.value), us.value, bool(fc.value)
 
 
 def wl_pcgnr_params_default() -> PcgnrParams:

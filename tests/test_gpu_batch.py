@@ -5,7 +5,7 @@ right-hand sides), and CG on all of them in lockstep.
 Every output point of the persistent kernel is computed by the same per-point
 code as the one-thread-per-point kernel of a single context, so the batch
 operator equals the single-context operator (tps = 1) bit for bit, whatever the
-tile size and number of workgroups; against the oracle it holds the per-op
+tile size and number of workgroups (with the same threads per point); against the oracle it holds the per-op
 bar of 1e-13 (FP64) / the storage tolerances (FP32).  Batched solves are
 judged by the oracle-restated residual of every system and right-hand side.
 """
@@ -53,8 +53,11 @@ def stacked(dims, seeds):
 @pytest.mark.parametrize("op", [W.WL_OP_D, W.WL_OP_DHAT])
 @pytest.mark.parametrize("dagger", [False, True])
 @pytest.mark.parametrize("nrhs", [1, 4])
-def test_batch_operator_matches_single_context_and_oracle(batch, op, dagger, nrhs):
+@pytest.mark.parametrize("tps", [1, 2])
+def test_batch_operator_matches_single_context_and_oracle(batch, op, dagger, nrhs, tps):
     b, lats, gauges = batch
+    saved = W.wl_batch_get_launch(b)
+    W.wl_batch_set_launch(b, saved[0], 256, -1, tps)
     subset = W.WL_FULL if op == W.WL_OP_D else W.WL_EVEN
     kappas = [s[3] for s in SYSTEMS]
     ins, outs, fields = [], [], []
@@ -66,9 +69,10 @@ def test_batch_operator_matches_single_context_and_oracle(batch, op, dagger, nrh
         ins.append(lat.pack(f if nrhs > 1 else f[0], subset, W.WL_F64, nrhs))
         outs.append(lat.new(subset, W.WL_F64, nrhs))
     W.wl_batch_dirac_apply(b, outs, ins, op, dagger, kappas, W.WL_F64, 18, nrhs)
+    W.wl_batch_set_launch(b, *saved)
     for k, (lat, u, (dims, _, _, kappa)) in enumerate(zip(lats, gauges, SYSTEMS)):
-        # single context, one thread per point: the same per-point code
-        W.wl_ctx_set_launch(lat.ctx, W.WL_F64, 256, 1, 1, 0, -1)
+        # single context with the same threads per point: the same per-point code
+        W.wl_ctx_set_launch(lat.ctx, W.WL_F64, 256, 1, tps, 0, -1)
         ref = lat.new(subset, W.WL_F64, nrhs)
         W.wl_dirac_apply(lat.ctx, ref, ins[k], op, dagger, kappa, W.WL_F64, 18, nrhs)
         torch.cuda.synchronize()
@@ -93,7 +97,7 @@ def test_batch_launch_shape_does_not_change_results_and_counters_reset(batch):
     default = W.wl_batch_get_launch(b)
     results = []
     for wg, blk in ((default[0], 256), (8, 64), (64, 128), (16, 256), (default[0], 256)):
-        W.wl_batch_set_launch(b, wg, blk, -1)
+        W.wl_batch_set_launch(b, wg, blk, -1, default[3])
         outs = [lat.new(W.WL_FULL, W.WL_F32, 2) for lat in lats]
         # three launches in a row: each must find its work counters back at zero
         for _ in range(3):
@@ -159,6 +163,8 @@ def test_batch_rejects_bad_arguments(batch):
     with pytest.raises(W.WilsonError):
         W.wl_batch_set_launch(b, 64, 96, -1)
     with pytest.raises(W.WilsonError):
+        W.wl_batch_set_launch(b, 64, 256, -1, 3)
+    with pytest.raises(W.WilsonError):
         W.wl_batch_create([lats[0].ctx, lats[0].ctx])
     outs = [lat.new(W.WL_FULL) for lat in lats]
     with pytest.raises(W.WilsonError):
@@ -200,9 +206,9 @@ def test_autotune_picks_a_valid_launch_and_caches_it(tmp_path):
 def test_batch_autotune(batch, tmp_path):
     b, lats, _ = batch
     before = W.wl_batch_get_launch(b)
-    (wg, blk, nt), us, cached = W.wl_batch_autotune(b, W.WL_F32, 18, 2, tmp_path / "b.txt")
-    assert not cached and us > 0 and wg % 8 == 0 and blk in (64, 128, 256) and nt in (0, 1)
-    assert W.wl_batch_get_launch(b) == (wg, blk, nt)
+    (wg, blk, nt, tps), us, cached = W.wl_batch_autotune(b, W.WL_F32, 18, 2, tmp_path / "b.txt")
+    assert not cached and us > 0 and wg % 8 == 0 and blk in (64, 128, 256) and nt in (0, 1) and tps in (1, 2)
+    assert W.wl_batch_get_launch(b) == (wg, blk, nt, tps)
     again = W.wl_batch_autotune(b, W.WL_F32, 18, 2, tmp_path / "b.txt")
-    assert again[2] and again[0] == (wg, blk, nt)
+    assert again[2] and again[0] == (wg, blk, nt, tps)
     W.wl_batch_set_launch(b, *before)

@@ -149,8 +149,89 @@ __global__ void __launch_bounds__(256) k_ptc_layer(const PtcArgs a) {
     SpinorIO<WL_F32>::store(a.out + (2 * (size_t)o + par) * a.half, i, acc);
 }
 
+// One input channel fanned out to cout > 1 output channels: a block takes 64
+// sites; first its 256 threads compute the 8 one-hop transports of each site
+// once (into LDS), then every (site, output channel) pair mixes the nine
+// transported spinors with its own weights.  The per-channel kernel above
+// would repeat every transport for each output channel.
+constexpr int PTC_FAN_SITES = 64;
+
+template <bool BF16W>
+__global__ void __launch_bounds__(256) k_ptc_layer_fan(const PtcArgs a) {
+    __shared__ float2 ts[8 * 12 * PTC_FAN_SITES];   // transported spinors [path-1][component][site]
+    __shared__ float2 wl[PTC_NPATH * PTC_MAXC * 16];  // spin matrices [path][output channel][4x4]
+    const int par = blockIdx.y;
+    const int nw = PTC_NPATH * a.cout * 16;
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) {
+        const int q = k / (a.cout * 16), rem = k - q * a.cout * 16, o = rem >> 4, st = rem & 15;
+        float2 e;
+        if (a.adjoint) {
+            // (W_p^{0 o})^+ of the forward layer (1 -> cout here is its cout_f = 1, cin_f = cout)
+            e = ptc_weight<BF16W>(a.w, ((long)ptc_reverse(q) * a.cout + o) * 16 + 4 * (st & 3) + (st >> 2));
+            e.y = -e.y;
+        } else {
+            e = ptc_weight<BF16W>(a.w, ((long)q * a.cout + o) * 16 + st);
+        }
+        wl[k] = e;
+    }
+    const long base = (long)blockIdx.x * PTC_FAN_SITES;
+    for (int task = threadIdx.x; task < 8 * PTC_FAN_SITES; task += blockDim.x) {
+        const int sl = task % PTC_FAN_SITES, q = task / PTC_FAN_SITES + 1;
+        const long i = base + sl;
+        cpx<float> t[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) t[k] = {0.f, 0.f};
+        if (i < a.vh) {
+            int c[4];
+            eo_coords(a.g, (int)i, par, c);
+            const PathHop h = ptc_hop(a.g, (int)i, par, c, q);
+            cpx<float> v[12];
+            SpinorIO<WL_F32>::load(a.in + (size_t)h.npar * a.half, h.j, v);
+            ptc_transport(a.g, a.gauge, a.slab_bytes, h, v, t);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ts[((q - 1) * 12 + k) * PTC_FAN_SITES + sl] = make_float2(t[k].re, t[k].im);
+    }
+    __syncthreads();
+    for (int task = threadIdx.x; task < a.cout * PTC_FAN_SITES; task += blockDim.x) {
+        const int sl = task % PTC_FAN_SITES, o = task / PTC_FAN_SITES;
+        const long i = base + sl;
+        if (i >= a.vh) continue;
+        cpx<float> acc[12], v[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+        SpinorIO<WL_F32>::load(a.in + (size_t)par * a.half, i, v);  // identity path
+        for (int q = 0; q < PTC_NPATH; ++q) {
+            if (q > 0) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const float2 f = ts[((q - 1) * 12 + k) * PTC_FAN_SITES + sl];
+                    v[k] = {f.x, f.y};
+                }
+            }
+            const float2 *m = &wl[(q * a.cout + o) * 16];
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                for (int t_ = 0; t_ < 4; ++t_) {
+                    const float2 e = m[4 * s_ + t_];
+                    const cpx<float> ms = {e.x, e.y};
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) acc[3 * s_ + cc] = cfma(ms, v[3 * t_ + cc], acc[3 * s_ + cc]);
+                }
+        }
+        SpinorIO<WL_F32>::store(a.out + (2 * (size_t)o + par) * a.half, i, acc);
+    }
+}
+
 hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16, hipStream_t s) {
     if (a.cout < 1 || a.cin < 1 || a.cout * a.cin > PTC_MAXC) return hipErrorInvalidValue;
+    if (a.cin == 1 && a.cout > 1) {
+        dim3 grid((unsigned)((a.vh + PTC_FAN_SITES - 1) / PTC_FAN_SITES), 2);
+        if (bf16) hipLaunchKernelGGL(k_ptc_layer_fan<true>, grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(k_ptc_layer_fan<false>, grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)((a.vh + 255) / 256), 2, (unsigned)a.cout);
     if (bf16) hipLaunchKernelGGL(k_ptc_layer<true>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_ptc_layer<false>, grid, dim3(256), 0, s, a);

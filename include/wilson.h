@@ -186,6 +186,25 @@ wl_status wl_eo_prepare(const wl_ctx *ctx, void *bhat_e, const void *b_e, const 
 wl_status wl_eo_reconstruct(const wl_ctx *ctx, void *x_o, const void *x_e, const void *b_o,
                             double kappa, wl_prec prec, int recon, int nrhs, void *stream);
 
+/* ---------------------------------------------------------------- twisted mass
+ *
+ * The twisted-mass Wilson operator (the operator of the paper's twisted-mass
+ * solver section; its form in hopping-parameter normalisation):
+ *   D_tm = A - kappa H,  A = 1 + i nu gamma_5,  nu = 2 kappa mu,
+ * D_tm^+ = A^+ - kappa H^+ (A^+ = 1 - i nu gamma_5).  Even/odd:
+ *   D_hat_tm = A - kappa^2 H_eo A^-1 H_oe  on even sites,  A^-1 = (1 - i nu gamma_5) / (1 + nu^2),
+ *   bhat_e = b_e + kappa H_eo A^-1 b_o,   x_o = A^-1 (b_o + kappa H_oe x_e).
+ * The site-diagonal factors are applied in the hopping kernels' epilogue.
+ * Arguments, layouts and errors as for wl_dirac_apply / wl_eo_prepare /
+ * wl_eo_reconstruct; mu must be finite; mu = 0 gives the Wilson operator.
+ * wl_cg_solve takes mu in its parameters. */
+wl_status wl_dirac_tm_apply(wl_ctx *ctx, void *out, const void *in, wl_op op, int dagger, double kappa, double mu,
+                            wl_prec prec, int recon, int nrhs, void *stream);
+wl_status wl_eo_prepare_tm(const wl_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o, double kappa, double mu,
+                           wl_prec prec, int recon, int nrhs, void *stream);
+wl_status wl_eo_reconstruct_tm(const wl_ctx *ctx, void *x_o, const void *x_e, const void *b_o, double kappa, double mu,
+                               wl_prec prec, int recon, int nrhs, void *stream);
+
 /* ---------------------------------------------------------------- BLAS-1 */
 
 /* y = a x + y on internal fields (real a).  */
@@ -215,6 +234,7 @@ typedef struct {
                             every FP64 residual refresh; 1 on, 0 off, -1 on for the
                             16-bit formats (whose iterated residual drifts too far
                             for the old direction to stay useful)                    */
+    double mu;           /* twisted mass: M = D_tm or D_hat_tm (0: Wilson)             */
 } wl_solver_params;
 
 typedef struct {
@@ -230,7 +250,7 @@ typedef struct {
 
 /* Fill in defaults: tol 1e-10, maxiter 100000, check_every 25, max_restarts 5,
  * prec WL_F64, recon 18, reliable_every 100, reliable_delta 0.1, no graph,
- * ru_restart -1.
+ * ru_restart -1, mu 0.
  * Mixed precision: the FP64 residual is refreshed every reliable_every
  * iterations and whenever ||r|| has dropped by reliable_delta since the last
  * refresh; the iteration of that drop is predicted from the observed decay of

@@ -171,6 +171,37 @@ def dirac(phi, gauge, kappa, phases, dagger=False):
     return phi - kappa * hop(phi, gauge, phases, dagger)
 
 
+def twist(phi, nu):
+    """(1 + i nu gamma_5) phi for a field whose last two axes are (spin, colour)."""
+    return phi + 1j * nu * np.einsum("st,...tc->...sc", gamma5(), phi)
+
+
+def dirac_tm(phi, gauge, kappa, mu, phases, dagger=False):
+    """Twisted-mass operator D_tm = 1 + 2 i kappa mu gamma_5 - kappa H (D_tm^+: -mu and H^+), full lattice."""
+    nu = (-2.0 if dagger else 2.0) * kappa * mu
+    return twist(phi, nu) - kappa * hop(phi, gauge, phases, dagger)
+
+
+def schur_tm(phi_e, gauge, kappa, mu, phases, dagger=False):
+    """D_hat_tm phi_e = A phi_e - kappa^2 H_eo A^-1 H_oe phi_e, A = 1 + 2 i kappa mu gamma_5 (A^+ for the dagger)."""
+    nu = (-2.0 if dagger else 2.0) * kappa * mu
+    t = hop_eo(phi_e, 0, gauge, phases, dagger)
+    t = twist(t, -nu) / (1.0 + nu * nu)
+    return twist(phi_e, nu) - kappa * kappa * hop_eo(t, 1, gauge, phases, dagger)
+
+
+def eo_prepare_tm(b_e, b_o, gauge, kappa, mu, phases):
+    """bhat_e = b_e + kappa H_eo A^-1 b_o."""
+    nu = 2.0 * kappa * mu
+    return b_e + kappa * hop_eo(twist(b_o, -nu) / (1.0 + nu * nu), 1, gauge, phases)
+
+
+def eo_reconstruct_tm(x_e, b_o, gauge, kappa, mu, phases):
+    """x_o = A^-1 (b_o + kappa H_oe x_e)."""
+    nu = 2.0 * kappa * mu
+    return twist(b_o + kappa * hop_eo(x_e, 0, gauge, phases), -nu) / (1.0 + nu * nu)
+
+
 def schur(phi_e, gauge, kappa, phases, dagger=False):
     """D_hat phi_e = phi_e - kappa^2 H_eo H_oe phi_e (D_hat^+ with H^+)."""
     t = hop_eo(phi_e, 0, gauge, phases, dagger)

@@ -463,7 +463,7 @@ extern "C" wl_status wl_convert_spinor(const wl_ctx *c, void *dst, wl_prec dprec
 // HopArgs of out = a x + b H in for one output subset; *np = output parities
 static wl_status fill_hop_args(wl_ctx *c, int prec, int recon, void *out, const void *in, const void *x,
                                int out_subset, int nrhs, double a, double b, double *partials, long part_stride,
-                               const int *flag, HopArgs &h, int *np_out) {
+                               const int *flag, HopArgs &h, int *np_out, double tm_x = 0.0, double tm_h = 0.0) {
     const void *gauge;
     size_t slab;
     wl_status st = get_links(c, prec, recon, &gauge, &slab);
@@ -477,6 +477,8 @@ static wl_status fill_hop_args(wl_ctx *c, int prec, int recon, void *out, const 
     h.npts = c->Vh * (long)nrhs;
     h.a = a;
     h.b = b;
+    h.tm_x = tm_x;
+    h.tm_h = tm_h;
     h.partials = partials;
     h.part_stride = part_stride;
     h.flag = flag;
@@ -505,11 +507,12 @@ static wl_status fill_hop_args(wl_ctx *c, int prec, int recon, void *out, const 
 
 static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, void *out, const void *in,
                           const void *x, int out_subset, int nrhs, double a, double b, double *partials,
-                          long part_stride, const int *flag, hipStream_t s, long *nblk_out = nullptr) {
+                          long part_stride, const int *flag, hipStream_t s, long *nblk_out = nullptr,
+                          double tm_x = 0.0, double tm_h = 0.0) {
     HopArgs h;
     int np = 1;
     wl_status st = fill_hop_args(c, prec, recon, out, in, x, out_subset, nrhs, a, b, partials, part_stride, flag, h,
-                                 &np);
+                                 &np, tm_x, tm_h);
     if (st) return st;
     hipEvent_t *ev = nullptr;
     if (c->timing && !c->capturing && c->timed.size() < (1u << 16)) {
@@ -558,22 +561,26 @@ extern "C" wl_status wl_dslash_dagger_apply(const wl_ctx *c, void *out, const vo
 }
 
 // out = M in (M^+ if dag); tmp: odd half temporary for DHAT.  Norm partials of
-// out if partials != null.
+// out if partials != null.  With a twisted mass mu the site-diagonal part is
+// A = 1 + i nu gamma_5, nu = 2 kappa mu (A^+ for M^+): D = A - kappa H and
+// D_hat = A - kappa^2 H_eo A^-1 H_oe, A^-1 = (1 - i nu gamma_5) / (1 + nu^2).
 static wl_status apply_m(wl_ctx *c, int op, bool dag, double kappa, int prec, int recon, int nrhs, void *out,
                          const void *in, void *tmp, double *partials, long stride, const int *flag, hipStream_t s,
-                         long *nblk) {
+                         long *nblk, double mu = 0.0) {
     const int epi = EPI_XPAY | (partials ? EPI_NORM : 0);
+    const double nu = (dag ? -2.0 : 2.0) * kappa * mu;
     if (op == WL_OP_D)
         return hop_core(c, prec, recon, dag, epi, out, in, in, WL_FULL, nrhs, 1.0, -kappa, partials, stride, flag, s,
-                        nblk);
-    wl_status st = hop_core(c, prec, recon, dag, 0, tmp, in, nullptr, WL_ODD, nrhs, 0.0, 1.0, nullptr, 0, flag, s);
+                        nblk, nu, 0.0);
+    wl_status st = hop_core(c, prec, recon, dag, 0, tmp, in, nullptr, WL_ODD, nrhs, 0.0, 1.0 / (1.0 + nu * nu),
+                            nullptr, 0, flag, s, nullptr, 0.0, -nu);
     if (st) return st;
     return hop_core(c, prec, recon, dag, epi, out, tmp, in, WL_EVEN, nrhs, 1.0, -kappa * kappa, partials, stride,
-                    flag, s, nblk);
+                    flag, s, nblk, nu, 0.0);
 }
 
-extern "C" wl_status wl_dirac_apply(wl_ctx *c, void *out, const void *in, wl_op op, int dagger, double kappa,
-                                    wl_prec prec, int recon, int nrhs, void *stream) {
+static wl_status dirac_common(wl_ctx *c, void *out, const void *in, wl_op op, int dagger, double kappa, double mu,
+                              wl_prec prec, int recon, int nrhs, void *stream) {
     g_err.clear();
     if (op != WL_OP_D && op != WL_OP_DHAT) return fail(WL_ERR_ARG, "bad operator %d", (int)op);
     const int subset = op == WL_OP_D ? WL_FULL : WL_EVEN;
@@ -581,7 +588,7 @@ extern "C" wl_status wl_dirac_apply(wl_ctx *c, void *out, const void *in, wl_op 
     if (st) return st;
     if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", prec, recon);
     if (!out || !in || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
-    if (!std::isfinite(kappa)) return fail(WL_ERR_ARG, "non-finite kappa");
+    if (!std::isfinite(kappa) || !std::isfinite(mu)) return fail(WL_ERR_ARG, "non-finite kappa or mu");
     const size_t hb = half_bytes(c, prec, nrhs);
     const size_t bytes = hb * (op == WL_OP_D ? 2 : 1);
     if (overlap(out, bytes, in, bytes)) return fail(WL_ERR_ARG, "out and in overlap");
@@ -592,7 +599,17 @@ extern "C" wl_status wl_dirac_apply(wl_ctx *c, void *out, const void *in, wl_op 
         tmp = c->buf[S_TMP_OP];
     }
     return apply_m(c, op, dagger != 0, kappa, prec, recon, nrhs, out, in, tmp, nullptr, 0, nullptr,
-                   (hipStream_t)stream, nullptr);
+                   (hipStream_t)stream, nullptr, mu);
+}
+
+extern "C" wl_status wl_dirac_apply(wl_ctx *c, void *out, const void *in, wl_op op, int dagger, double kappa,
+                                    wl_prec prec, int recon, int nrhs, void *stream) {
+    return dirac_common(c, out, in, op, dagger, kappa, 0.0, prec, recon, nrhs, stream);
+}
+
+extern "C" wl_status wl_dirac_tm_apply(wl_ctx *c, void *out, const void *in, wl_op op, int dagger, double kappa,
+                                       double mu, wl_prec prec, int recon, int nrhs, void *stream) {
+    return dirac_common(c, out, in, op, dagger, kappa, mu, prec, recon, nrhs, stream);
 }
 
 static wl_status eo_helper(const wl_ctx *cc, void *out, const void *a_in, const void *hop_in, int out_subset,
@@ -618,6 +635,45 @@ extern "C" wl_status wl_eo_prepare(const wl_ctx *c, void *bhat_e, const void *b_
 extern "C" wl_status wl_eo_reconstruct(const wl_ctx *c, void *x_o, const void *x_e, const void *b_o, double kappa,
                                        wl_prec prec, int recon, int nrhs, void *stream) {
     return eo_helper(c, x_o, b_o, x_e, WL_ODD, kappa, prec, recon, nrhs, stream);
+}
+
+// twisted mass: bhat_e = b_e + kappa H_eo A^-1 b_o ; x_o = A^-1 (b_o + kappa H_oe x_e)
+extern "C" wl_status wl_eo_prepare_tm(const wl_ctx *cc, void *bhat_e, const void *b_e, const void *b_o, double kappa,
+                                      double mu, wl_prec prec, int recon, int nrhs, void *stream) {
+    g_err.clear();
+    wl_ctx *c = const_cast<wl_ctx *>(cc);
+    wl_status st = check_field_args(c, WL_ODD, prec, nrhs);
+    if (st) return st;
+    if (!b_o || !aligned16(b_o)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    if (!std::isfinite(kappa) || !std::isfinite(mu)) return fail(WL_ERR_ARG, "non-finite kappa or mu");
+    const size_t hb = half_bytes(c, prec, nrhs);
+    if ((st = ensure_buf(c, S_TMP_OP, hb))) return st;
+    const double nu = 2.0 * kappa * mu;
+    VecArgs v = vec_args(c, prec, nrhs);
+    set_vec(v, 0, b_o, hb);
+    set_vec(v, 1, c->buf[S_TMP_OP], hb);
+    v.a = 1.0 / (1.0 + nu * nu);
+    v.b = -nu;
+    HIP_TRY(blas_twist(prec, v, 1, (hipStream_t)stream));
+    return eo_helper(c, bhat_e, b_e, c->buf[S_TMP_OP], WL_EVEN, kappa, prec, recon, nrhs, stream);
+}
+
+extern "C" wl_status wl_eo_reconstruct_tm(const wl_ctx *cc, void *x_o, const void *x_e, const void *b_o,
+                                          double kappa, double mu, wl_prec prec, int recon, int nrhs, void *stream) {
+    g_err.clear();
+    wl_ctx *c = const_cast<wl_ctx *>(cc);
+    wl_status st = check_field_args(c, WL_ODD, prec, nrhs);
+    if (st) return st;
+    if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", prec, recon);
+    if (!x_o || !x_e || !b_o || !aligned16(x_o) || !aligned16(x_e) || !aligned16(b_o))
+        return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    if (!std::isfinite(kappa) || !std::isfinite(mu)) return fail(WL_ERR_ARG, "non-finite kappa or mu");
+    const size_t hb = half_bytes(c, prec, nrhs);
+    if (overlap(x_o, hb, x_e, hb)) return fail(WL_ERR_ARG, "output overlaps the hopping input");
+    const double nu = 2.0 * kappa * mu, sc = 1.0 / (1.0 + nu * nu);
+    // (1 - i nu gamma_5) / (1 + nu^2) applied to both terms of the epilogue
+    return hop_core(c, prec, recon, false, EPI_XPAY, x_o, x_e, b_o, WL_ODD, nrhs, sc, kappa * sc, nullptr, 0, nullptr,
+                    (hipStream_t)stream, nullptr, -nu, -nu);
 }
 
 // ------------------------------------------------------------------ BLAS API
@@ -727,6 +783,7 @@ extern "C" void wl_solver_params_default(wl_solver_params *p) {
     p->reliable_delta = 0.1;
     p->use_graph = 0;
     p->ru_restart = -1;
+    p->mu = 0.0;
 }
 
 namespace {
@@ -746,16 +803,17 @@ struct CGRun {
     int *done;
     long nblk_blas;
     int ru_restart;
+    double mu;  // twisted mass (0: Wilson)
 };
 }  // namespace
 
 // t = A x = M^+ M x in FP64; r_hi = b - t; partials of ||r_hi||^2
 static wl_status true_residual(CGRun &R) {
     wl_status st = apply_m(R.c, R.op, false, R.kappa, WL_F64, 18, R.nrhs, R.thi, R.x, R.tmphi, nullptr, 0, nullptr,
-                           R.s, nullptr);
+                           R.s, nullptr, R.mu);
     if (st) return st;
     st = apply_m(R.c, R.op, true, R.kappa, WL_F64, 18, R.nrhs, R.rhi, R.thi, R.tmphi, nullptr, 0, nullptr, R.s,
-                 nullptr);
+                 nullptr, R.mu);
     if (st) return st;
     VecArgs v = vec_args(R.c, WL_F64, R.nrhs);
     set_vec(v, 0, R.b, R.hb_hi);
@@ -821,11 +879,11 @@ static wl_status cg_finish_iteration(CGRun &R, bool reliable) {
 static wl_status cg_iteration(CGRun &R, bool reliable) {
     long nblk = 0;
     wl_status st = apply_m(R.c, R.op, false, R.kappa, R.prec, R.recon, R.nrhs, R.q, R.p, R.tmp, R.partials, R.stride,
-                           R.done, R.s, &nblk);
+                           R.done, R.s, &nblk, R.mu);
     if (st) return st;
     HIP_TRY(cg_alpha(R.sc, R.nrhs, R.partials, R.stride, nblk, R.done, R.s));
     st = apply_m(R.c, R.op, true, R.kappa, R.prec, R.recon, R.nrhs, R.sv, R.q, R.tmp, nullptr, 0, R.done, R.s,
-                 nullptr);
+                 nullptr, R.mu);
     if (st) return st;
     return cg_finish_iteration(R, reliable);
 }
@@ -834,9 +892,10 @@ static wl_status cg_iteration(CGRun &R, bool reliable) {
 // while this key is unchanged.
 static std::vector<uintptr_t> graph_key(const CGRun &R) {
     const LaunchCfg &g = R.c->cfg[R.prec];
-    uint64_t kb;
+    uint64_t kb, mb;
     std::memcpy(&kb, &R.kappa, sizeof kb);
-    return {(uintptr_t)R.op, (uintptr_t)R.prec, (uintptr_t)R.recon, (uintptr_t)R.nrhs, (uintptr_t)kb,
+    std::memcpy(&mb, &R.mu, sizeof mb);
+    return {(uintptr_t)R.op, (uintptr_t)R.prec, (uintptr_t)R.recon, (uintptr_t)R.nrhs, (uintptr_t)kb, (uintptr_t)mb,
             (uintptr_t)R.x, (uintptr_t)R.r, (uintptr_t)R.p, (uintptr_t)R.q, (uintptr_t)R.sv, (uintptr_t)R.tmp,
             (uintptr_t)R.partials, (uintptr_t)R.stride, (uintptr_t)R.sc, (uintptr_t)R.done,
             (uintptr_t)R.nblk_blas, (uintptr_t)g.block, (uintptr_t)g.swizzle, (uintptr_t)g.tps,
@@ -890,6 +949,7 @@ static wl_status cg_setup(wl_ctx *c, void *x, const void *b, int op, double kapp
     R.nh = nh;
     R.kappa = kappa;
     R.ru_restart = P.ru_restart < 0 ? (P.prec >= WL_F16N ? 1 : 0) : P.ru_restart;
+    R.mu = P.mu;
     R.s = s;
     R.hb_lo = half_bytes(c, P.prec, nrhs);
     R.hb_hi = half_bytes(c, WL_F64, nrhs);
@@ -942,7 +1002,7 @@ extern "C" wl_status wl_cg_solve(wl_ctx *c, void *x, const void *b, wl_op op, do
     if (params) P = *params;
     if (!prec_ok(P.prec)) return fail(WL_ERR_ARG, "bad inner precision %d", (int)P.prec);
     if (!recon_ok(P.prec, P.recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", P.prec, P.recon);
-    if (!(P.tol >= 0.0) || !std::isfinite(kappa)) return fail(WL_ERR_ARG, "bad tolerance or kappa");
+    if (!(P.tol >= 0.0) || !std::isfinite(kappa) || !std::isfinite(P.mu)) return fail(WL_ERR_ARG, "bad tolerance, kappa or mu");
     if (P.maxiter < 0 || P.check_every < 1 || P.max_restarts < 0) return fail(WL_ERR_ARG, "bad iteration limits");
     if (!x || !b || !aligned16(x) || !aligned16(b)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
     CGRun R;
@@ -1249,7 +1309,7 @@ extern "C" wl_status wl_batch_timing_read(wl_batch *B, int *count, double *total
 // skipped), or null.
 static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa, int prec, int recon, int nrhs,
                              void *const *out, const void *const *in, void *const *tmp, double *const *partials,
-                             const long *stride, int *const *flags, long *nblk, hipStream_t s) {
+                             const long *stride, int *const *flags, long *nblk, hipStream_t s, double mu = 0.0) {
     const int n = (int)B->ctx.size();
     const int nst = op == WL_OP_D ? 1 : 2;
     const int tps = (prec == WL_F64 || prec == WL_F32) && B->tps == 2 ? 2 : 1;
@@ -1270,15 +1330,17 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
             double *pk = partials ? partials[k] : nullptr;
             const long sk = partials ? stride[k] : 0;
             wl_status st;
+            // twisted mass as in apply_m
+            const double nu = (dag ? -2.0 : 2.0) * kappa[k] * mu;
             if (op == WL_OP_D)
                 st = fill_hop_args(c, prec, recon, out[k], in[k], in[k], WL_FULL, nrhs, 1.0, -kappa[k], pk, sk, flag, h,
-                                   &np);
+                                   &np, nu, 0.0);
             else if (stage == 0)
-                st = fill_hop_args(c, prec, recon, tmp[k], in[k], nullptr, WL_ODD, nrhs, 0.0, 1.0, nullptr, 0, flag, h,
-                                   &np);
+                st = fill_hop_args(c, prec, recon, tmp[k], in[k], nullptr, WL_ODD, nrhs, 0.0, 1.0 / (1.0 + nu * nu),
+                                   nullptr, 0, flag, h, &np, 0.0, -nu);
             else
                 st = fill_hop_args(c, prec, recon, out[k], tmp[k], in[k], WL_EVEN, nrhs, 1.0, -kappa[k] * kappa[k], pk,
-                                   sk, flag, h, &np);
+                                   sk, flag, h, &np, nu, 0.0);
             if (st) return st;
             A.per_par[k] = hop_blocks(h.npts, B->block, tps);
             A.start[k] = tiles;
@@ -1369,12 +1431,12 @@ static wl_status batch_iteration(wl_batch *B, std::vector<CGRun> &R, const std::
     }
     wl_status st = batch_apply(B, R0.op, false, kap.data(), R0.prec, R0.recon, R0.nrhs, q.data(),
                                (const void *const *)p.data(), tmp.data(), part.data(), stride.data(), flags.data(),
-                               nblk.data(), R0.s);
+                               nblk.data(), R0.s, R0.mu);
     if (st) return st;
     for (int k = 0; k < n; ++k)
         HIP_TRY(cg_alpha(R[k].sc, R[k].nrhs, R[k].partials, R[k].stride, nblk[k], R[k].done, R[k].s));
     st = batch_apply(B, R0.op, true, kap.data(), R0.prec, R0.recon, R0.nrhs, sv.data(), (const void *const *)q.data(),
-                     tmp.data(), nullptr, nullptr, flags.data(), nullptr, R0.s);
+                     tmp.data(), nullptr, nullptr, flags.data(), nullptr, R0.s, R0.mu);
     if (st) return st;
     for (int k = 0; k < n; ++k)
         if ((st = cg_finish_iteration(R[k], ru[k] != 0))) return st;

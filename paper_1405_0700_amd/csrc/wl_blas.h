@@ -46,6 +46,8 @@ hipError_t cg_update_p(int prec, VecArgs &a, int nhalves, hipStream_t s);
 hipError_t blas_convert(int dprec, int sprec, bool accumulate, VecArgs &a, int nhalves, hipStream_t s);
 // v1 += (a + i b) v0
 hipError_t blas_caxpy(int prec, VecArgs &a, int nhalves, hipStream_t s);
+// v1 = a (1 + i b gamma_5) v0
+hipError_t blas_twist(int prec, VecArgs &a, int nhalves, hipStream_t s);
 // r = b - v  (v2 = r output, v0 = b, v1 = v), ||r||^2 partials: used for true residuals
 hipError_t blas_residual(int prec, VecArgs &a, int nhalves, hipStream_t s);
 

@@ -192,6 +192,26 @@ __global__ void __launch_bounds__(256) k_caxpy(const VecArgs a) {
     }
 }
 
+// v1 = a (1 + i b gamma_5) v0 (gamma_5 = +1 on spins 0, 1 and -1 on spins 2, 3)
+template <int SP>
+__global__ void __launch_bounds__(256) k_twist(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < a.n) {
+        cpx<T> x[12];
+        SpinorIO<SP>::load(a.v[0][h], gid, x);
+        const T sc = (T)a.a;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const T m = k < 6 ? (T)a.b : -(T)a.b;
+            x[k] = {sc * (x[k].re - m * x[k].im), sc * (x[k].im + m * x[k].re)};
+        }
+        SpinorIO<SP>::store(a.v[1][h], gid, x);
+    }
+}
+
 // r = b - v, partial ||r||^2
 template <int SP>
 __global__ void __launch_bounds__(256) k_residual(const VecArgs a) {
@@ -375,6 +395,10 @@ hipError_t blas_axpby(int prec, VecArgs &a, int nh, bool norm, hipStream_t s) {
     } else {
         WL_DISPATCH_PREC(prec, k_axpby, , false)
     }
+}
+hipError_t blas_twist(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_twist)
 }
 hipError_t blas_dot(int prec, VecArgs &a, int nh, hipStream_t s) {
     dim3 grid = vgrid(a, nh);

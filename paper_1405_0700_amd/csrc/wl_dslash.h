@@ -18,6 +18,7 @@ struct HopArgs {
     int nrhs;
     long npts;            // points per parity = vh * nrhs
     double a, b;          // out = a x + b (H in)   (a ignored without EPI_XPAY)
+    double tm_x, tm_h;    // twists: x -> (1 + i tm_x gamma_5) x, H in -> (1 + i tm_h gamma_5) H in (0: none)
     double *partials;     // EPI_NORM: per-block, per-rhs partial sums of ||out||^2
     long part_stride;     // distance between the partials of consecutive rhs
     const int *flag;      // if non-null and *flag == 0 (no system still iterating) the launch does nothing

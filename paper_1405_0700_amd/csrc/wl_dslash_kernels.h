@@ -10,6 +10,18 @@ namespace wl {
 // -i a
 template <typename T> __device__ __forceinline__ cpx<T> mi(cpx<T> a) { return {a.im, -a.re}; }
 
+// v[k] <- (1 + i m gamma_5) v[k] for N consecutive components starting at
+// component `first` of a spinor (component 3 spin + colour; gamma_5 = +1 on
+// spins 0 and 1, -1 on spins 2 and 3 in the chiral basis)
+template <typename T, int N>
+__device__ __forceinline__ void twist(cpx<T> *v, int first, T m) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const T s = first + k < 6 ? m : -m;
+        v[k] = {v[k].re - s * v[k].im, v[k].im + s * v[k].re};
+    }
+}
+
 // h = upper + S * A_mu * lower for both upper spin rows, colour c.
 // A_x = -i s1, A_y = -i s2, A_z = -i s3, A_t = -1.
 template <typename T, int MU, int S>
@@ -308,9 +320,11 @@ __device__ __forceinline__ double hop_point(const HopArgs &a, int par, long gid)
     hop<SP, GP, RECON, DAG, NT, 3, true>(a, par, i, xh, c, rhs, acc);
     hop<SP, GP, RECON, DAG, NT, 3, false>(a, par, i, xh, c, rhs, acc);
     const T b = (T)a.b;
+    if (a.tm_h != 0.0) twist<T, 12>(acc, 0, (T)a.tm_h);
     if constexpr (EPI & EPI_XPAY) {
         cpx<T> xv[12];
         SpinorIO<SP>::load(a.x[par], pt, xv);
+        if (a.tm_x != 0.0) twist<T, 12>(xv, 0, (T)a.tm_x);
         const T aa = (T)a.a;
 #pragma unroll
         for (int k = 0; k < 12; ++k)
@@ -388,9 +402,11 @@ __global__ void __launch_bounds__(256) hop_kernel_mr(const HopArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const long pt = (long)i * a.nrhs + rhs0 + r;
+            if (a.tm_h != 0.0) twist<T, 12>(acc[r], 0, (T)a.tm_h);
             if constexpr (EPI & EPI_XPAY) {
                 cpx<T> xv[12];
                 SpinorIO<SP>::load(a.x[par], pt, xv);
+                if (a.tm_x != 0.0) twist<T, 12>(xv, 0, (T)a.tm_x);
                 const T aa = (T)a.a;
 #pragma unroll
                 for (int k = 0; k < 12; ++k)
@@ -484,9 +500,11 @@ __device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, lon
     double nrm = 0.0;
     if (active) {
         const T b = (T)a.b;
+        if (a.tm_h != 0.0) twist<T, 6>(res, 6 * hf, (T)a.tm_h);
         if constexpr (EPI & EPI_XPAY) {
             cpx<T> xv[6];
             SpinorIO<SP>::load_half(a.x[par], pt, hf, xv);
+            if (a.tm_x != 0.0) twist<T, 6>(xv, 6 * hf, (T)a.tm_x);
             const T aa = (T)a.a;
 #pragma unroll
             for (int k = 0; k < 6; ++k)

@@ -50,6 +50,7 @@ class SolverParams(ctypes.Structure):
         ("reliable_delta", ctypes.c_double),
         ("use_graph", ctypes.c_int),
         ("ru_restart", ctypes.c_int),
+        ("mu", ctypes.c_double),
     ]
 
 
@@ -119,6 +120,12 @@ _SIGS = {
                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_params_default": (None, [ctypes.POINTER(FgcrParams)]),
     "wl_pcgnr_params_default": (None, [ctypes.POINTER(PcgnrParams)]),
+    "wl_dirac_tm_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_eo_prepare_tm": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, _vp]),
+    "wl_eo_reconstruct_tm": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int, _vp]),
     "wl_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]),
     "wl_batch_destroy": (ctypes.c_int, [_vp]),
     "wl_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
@@ -329,6 +336,21 @@ def wl_fgcr_solve(ctx, x, b, kappa, net=None, params: FgcrParams | None = None, 
     st = _check(lib().wl_fgcr_solve(ctx, _ptr(x), _ptr(b), float(kappa), net, ctypes.byref(p), ctypes.byref(info),
                                     _stream(stream)))
     return st, info.as_dict()
+
+
+def wl_dirac_tm_apply(ctx, out, inp, op, dagger, kappa, mu, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_dirac_tm_apply(ctx, _ptr(out), _ptr(inp), op, int(bool(dagger)), float(kappa), float(mu),
+                                          prec, recon, nrhs, _stream(stream)))
+
+
+def wl_eo_prepare_tm(ctx, bhat_e, b_e, b_o, kappa, mu, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_eo_prepare_tm(ctx, _ptr(bhat_e), _ptr(b_e), _ptr(b_o), float(kappa), float(mu), prec, recon,
+                                         nrhs, _stream(stream)))
+
+
+def wl_eo_reconstruct_tm(ctx, x_o, x_e, b_o, kappa, mu, prec=WL_F64, recon=18, nrhs=1, stream=None):
+    return _check(lib().wl_eo_reconstruct_tm(ctx, _ptr(x_o), _ptr(x_e), _ptr(b_o), float(kappa), float(mu), prec,
+                                             recon, nrhs, _stream(stream)))
 
 
 def _ptr_array(items):

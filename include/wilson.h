@@ -87,6 +87,7 @@ typedef enum { WL_OP_D = 0, WL_OP_DHAT = 1 } wl_op;
 typedef struct wl_ctx wl_ctx;
 typedef struct wl_ptc wl_ptc; /* learned preconditioner (see below) */
 typedef struct wl_batch wl_batch; /* several contexts solved together (see below) */
+typedef struct wl_eigcg wl_eigcg; /* deflation space of the incremental EigCG solver (see below) */
 
 /* ---------------------------------------------------------------- context */
 
@@ -454,6 +455,37 @@ wl_status wl_autotune(wl_ctx *ctx, wl_prec prec, int recon, int nrhs, const char
  * system; the result becomes the batch's launch configuration. */
 wl_status wl_batch_autotune(wl_batch *batch, wl_prec prec, int recon, int nrhs, const char *cache_path,
                             int *workgroups, int *block, int *nt, int *tps, double *best_us, int *from_cache);
+
+/* ---------------------------------------------------------------- incremental EigCG
+ *
+ * The paper's solver for many right-hand sides of the twisted-mass operator
+ * (section on EigCG for twisted-mass fermions; algorithm of Stathopoulos and
+ * Orginos): CG on A = M^+ M (M = D or D_hat, optionally twisted, FP64) that
+ * also keeps a search space of m normalised residuals (the Lanczos vectors of
+ * the CG run) and the real tridiagonal matrix built from CG's alpha and beta;
+ * when the space is full it is restarted with the nev lowest Ritz vectors of
+ * T_m and of T_{m-1}.  At convergence the nev lowest Ritz vectors are
+ * orthonormalised into a growing deflation space U (up to max_vectors), with
+ * H = U^+ A U kept on the host.  Every solve starts from the Galerkin guess
+ * x0 = U H^-1 U^+ b (init-CG), which removes the error along the computed low
+ * modes.  The small dense eigenproblems (m <= 64) and the Cholesky solve with
+ * H run on the host; all field operations run on the device (a fused kernel
+ * forms the linear combinations of the search vectors).
+ *
+ * wl_eigcg_create: op, kappa and mu fix A; 1 <= nev <= 16, 2 nev + 2 <= m <= 64;
+ *   allocates (m + 2 nev + 5 + 2 max_vectors) FP64 fields of op's subset.
+ * wl_eigcg_solve: solves A x = b (x: output, the input value is ignored)
+ *   to ||b - A x|| <= tol ||b|| (FP64 true residual; up to 4 restarts from it),
+ *   adding nev vectors to U if collect != 0 and there is room.  info: iters
+ *   (all cycles), restarts, rel_resid, true_rel_resid, seconds.  Synchronous.
+ * wl_eigcg_vectors: number of vectors kept and their Rayleigh quotients
+ *   u^+ A u (ritz may be NULL, else room for max_vectors doubles). */
+wl_status wl_eigcg_create(wl_ctx *ctx, wl_op op, double kappa, double mu, int nev, int m, int max_vectors,
+                          wl_eigcg **out);
+wl_status wl_eigcg_destroy(wl_eigcg *e);
+wl_status wl_eigcg_solve(wl_eigcg *e, void *x, const void *b, double tol, int maxiter, int collect,
+                         wl_solver_info *info, void *stream);
+wl_status wl_eigcg_vectors(const wl_eigcg *e, int *nvec, double *ritz);
 
 /* ---------------------------------------------------------------- kernel timing */
 

@@ -283,3 +283,95 @@ def cg(apply_a, b, tol=1e-10, maxiter=10000, x0=None, fixed_iters=None,
 def cg_normal(apply_m, apply_mdag, b, **kw):
     """CG on the normal equations M^+ M x = b."""
     return cg(lambda v: apply_mdag(apply_m(v)), b, **kw)
+
+
+# --------------------------------------------------------------------------
+# Incremental EigCG (the paper's section on EigCG for twisted-mass fermions;
+# algorithm of Stathopoulos and Orginos): CG on a Hermitian positive-definite
+# A that also tracks a small search space of Lanczos vectors and keeps the
+# lowest Ritz vectors; solutions of later right-hand sides start from the
+# Galerkin projection onto the accumulated vectors (init-CG).
+# --------------------------------------------------------------------------
+class EigCG:
+    """Plain restatement with numpy.  apply_a: A (Hermitian positive definite) on a flat complex vector."""
+
+    def __init__(self, apply_a, nev=10, m=60, max_vectors=300):
+        self.a, self.nev, self.m, self.max_vectors = apply_a, nev, m, max_vectors
+        self.U = []          # orthonormal deflation vectors
+        self.AU = []         # A applied to them
+        self.ritz = []       # Rayleigh quotient u^+ A u of each kept vector
+
+    def _init_guess(self, b):
+        if not self.U:
+            return np.zeros_like(b)
+        U = np.stack(self.U, axis=1)
+        H = U.conj().T @ np.stack(self.AU, axis=1)
+        y = np.linalg.solve(H, U.conj().T @ b)
+        return U @ y
+
+    def solve(self, b, tol=1e-8, maxiter=100000, collect=True):
+        """-> (x, iterations).  Collects nev Ritz vectors while the space has room."""
+        b = np.asarray(b, dtype=np.complex128).ravel()
+        x = self._init_guess(b)
+        r = b - self.a(x)
+        p = r.copy()
+        rho = float(np.vdot(r, r).real)
+        target = tol * tol * float(np.vdot(b, b).real)
+        collect = collect and len(self.U) + self.nev <= self.max_vectors
+        V, T = [], np.zeros((self.m, self.m))
+        alpha_old = beta_old = None
+        pending = None  # coupling row of the next basis vector after a restart
+        k = it = 0
+        while rho > target and it < maxiter:
+            if collect:
+                V.append(r / np.sqrt(rho))
+                k = len(V)
+            q = self.a(p)
+            alpha = rho / float(np.vdot(p, q).real)
+            x = x + alpha * p
+            r = r - alpha * q
+            rho_new = float(np.vdot(r, r).real)
+            beta = rho_new / rho
+            if collect:
+                d = 1.0 / alpha + (beta_old / alpha_old if beta_old is not None else 0.0)
+                T[k - 1, k - 1] = d
+                if pending is not None:
+                    T[: k - 1, k - 1] = pending
+                    T[k - 1, : k - 1] = pending
+                    pending = None
+                off = -np.sqrt(beta) / alpha   # T_{k, k+1}: coupling to the next vector
+                if k == self.m:
+                    # restart: nev lowest Ritz vectors of T_m and of T_{m-1}
+                    w, Y = np.linalg.eigh(T[:k, :k])
+                    w1, Y1 = np.linalg.eigh(T[: k - 1, : k - 1])
+                    Z = np.concatenate([Y[:, : self.nev], np.vstack([Y1[:, : self.nev], np.zeros((1, self.nev))])], axis=1)
+                    Q, _ = np.linalg.qr(Z)
+                    Vm = np.stack(V, axis=1) @ Q
+                    V = [Vm[:, i] for i in range(Q.shape[1])]
+                    Tn = Q.T @ T[:k, :k] @ Q
+                    T = np.zeros((self.m, self.m))
+                    T[: Q.shape[1], : Q.shape[1]] = Tn
+                    pending = Q[k - 1, :] * off
+                elif k < self.m:
+                    T[k - 1, k] = T[k, k - 1] = off
+            alpha_old, beta_old = alpha, beta
+            p = r + beta * p
+            rho = rho_new
+            it += 1
+        if collect and V:
+            k = len(V)
+            w, Y = np.linalg.eigh(T[:k, :k])
+            W = np.stack(V, axis=1) @ Y[:, : self.nev]
+            for i in range(W.shape[1]):
+                v = W[:, i]
+                for _ in range(2):
+                    for u in self.U:
+                        v = v - np.vdot(u, v) * u
+                nv = np.linalg.norm(v)
+                if nv < 1e-10:
+                    continue
+                v = v / nv
+                self.U.append(v)
+                self.AU.append(self.a(v))
+                self.ritz.append(float(np.vdot(v, self.AU[-1]).real))
+        return x, it

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -1924,6 +1925,482 @@ extern "C" wl_status wl_batch_autotune(wl_batch *B, wl_prec prec, int recon, int
     if (tps) *tps = bt;
     if (best_us) *best_us = best_t;
     if (from_cache) *from_cache = cached;
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ incremental EigCG
+namespace {
+using cd = std::complex<double>;
+
+// Eigenvalues (ascending) and orthonormal eigenvectors (column k of the
+// row-major n x n array v) of a real symmetric matrix, cyclic Jacobi rotations.
+void sym_eig(int n, std::vector<double> a, std::vector<double> &w, std::vector<double> &v) {
+    v.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double x = a[(size_t)i * n + j] * a[(size_t)i * n + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double theta = (a[(size_t)q * n + q] - a[(size_t)p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+                    a[(size_t)k * n + p] = c * akp - sn * akq;
+                    a[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+                    a[(size_t)p * n + k] = c * apk - sn * aqk;
+                    a[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+                    v[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    v[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return a[(size_t)x * n + x] < a[(size_t)y * n + y]; });
+    std::vector<double> vs((size_t)n * n);
+    w.resize(n);
+    for (int k = 0; k < n; ++k) {
+        w[k] = a[(size_t)order[k] * n + order[k]];
+        for (int i = 0; i < n; ++i) vs[(size_t)i * n + k] = v[(size_t)i * n + order[k]];
+    }
+    v.swap(vs);
+}
+
+// Solve H y = b in place for a Hermitian positive-definite H (row-major), Cholesky.
+bool hpd_solve(int n, const std::vector<cd> &h, std::vector<cd> &b) {
+    std::vector<cd> l((size_t)n * n, cd(0.0, 0.0));
+    for (int j = 0; j < n; ++j) {
+        double d = h[(size_t)j * n + j].real();
+        for (int k = 0; k < j; ++k) d -= std::norm(l[(size_t)j * n + k]);
+        if (!(d > 0.0)) return false;
+        const double ljj = std::sqrt(d);
+        l[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            cd sum = h[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) sum -= l[(size_t)i * n + k] * std::conj(l[(size_t)j * n + k]);
+            l[(size_t)i * n + j] = sum / ljj;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        cd sum = b[i];
+        for (int k = 0; k < i; ++k) sum -= l[(size_t)i * n + k] * b[k];
+        b[i] = sum / l[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        cd sum = b[i];
+        for (int k = i + 1; k < n; ++k) sum -= std::conj(l[(size_t)k * n + i]) * b[k];
+        b[i] = sum / l[(size_t)i * n + i];
+    }
+    return true;
+}
+}  // namespace
+
+struct wl_eigcg {
+    wl_ctx *c = nullptr;
+    int op = WL_OP_DHAT, nev = 10, m = 60, max_vec = 0;
+    double kappa = 0.0, mu = 0.0;
+    int nh = 1;
+    size_t fbytes = 0;   // one FP64 single-rhs field of the operator's subset
+    long nelem = 0;      // complex doubles per field
+    char *ubuf = nullptr, *aubuf = nullptr, *vbuf = nullptr, *wbuf = nullptr;
+    double2 *coef = nullptr;
+    int nvec = 0;
+    std::vector<cd> H;   // U^+ A U, row-major nvec x nvec
+    std::vector<double> ritz;
+    void *U(int k) const { return ubuf + (size_t)k * fbytes; }
+    void *AU(int k) const { return aubuf + (size_t)k * fbytes; }
+    void *V(int slot) const { return vbuf + (size_t)slot * fbytes; }
+    void *W(int k) const { return wbuf + (size_t)k * fbytes; }  // r, p, q, t, tmp (odd)
+};
+
+extern "C" wl_status wl_eigcg_create(wl_ctx *c, wl_op op, double kappa, double mu, int nev, int m, int max_vectors,
+                                     wl_eigcg **out) {
+    g_err.clear();
+    if (!c || !out) return fail(WL_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (op != WL_OP_D && op != WL_OP_DHAT) return fail(WL_ERR_ARG, "bad operator %d", (int)op);
+    if (!std::isfinite(kappa) || !std::isfinite(mu)) return fail(WL_ERR_ARG, "non-finite kappa or mu");
+    if (nev < 1 || 2 * nev > LC_MAX_OUT || m < 2 * nev + 2 || m > LC_MAX_IN || max_vectors < 0)
+        return fail(WL_ERR_ARG, "need 1 <= nev <= 16, 2 nev + 2 <= m <= 64, max_vectors >= 0");
+    wl_eigcg *E = new wl_eigcg();
+    E->c = c;
+    E->op = op;
+    E->kappa = kappa;
+    E->mu = mu;
+    E->nev = nev;
+    E->m = m;
+    E->max_vec = max_vectors;
+    E->nh = op == WL_OP_D ? 2 : 1;
+    E->fbytes = half_bytes(c, WL_F64, 1) * E->nh;
+    E->nelem = (long)(E->fbytes / 16);
+    hipError_t e = hipSuccess;
+    if (max_vectors > 0) {
+        e = hipMalloc(&E->ubuf, E->fbytes * max_vectors);
+        if (e == hipSuccess) e = hipMalloc(&E->aubuf, E->fbytes * max_vectors);
+    }
+    if (e == hipSuccess) e = hipMalloc(&E->vbuf, E->fbytes * (m + 2 * nev));
+    if (e == hipSuccess) e = hipMalloc(&E->wbuf, E->fbytes * 5);
+    if (e == hipSuccess) e = hipMalloc(&E->coef, sizeof(double2) * LC_MAX_IN * LC_MAX_OUT);
+    if (e != hipSuccess) {
+        wl_eigcg_destroy(E);
+        return fail(WL_ERR_NOMEM, "EigCG workspace: %s", hipGetErrorString(e));
+    }
+    const void *lk;
+    size_t sl;
+    wl_status st = get_links(c, WL_F64, 18, &lk, &sl);
+    if (st) {
+        wl_eigcg_destroy(E);
+        return st;
+    }
+    *out = E;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_eigcg_destroy(wl_eigcg *E) {
+    if (!E) return WL_OK;
+    (void)hipDeviceSynchronize();
+    for (void *p : {(void *)E->ubuf, (void *)E->aubuf, (void *)E->vbuf, (void *)E->wbuf, (void *)E->coef})
+        if (p) (void)hipFree(p);
+    delete E;
+    return WL_OK;
+}
+
+extern "C" wl_status wl_eigcg_vectors(const wl_eigcg *E, int *nvec, double *ritz) {
+    g_err.clear();
+    if (!E || !nvec) return fail(WL_ERR_ARG, "null argument");
+    *nvec = E->nvec;
+    if (ritz)
+        for (int k = 0; k < E->nvec; ++k) ritz[k] = E->ritz[k];
+    return WL_OK;
+}
+
+namespace {
+// FP64 single-rhs field helpers of an EigCG context (all synchronous where they return a number)
+struct EigOps {
+    wl_eigcg *E;
+    hipStream_t s;
+    long stride;
+    size_t hb;
+    VecArgs vec(int n) const { return vec_args(E->c, WL_F64, 1); }
+    wl_status apply_a(void *out, const void *in, double *pap) {
+        // out = M^+ M in; *pap = ||M in||^2 (= <in, A in>) when pap != null
+        wl_ctx *c = E->c;
+        long nblk = 0;
+        wl_status st = apply_m(c, E->op, false, E->kappa, WL_F64, 18, 1, E->W(3), in, E->W(4),
+                               pap ? (double *)c->buf[S_PARTIALS] : nullptr, stride, nullptr, s, &nblk, E->mu);
+        if (st) return st;
+        if (pap && (st = reduce_to_host(c, 1, stride, nblk, pap, s))) return st;
+        return apply_m(c, E->op, true, E->kappa, WL_F64, 18, 1, out, E->W(3), E->W(4), nullptr, 0, nullptr, s,
+                       nullptr, E->mu);
+    }
+    wl_status dot(const void *x, const void *y, cd *out) {
+        VecArgs v = vec_args(E->c, WL_F64, 1);
+        set_vec(v, 0, x, hb);
+        set_vec(v, 1, y, hb);
+        v.partials = (double *)E->c->buf[S_PARTIALS];
+        v.part_stride = stride;
+        HIP_TRY(blas_dot(WL_F64, v, E->nh, s));
+        double d[2];
+        wl_status st = reduce_to_host(E->c, 2, stride, blas_blocks(v.n) * E->nh, d, s);
+        *out = cd(d[0], d[1]);
+        return st;
+    }
+    // y = a x + b y [, *n2 = ||y||^2]
+    wl_status axpby(double a, const void *x, double b, void *y, double *n2) {
+        VecArgs v = vec_args(E->c, WL_F64, 1);
+        set_vec(v, 0, x, hb);
+        set_vec(v, 1, y, hb);
+        v.a = a;
+        v.b = b;
+        v.partials = (double *)E->c->buf[S_PARTIALS];
+        v.part_stride = stride;
+        HIP_TRY(blas_axpby(WL_F64, v, E->nh, n2 != nullptr, s));
+        if (n2) return reduce_to_host(E->c, 1, stride, blas_blocks(v.n) * E->nh, n2, s);
+        return WL_OK;
+    }
+    wl_status scale(double a, const void *x, void *y) {  // y = a x
+        VecArgs v = vec_args(E->c, WL_F64, 1);
+        set_vec(v, 0, x, hb);
+        set_vec(v, 1, y, hb);
+        v.a = a;
+        v.b = 0.0;
+        HIP_TRY(blas_twist(WL_F64, v, E->nh, s));
+        return WL_OK;
+    }
+    wl_status caxpy(cd a, const void *x, void *y) {
+        VecArgs v = vec_args(E->c, WL_F64, 1);
+        set_vec(v, 0, x, hb);
+        set_vec(v, 1, y, hb);
+        v.a = a.real();
+        v.b = a.imag();
+        HIP_TRY(blas_caxpy(WL_F64, v, E->nh, s));
+        return WL_OK;
+    }
+    // out[o] (+)= sum_j coef[j][o] in[j] for nin <= 64, nout <= 32 (coef row-major nin x nout)
+    wl_status lincomb(const std::vector<const void *> &in, const std::vector<void *> &out, const std::vector<cd> &coef,
+                      bool accumulate) {
+        LinCombArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.nin = (int)in.size();
+        a.nout = (int)out.size();
+        for (int j = 0; j < a.nin; ++j) a.in[j] = (const double2 *)in[j];
+        for (int o = 0; o < a.nout; ++o) a.out[o] = (double2 *)out[o];
+        std::vector<double2> h(coef.size());
+        for (size_t k = 0; k < coef.size(); ++k) h[k] = make_double2(coef[k].real(), coef[k].imag());
+        HIP_TRY(hipMemcpyAsync(E->coef, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, s));
+        a.coef = E->coef;
+        a.accumulate = accumulate ? 1 : 0;
+        a.n = E->nelem;
+        HIP_TRY(blas_lincomb(a, s));
+        HIP_TRY(hipStreamSynchronize(s));  // the coefficient buffer is reused by the next call
+        return WL_OK;
+    }
+};
+}  // namespace
+
+extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double tol, int maxiter, int collect,
+                                    wl_solver_info *info, void *stream) {
+    g_err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!E) return fail(WL_ERR_ARG, "null EigCG context");
+    wl_ctx *c = E->c;
+    const int subset = E->op == WL_OP_D ? WL_FULL : WL_EVEN;
+    wl_status st = check_field_args(c, subset, WL_F64, 1);
+    if (st) return st;
+    if (!x || !b || !aligned16(x) || !aligned16(b)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    if (!(tol > 0.0) || maxiter < 1) return fail(WL_ERR_ARG, "bad tolerance or iteration limit");
+    if (overlap(x, E->fbytes, b, E->fbytes)) return fail(WL_ERR_ARG, "x and b overlap");
+    EigOps O{E, (hipStream_t)stream, part_stride_for(c, 1), half_bytes(c, WL_F64, 1)};
+    if ((st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * O.stride)) ||
+        (st = ensure_buf(c, S_SCAL, 64 * sizeof(double) * 2)))
+        return st;
+    void *r = E->W(0), *p = E->W(1), *q = E->W(2);
+    double b2 = 0.0;
+    {
+        cd d;
+        if ((st = O.dot(b, b, &d))) return st;
+        b2 = d.real();
+    }
+    wl_solver_info out{};
+    // init-CG: x0 = U H^-1 U^+ b
+    {
+        VecArgs v = vec_args(c, WL_F64, 1);
+        set_vec(v, 0, x, O.hb);
+        HIP_TRY(blas_zero(WL_F64, v, E->nh, O.s));
+    }
+    if (E->nvec > 0 && b2 > 0.0) {
+        const int K = E->nvec;
+        std::vector<cd> y(K);
+        for (int k = 0; k < K; ++k)
+            if ((st = O.dot(E->U(k), b, &y[k]))) return st;
+        if (!hpd_solve(K, E->H, y)) return fail(WL_BREAKDOWN, "deflation matrix not positive definite");
+        for (int k0 = 0; k0 < K; k0 += LC_MAX_IN) {
+            const int kn = std::min(LC_MAX_IN, K - k0);
+            std::vector<const void *> in(kn);
+            std::vector<cd> cf(kn);
+            for (int k = 0; k < kn; ++k) {
+                in[k] = E->U(k0 + k);
+                cf[k] = y[k0 + k];
+            }
+            if ((st = O.lincomb(in, {x}, cf, true))) return st;
+        }
+    }
+    if (!(b2 > 0.0)) {
+        HIP_TRY(hipStreamSynchronize(O.s));
+        if (info) *info = out;
+        return WL_OK;
+    }
+    const double target2 = tol * tol * b2;
+    // search space (slots of vbuf), tridiagonal / projected matrix T, pending coupling after a restart
+    const int m = E->m, nev = E->nev, nslot = m + 2 * nev;
+    bool track = collect && E->nvec + nev <= E->max_vec;
+    std::vector<int> cols;  // physical slot of each column
+    std::vector<char> used(nslot, 0);
+    std::vector<double> T((size_t)m * m, 0.0), pending;
+    int total = 0, restarts = 0;
+    double rho = 0.0, true2 = 0.0;
+    for (int cycle = 0;; ++cycle) {
+        // r = b - A x (FP64 true residual), p = r
+        if ((st = O.apply_a(q, x, nullptr)) || (st = O.scale(1.0, b, r)) || (st = O.axpby(-1.0, q, 1.0, r, &rho)))
+            return st;
+        true2 = rho;
+        if (rho <= target2 || total >= maxiter || cycle >= 4) break;
+        if (cycle > 0) {
+            ++restarts;
+            track = false;  // the Lanczos relation holds within one uninterrupted CG run only
+        }
+        if ((st = O.scale(1.0, r, p))) return st;
+        double alpha_old = 0.0, beta_old = 0.0;
+        bool have_old = false;
+        while (rho > target2 && total < maxiter) {
+            int k = (int)cols.size();
+            if (track) {
+                int slot = 0;
+                while (used[slot]) ++slot;
+                used[slot] = 1;
+                cols.push_back(slot);
+                k = (int)cols.size();
+                if ((st = O.scale(1.0 / std::sqrt(rho), r, E->V(slot)))) return st;
+            }
+            double pap = 0.0;
+            if ((st = O.apply_a(q, p, &pap))) return st;
+            if (!(pap > 0.0) || !std::isfinite(pap)) return fail(WL_BREAKDOWN, "EigCG breakdown: <p, A p> = %g", pap);
+            const double alpha = rho / pap;
+            double rho_new = 0.0;
+            if ((st = O.axpby(alpha, p, 1.0, x, nullptr)) || (st = O.axpby(-alpha, q, 1.0, r, &rho_new))) return st;
+            const double beta = rho_new / rho;
+            if (track) {
+                T[(size_t)(k - 1) * m + (k - 1)] = 1.0 / alpha + (have_old ? beta_old / alpha_old : 0.0);
+                if (!pending.empty()) {
+                    for (int i = 0; i < k - 1; ++i)
+                        T[(size_t)i * m + (k - 1)] = T[(size_t)(k - 1) * m + i] = pending[i];
+                    pending.clear();
+                }
+                const double off = -std::sqrt(beta) / alpha;
+                if (k == m) {
+                    // restart with the nev lowest Ritz vectors of T_m and of T_{m-1}
+                    std::vector<double> tm((size_t)m * m), tm1((size_t)(m - 1) * (m - 1)), w, Y, w1, Y1;
+                    for (int i = 0; i < m; ++i)
+                        for (int j = 0; j < m; ++j) tm[(size_t)i * m + j] = T[(size_t)i * m + j];
+                    for (int i = 0; i < m - 1; ++i)
+                        for (int j = 0; j < m - 1; ++j) tm1[(size_t)i * (m - 1) + j] = T[(size_t)i * m + j];
+                    sym_eig(m, tm, w, Y);
+                    sym_eig(m - 1, tm1, w1, Y1);
+                    // Z = [Y(:, :nev), [Y1(:, :nev); 0]], orthonormalised (two Gram-Schmidt passes)
+                    std::vector<std::vector<double>> Z;
+                    for (int j = 0; j < 2 * nev; ++j) {
+                        std::vector<double> z(m, 0.0);
+                        for (int i = 0; i < m; ++i)
+                            z[i] = j < nev ? Y[(size_t)i * m + j] : (i < m - 1 ? Y1[(size_t)i * (m - 1) + (j - nev)] : 0.0);
+                        for (int pass = 0; pass < 2; ++pass)
+                            for (auto &zz : Z) {
+                                double d = 0.0;
+                                for (int i = 0; i < m; ++i) d += zz[i] * z[i];
+                                for (int i = 0; i < m; ++i) z[i] -= d * zz[i];
+                            }
+                        double nz = 0.0;
+                        for (int i = 0; i < m; ++i) nz += z[i] * z[i];
+                        nz = std::sqrt(nz);
+                        if (nz < 1e-10) continue;
+                        for (int i = 0; i < m; ++i) z[i] /= nz;
+                        Z.push_back(z);
+                    }
+                    const int kq = (int)Z.size();
+                    std::vector<const void *> in(m);
+                    for (int i = 0; i < m; ++i) in[i] = E->V(cols[i]);
+                    std::vector<int> fresh;
+                    for (int sl = 0; sl < nslot && (int)fresh.size() < kq; ++sl)
+                        if (!used[sl]) fresh.push_back(sl);
+                    std::vector<void *> outs(kq);
+                    for (int j = 0; j < kq; ++j) outs[j] = E->V(fresh[j]);
+                    std::vector<cd> cf((size_t)m * kq);
+                    for (int i = 0; i < m; ++i)
+                        for (int j = 0; j < kq; ++j) cf[(size_t)i * kq + j] = Z[j][i];
+                    if ((st = O.lincomb(in, outs, cf, false))) return st;
+                    for (int sl : cols) used[sl] = 0;
+                    cols.clear();
+                    for (int j = 0; j < kq; ++j) {
+                        used[fresh[j]] = 1;
+                        cols.push_back(fresh[j]);
+                    }
+                    // T <- Z^T T_m Z, and the next vector couples through the last row of Z
+                    std::vector<double> tn((size_t)kq * kq, 0.0);
+                    for (int a = 0; a < kq; ++a)
+                        for (int bb = 0; bb < kq; ++bb) {
+                            double sum = 0.0;
+                            for (int i = 0; i < m; ++i)
+                                for (int j = 0; j < m; ++j) sum += Z[a][i] * T[(size_t)i * m + j] * Z[bb][j];
+                            tn[(size_t)a * kq + bb] = sum;
+                        }
+                    std::fill(T.begin(), T.end(), 0.0);
+                    for (int a = 0; a < kq; ++a)
+                        for (int bb = 0; bb < kq; ++bb) T[(size_t)a * m + bb] = tn[(size_t)a * kq + bb];
+                    pending.assign(kq, 0.0);
+                    for (int a = 0; a < kq; ++a) pending[a] = Z[a][m - 1] * off;
+                } else {
+                    T[(size_t)(k - 1) * m + k] = T[(size_t)k * m + (k - 1)] = off;
+                }
+            }
+            alpha_old = alpha;
+            beta_old = beta;
+            have_old = true;
+            if ((st = O.axpby(1.0, r, beta, p, nullptr))) return st;
+            rho = rho_new;
+            ++total;
+        }
+    }
+    // keep the nev lowest Ritz vectors of the tracked space
+    if (collect && track && !cols.empty()) {
+        const int k = (int)cols.size();
+        std::vector<double> tk((size_t)k * k), w, Y;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) tk[(size_t)i * k + j] = T[(size_t)i * m + j];
+        sym_eig(k, tk, w, Y);
+        const int nr = std::min(nev, k);
+        std::vector<const void *> in(k);
+        for (int i = 0; i < k; ++i) in[i] = E->V(cols[i]);
+        std::vector<int> fresh;
+        for (int sl = 0; sl < nslot && (int)fresh.size() < nr; ++sl)
+            if (!used[sl]) fresh.push_back(sl);
+        std::vector<void *> outs(nr);
+        for (int j = 0; j < nr; ++j) outs[j] = E->V(fresh[j]);
+        std::vector<cd> cf((size_t)k * nr);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < nr; ++j) cf[(size_t)i * nr + j] = Y[(size_t)i * k + j];
+        if ((st = O.lincomb(in, outs, cf, false))) return st;
+        for (int j = 0; j < nr && E->nvec < E->max_vec; ++j) {
+            void *wv = outs[j];
+            for (int pass = 0; pass < 2; ++pass)
+                for (int u = 0; u < E->nvec; ++u) {
+                    cd d;
+                    if ((st = O.dot(E->U(u), wv, &d)) || (st = O.caxpy(-d, E->U(u), wv))) return st;
+                }
+            cd n2;
+            if ((st = O.dot(wv, wv, &n2))) return st;
+            if (!(n2.real() > 1e-20)) continue;
+            const int K = E->nvec;
+            if ((st = O.scale(1.0 / std::sqrt(n2.real()), wv, E->U(K)))) return st;
+            double rq = 0.0;
+            if ((st = O.apply_a(E->AU(K), E->U(K), &rq))) return st;
+            std::vector<cd> Hn((size_t)(K + 1) * (K + 1));
+            for (int i = 0; i < K; ++i)
+                for (int jj = 0; jj < K; ++jj) Hn[(size_t)i * (K + 1) + jj] = E->H[(size_t)i * K + jj];
+            for (int i = 0; i < K; ++i) {
+                cd h;
+                if ((st = O.dot(E->U(i), E->AU(K), &h))) return st;
+                Hn[(size_t)i * (K + 1) + K] = h;
+                Hn[(size_t)K * (K + 1) + i] = std::conj(h);
+            }
+            Hn[(size_t)K * (K + 1) + K] = cd(rq, 0.0);
+            E->H.swap(Hn);
+            E->ritz.push_back(rq);
+            E->nvec = K + 1;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(O.s));
+    out.iters = total;
+    out.restarts = restarts;
+    out.rel_resid = std::sqrt(rho / b2);
+    out.true_rel_resid = std::sqrt(true2 / b2);
+    out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = out;
+    if (true2 > target2) return fail(WL_NOT_CONVERGED, "EigCG did not reach the tolerance");
     return WL_OK;
 }
 

@@ -48,6 +48,19 @@ hipError_t blas_convert(int dprec, int sprec, bool accumulate, VecArgs &a, int n
 hipError_t blas_caxpy(int prec, VecArgs &a, int nhalves, hipStream_t s);
 // v1 = a (1 + i b gamma_5) v0
 hipError_t blas_twist(int prec, VecArgs &a, int nhalves, hipStream_t s);
+
+// Linear combinations of FP64 fields viewed as arrays of n complex numbers:
+// out[o] (+)= sum_j coef[j * nout + o] in[j], each input read once.
+constexpr int LC_MAX_IN = 64, LC_MAX_OUT = 32;
+struct LinCombArgs {
+    const double2 *in[LC_MAX_IN];
+    double2 *out[LC_MAX_OUT];
+    const double2 *coef;  // device, nin * nout complex
+    int nin, nout;
+    int accumulate;       // add to out instead of overwriting it
+    long n;
+};
+hipError_t blas_lincomb(const LinCombArgs &a, hipStream_t s);
 // r = b - v  (v2 = r output, v0 = b, v1 = v), ||r||^2 partials: used for true residuals
 hipError_t blas_residual(int prec, VecArgs &a, int nhalves, hipStream_t s);
 

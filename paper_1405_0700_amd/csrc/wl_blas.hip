@@ -212,6 +212,28 @@ __global__ void __launch_bounds__(256) k_twist(const VecArgs a) {
     }
 }
 
+__global__ void __launch_bounds__(256) k_lincomb(const LinCombArgs a) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.n) return;
+    double2 acc[LC_MAX_OUT];
+#pragma unroll
+    for (int o = 0; o < LC_MAX_OUT; ++o) acc[o] = (a.accumulate && o < a.nout) ? a.out[o][e] : make_double2(0.0, 0.0);
+    for (int j = 0; j < a.nin; ++j) {
+        const double2 v = a.in[j][e];
+        const double2 *c = a.coef + (long)j * a.nout;
+#pragma unroll
+        for (int o = 0; o < LC_MAX_OUT; ++o)
+            if (o < a.nout) {
+                const double2 w = c[o];
+                acc[o].x = fma(w.x, v.x, fma(-w.y, v.y, acc[o].x));
+                acc[o].y = fma(w.x, v.y, fma(w.y, v.x, acc[o].y));
+            }
+    }
+#pragma unroll
+    for (int o = 0; o < LC_MAX_OUT; ++o)
+        if (o < a.nout) a.out[o][e] = acc[o];
+}
+
 // r = b - v, partial ||r||^2
 template <int SP>
 __global__ void __launch_bounds__(256) k_residual(const VecArgs a) {
@@ -395,6 +417,12 @@ hipError_t blas_axpby(int prec, VecArgs &a, int nh, bool norm, hipStream_t s) {
     } else {
         WL_DISPATCH_PREC(prec, k_axpby, , false)
     }
+}
+hipError_t blas_lincomb(const LinCombArgs &a, hipStream_t s) {
+    if (a.nin < 1 || a.nin > LC_MAX_IN || a.nout < 1 || a.nout > LC_MAX_OUT || a.n < 0) return hipErrorInvalidValue;
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 hipError_t blas_twist(int prec, VecArgs &a, int nh, hipStream_t s) {
     dim3 grid = vgrid(a, nh);

@@ -120,6 +120,12 @@ _SIGS = {
                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_params_default": (None, [ctypes.POINTER(FgcrParams)]),
     "wl_pcgnr_params_default": (None, [ctypes.POINTER(PcgnrParams)]),
+    "wl_eigcg_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(_vp)]),
+    "wl_eigcg_destroy": (ctypes.c_int, [_vp]),
+    "wl_eigcg_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(SolverInfo), _vp]),
+    "wl_eigcg_vectors": (ctypes.c_int, [_vp, _ip, _dp]),
     "wl_dirac_tm_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_eo_prepare_tm": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -351,6 +357,31 @@ def wl_eo_prepare_tm(ctx, bhat_e, b_e, b_o, kappa, mu, prec=WL_F64, recon=18, nr
 def wl_eo_reconstruct_tm(ctx, x_o, x_e, b_o, kappa, mu, prec=WL_F64, recon=18, nrhs=1, stream=None):
     return _check(lib().wl_eo_reconstruct_tm(ctx, _ptr(x_o), _ptr(x_e), _ptr(b_o), float(kappa), float(mu), prec,
                                              recon, nrhs, _stream(stream)))
+
+
+def wl_eigcg_create(ctx, op, kappa, mu=0.0, nev=10, m=60, max_vectors=300):
+    out = _vp()
+    _check(lib().wl_eigcg_create(ctx, int(op), float(kappa), float(mu), int(nev), int(m), int(max_vectors),
+                                 ctypes.byref(out)))
+    return out.value
+
+
+def wl_eigcg_destroy(e):
+    return _check(lib().wl_eigcg_destroy(e))
+
+
+def wl_eigcg_solve(e, x, b, tol=1e-8, maxiter=100000, collect=True, stream=None):
+    info = SolverInfo()
+    st = _check(lib().wl_eigcg_solve(e, _ptr(x), _ptr(b), float(tol), int(maxiter), int(bool(collect)),
+                                     ctypes.byref(info), _stream(stream)))
+    return st, info.as_dict()
+
+
+def wl_eigcg_vectors(e, max_vectors=300):
+    n = ctypes.c_int()
+    buf = (ctypes.c_double * max(1, max_vectors))()
+    _check(lib().wl_eigcg_vectors(e, ctypes.byref(n), buf))
+    return list(buf[: n.value])
 
 
 def _ptr_array(items):

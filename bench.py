@@ -141,10 +141,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
-    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch"], default="eo-cg",
+    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch", "eigcg"],
+                    default="eo-cg",
                     help="eo-cg: the headline (24^3x48 FP64 e/o CG); mixed: 32^3x64 FP64 vs mixed-precision CG; "
                          "propagator: 12 point sources, multi-RHS vs sequential; learned: train the PTC "
-                         "preconditioner on 16^3x32 fields and compare FGCR with plain FP64 CG on 32^3x64")
+                         "preconditioner on 16^3x32 fields and compare FGCR with plain FP64 CG on 32^3x64; "
+                         "eigcg: a sequence of right-hand sides, incremental EigCG vs plain FP64 CG")
+    ap.add_argument("--eig-kappa", type=float, default=0.135, help="eigcg: hopping parameter")
+    ap.add_argument("--eig-mu", type=float, default=0.0, help="eigcg: twisted mass")
+    ap.add_argument("--eig-rhs", type=int, default=35, help="eigcg: right-hand sides in the sequence")
+    ap.add_argument("--eig-collect", type=int, default=30, help="eigcg: right-hand sides that add vectors")
     ap.add_argument("--epochs", type=int, default=20, help="learned: training epochs")
     ap.add_argument("--train-fields", type=int, default=8, help="learned: number of 16^3x32 training fields")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
@@ -178,6 +184,8 @@ def main():
         return run_learned(args)
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "eigcg":
+        return run_eigcg(args)
     return run_eo_cg(args)
 
 
@@ -593,6 +601,79 @@ def run_learned(args):
                                             for k, v in res.items() if k != "cg_f64"}}))
     W.wl_ptc_destroy(net)
     W.wl_ptc_destroy(fresh)
+
+
+def run_eigcg(args):
+    """A sequence of right-hand sides of A = D_hat^+ D_hat (optionally twisted) on 24^3x48,
+    links exp(0.2iH) seed 401, Gaussian sources on the even sites (seeds 440...), all to
+    ||b - A x|| <= 1e-8 ||b|| in FP64: plain CG (the library's captured FP64 CG) per
+    right-hand side against incremental EigCG with nev = 10, m = 60, up to 300 vectors,
+    collecting on the first `eig_collect` right-hand sides (the paper's protocol for its
+    35 right-hand sides)."""
+    import torch
+    from paper_1405_0700_amd import synth
+    from paper_1405_0700_amd import wilson as W
+    dims, tol = (24, 24, 24, 48), 1e-8
+    kappa, mu, nrhs, ncol = args.eig_kappa, args.eig_mu, args.eig_rhs, args.eig_collect
+    log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    lat = W.Lattice.create(synth.su3_links(dims, 0.2, 401), (1, 1, 1, -1))
+    bs = [lat.pack(synth.gaussian_spinor(dims, seed=440 + k, nsites=lat.volume // 2), W.WL_EVEN)
+          for k in range(nrhs)]
+    x = lat.new(W.WL_EVEN)
+    p = W.wl_solver_params_default()
+    p.tol, p.mu, p.maxiter = tol, mu, 100000
+
+    def cg(b):
+        x.zero_()
+        return W.wl_cg_solve(lat.ctx, x, b, W.WL_OP_DHAT, kappa, params=p)
+
+    cg(bs[0])  # warm-up: builds the FP64 links and captures the iteration graph
+    torch.cuda.synchronize()
+    cg_ms, cg_it = [], []
+    for b in bs:
+        t = time.perf_counter()
+        st, info = cg(b)
+        torch.cuda.synchronize()
+        cg_ms.append((time.perf_counter() - t) * 1e3)
+        cg_it.append(info[0]["iters"])
+        if st != W.WL_OK:
+            log("cg status %d" % st)
+    log("cg iterations %s, %.1f ms total" % (cg_it, sum(cg_ms)))
+    e = W.wl_eigcg_create(lat.ctx, W.WL_OP_DHAT, kappa, mu, 10, 60, 300)
+    eig_ms, eig_it, eig_res = [], [], []
+    for k, b in enumerate(bs):
+        t = time.perf_counter()
+        st, info = W.wl_eigcg_solve(e, x, b, tol=tol, collect=k < ncol)
+        eig_ms.append((time.perf_counter() - t) * 1e3)
+        eig_it.append(info["iters"])
+        eig_res.append(info["true_rel_resid"])
+        if st != W.WL_OK:
+            log("eigcg status %d" % st)
+        log("eigcg rhs %d: %d iterations, %.1f ms, %d vectors" % (k, info["iters"], eig_ms[-1],
+                                                                 len(W.wl_eigcg_vectors(e, 300))))
+    ritz = W.wl_eigcg_vectors(e, 300)
+    W.wl_eigcg_destroy(e)
+    # the same sequence with EigCG's own CG loop and no deflation: its per-iteration cost
+    e0 = W.wl_eigcg_create(lat.ctx, W.WL_OP_DHAT, kappa, mu, 10, 60, 0)
+    t = time.perf_counter()
+    _, info0 = W.wl_eigcg_solve(e0, x, bs[0], tol=tol, collect=False)
+    plain_loop_ms = (time.perf_counter() - t) * 1e3
+    W.wl_eigcg_destroy(e0)
+    tail = slice(ncol, nrhs)
+    print(json.dumps({
+        "metric": "time for a sequence of right-hand sides: incremental EigCG vs plain FP64 CG", "unit": "ms",
+        "higher_is_better": False,
+        "workload": "24^3x48, links exp(0.2iH) seed 401, kappa %g, mu %g, %d Gaussian even-site sources "
+                    "(seeds 440-%d), tol 1e-8, A = D_hat^+ D_hat; EigCG nev 10, m 60, max 300 vectors, "
+                    "collecting on the first %d" % (kappa, mu, nrhs, 439 + nrhs, ncol),
+        "cg": {"total_ms": round(sum(cg_ms), 1), "iters": cg_it, "ms": [round(v, 1) for v in cg_ms]},
+        "eigcg": {"total_ms": round(sum(eig_ms), 1), "iters": eig_it, "ms": [round(v, 1) for v in eig_ms],
+                  "max_true_rel_resid": max(eig_res), "lowest_ritz": [round(r, 8) for r in sorted(ritz)[:5]]},
+        "eigcg_loop_no_deflation": {"ms": round(plain_loop_ms, 1), "iters": info0["iters"]},
+        "speedup_total": round(sum(cg_ms) / sum(eig_ms), 3),
+        "speedup_deflated_rhs": (round(sum(cg_ms[tail]) / sum(eig_ms[tail]), 3) if nrhs > ncol else None),
+        "iteration_ratio_last": round(cg_it[-1] / max(1, eig_it[-1]), 3)}))
+    lat.close()
 
 
 if __name__ == "__main__":

@@ -469,23 +469,32 @@ wl_status wl_batch_autotune(wl_batch *batch, wl_prec prec, int recon, int nrhs, 
  * H = U^+ A U kept on the host.  Every solve starts from the Galerkin guess
  * x0 = U H^-1 U^+ b (init-CG), which removes the error along the computed low
  * modes.  The small dense eigenproblems (m <= 64) and the Cholesky solve with
- * H run on the host; all field operations run on the device (a fused kernel
- * forms the linear combinations of the search vectors).
+ * H run on the host; all field operations run on the device: fused kernels
+ * form linear combinations of up to 64 fields, and blocks of up to 64 x 16
+ * inner products <u_j, w_o> in one pass (on the FP64 matrix cores); they serve
+ * the restarts, the init-CG projection, the block classical Gram-Schmidt (two
+ * passes) of the new vectors against U, and the new columns of H.
  *
  * wl_eigcg_create: op, kappa and mu fix A; 1 <= nev <= 16, 2 nev + 2 <= m <= 64;
  *   allocates (m + 2 nev + 5 + 2 max_vectors) FP64 fields of op's subset.
  * wl_eigcg_solve: solves A x = b (x: output, the input value is ignored)
  *   to ||b - A x|| <= tol ||b|| (FP64 true residual; up to 4 restarts from it),
- *   adding nev vectors to U if collect != 0 and there is room.  info: iters
- *   (all cycles), restarts, rel_resid, true_rel_resid, seconds.  Synchronous.
+ *   adding nev vectors to U if collect != 0 and there is room; otherwise (no
+ *   vectors to collect) it runs wl_cg_solve's FP64 CG from the init-CG guess.
+ *   info: iters (all cycles), restarts, rel_resid, true_rel_resid, seconds.
+ *   Synchronous.
  * wl_eigcg_vectors: number of vectors kept and their Rayleigh quotients
- *   u^+ A u (ritz may be NULL, else room for max_vectors doubles). */
+ *   u^+ A u (ritz may be NULL, else room for max_vectors doubles).
+ * wl_eigcg_eigenvalues: the Ritz values of A on the whole deflation space, the
+ *   eigenvalues of H = U^+ A U in ascending order (*n = number of vectors;
+ *   vals may be NULL, else room for max_vectors doubles).  Host-side, O(n^3). */
 wl_status wl_eigcg_create(wl_ctx *ctx, wl_op op, double kappa, double mu, int nev, int m, int max_vectors,
                           wl_eigcg **out);
 wl_status wl_eigcg_destroy(wl_eigcg *e);
 wl_status wl_eigcg_solve(wl_eigcg *e, void *x, const void *b, double tol, int maxiter, int collect,
                          wl_solver_info *info, void *stream);
 wl_status wl_eigcg_vectors(const wl_eigcg *e, int *nvec, double *ritz);
+wl_status wl_eigcg_eigenvalues(const wl_eigcg *e, int *n, double *vals);
 
 /* ---------------------------------------------------------------- kernel timing */
 

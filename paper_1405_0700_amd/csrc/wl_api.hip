@@ -2090,6 +2090,27 @@ extern "C" wl_status wl_eigcg_vectors(const wl_eigcg *E, int *nvec, double *ritz
     return WL_OK;
 }
 
+extern "C" wl_status wl_eigcg_eigenvalues(const wl_eigcg *E, int *n, double *vals) {
+    g_err.clear();
+    if (!E || !n) return fail(WL_ERR_ARG, "null argument");
+    const int K = E->nvec;
+    *n = K;
+    if (!vals || K == 0) return WL_OK;
+    // H = X + iY Hermitian: the real symmetric [[X, -Y], [Y, X]] has each eigenvalue of H twice
+    const int n2 = 2 * K;
+    std::vector<double> m((size_t)n2 * n2), w, v;
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j) {
+            const cd h = 0.5 * (E->H[(size_t)i * K + j] + std::conj(E->H[(size_t)j * K + i]));
+            m[(size_t)i * n2 + j] = m[(size_t)(i + K) * n2 + (j + K)] = h.real();
+            m[(size_t)(i + K) * n2 + j] = h.imag();
+            m[(size_t)i * n2 + (j + K)] = -h.imag();
+        }
+    sym_eig(n2, m, w, v);
+    for (int k = 0; k < K; ++k) vals[k] = 0.5 * (w[2 * k] + w[2 * k + 1]);
+    return WL_OK;
+}
+
 namespace {
 // FP64 single-rhs field helpers of an EigCG context (all synchronous where they return a number)
 struct EigOps {
@@ -2143,15 +2164,6 @@ struct EigOps {
         HIP_TRY(blas_twist(WL_F64, v, E->nh, s));
         return WL_OK;
     }
-    wl_status caxpy(cd a, const void *x, void *y) {
-        VecArgs v = vec_args(E->c, WL_F64, 1);
-        set_vec(v, 0, x, hb);
-        set_vec(v, 1, y, hb);
-        v.a = a.real();
-        v.b = a.imag();
-        HIP_TRY(blas_caxpy(WL_F64, v, E->nh, s));
-        return WL_OK;
-    }
     // out[o] (+)= sum_j coef[j][o] in[j] for nin <= 64, nout <= 32 (coef row-major nin x nout)
     wl_status lincomb(const std::vector<const void *> &in, const std::vector<void *> &out, const std::vector<cd> &coef,
                       bool accumulate) {
@@ -2171,6 +2183,53 @@ struct EigOps {
         HIP_TRY(hipStreamSynchronize(s));  // the coefficient buffer is reused by the next call
         return WL_OK;
     }
+    // out[j * w.size() + o] = <in[j], w[o]> for any number of inputs (64 per launch), w.size() <= 16
+    wl_status blockdot(const std::vector<const void *> &in, const std::vector<const void *> &w,
+                       std::vector<cd> &out) {
+        const int nw = (int)w.size();
+        out.assign(in.size() * nw, cd(0.0, 0.0));
+        if (in.empty() || nw == 0) return WL_OK;
+        if (nw > BD_MAX_W) return fail(WL_ERR_ARG, "more than %d fields in a block inner product", BD_MAX_W);
+        const long nb = blockdot_blocks(E->nelem);
+        std::vector<double> d(2 * BD_MAX_IN * nw);
+        double *dev = (double *)E->c->buf[S_SCAL];
+        for (size_t j0 = 0; j0 < in.size(); j0 += BD_MAX_IN) {
+            const int nj = (int)std::min<size_t>(BD_MAX_IN, in.size() - j0);
+            BlockDotArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.nin = nj;
+            a.nw = nw;
+            for (int k = 0; k < nj; ++k) a.in[k] = (const double2 *)in[j0 + k];
+            for (int o = 0; o < nw; ++o) a.w[o] = (const double2 *)w[o];
+            a.n = E->nelem;
+            a.partials = (double *)E->c->buf[S_PARTIALS];
+            a.stride = nb;
+            HIP_TRY(blas_blockdot(a, s));
+            HIP_TRY(reduce_rows(a.partials, nb, nb, 2 * nj * nw, dev, s));
+            HIP_TRY(hipMemcpyAsync(d.data(), dev, sizeof(double) * 2 * nj * nw, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            for (int k = 0; k < nj * nw; ++k) out[j0 * nw + k] = cd(d[2 * k], d[2 * k + 1]);
+        }
+        return WL_OK;
+    }
+    // outs[o] += sum_j c[j * outs.size() + o] in[j] for any number of inputs
+    wl_status combine_into(const std::vector<const void *> &in, const std::vector<void *> &outs,
+                           const std::vector<cd> &c) {
+        const size_t no = outs.size();
+        for (size_t j0 = 0; j0 < in.size(); j0 += LC_MAX_IN) {
+            const size_t nj = std::min<size_t>(LC_MAX_IN, in.size() - j0);
+            std::vector<const void *> part(in.begin() + j0, in.begin() + j0 + nj);
+            std::vector<cd> cf(c.begin() + j0 * no, c.begin() + (j0 + nj) * no);
+            wl_status st = lincomb(part, outs, cf, true);
+            if (st) return st;
+        }
+        return WL_OK;
+    }
+    std::vector<const void *> space(int k) const {
+        std::vector<const void *> u(k);
+        for (int i = 0; i < k; ++i) u[i] = E->U(i);
+        return u;
+    }
 };
 }  // namespace
 
@@ -2187,8 +2246,9 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
     if (!(tol > 0.0) || maxiter < 1) return fail(WL_ERR_ARG, "bad tolerance or iteration limit");
     if (overlap(x, E->fbytes, b, E->fbytes)) return fail(WL_ERR_ARG, "x and b overlap");
     EigOps O{E, (hipStream_t)stream, part_stride_for(c, 1), half_bytes(c, WL_F64, 1)};
-    if ((st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * O.stride)) ||
-        (st = ensure_buf(c, S_SCAL, 64 * sizeof(double) * 2)))
+    if ((st = ensure_buf(c, S_PARTIALS, sizeof(double) * std::max<long>(2 * O.stride, 2 * BD_MAX_IN * BD_MAX_W *
+                                                                                          blockdot_blocks(E->nelem)))) ||
+        (st = ensure_buf(c, S_SCAL, sizeof(double) * 2 * BD_MAX_IN * BD_MAX_W)))
         return st;
     void *r = E->W(0), *p = E->W(1), *q = E->W(2);
     double b2 = 0.0;
@@ -2206,20 +2266,11 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
     }
     if (E->nvec > 0 && b2 > 0.0) {
         const int K = E->nvec;
-        std::vector<cd> y(K);
-        for (int k = 0; k < K; ++k)
-            if ((st = O.dot(E->U(k), b, &y[k]))) return st;
+        const std::vector<const void *> us = O.space(K);
+        std::vector<cd> y;
+        if ((st = O.blockdot(us, {b}, y))) return st;
         if (!hpd_solve(K, E->H, y)) return fail(WL_BREAKDOWN, "deflation matrix not positive definite");
-        for (int k0 = 0; k0 < K; k0 += LC_MAX_IN) {
-            const int kn = std::min(LC_MAX_IN, K - k0);
-            std::vector<const void *> in(kn);
-            std::vector<cd> cf(kn);
-            for (int k = 0; k < kn; ++k) {
-                in[k] = E->U(k0 + k);
-                cf[k] = y[k0 + k];
-            }
-            if ((st = O.lincomb(in, {x}, cf, true))) return st;
-        }
+        if ((st = O.combine_into(us, {x}, y))) return st;
     }
     if (!(b2 > 0.0)) {
         HIP_TRY(hipStreamSynchronize(O.s));
@@ -2230,6 +2281,21 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
     // search space (slots of vbuf), tridiagonal / projected matrix T, pending coupling after a restart
     const int m = E->m, nev = E->nev, nslot = m + 2 * nev;
     bool track = collect && E->nvec + nev <= E->max_vec;
+    if (!track) {
+        // nothing to collect: the library's CG from the init-CG guess
+        wl_solver_params P;
+        wl_solver_params_default(&P);
+        P.tol = tol;
+        P.maxiter = maxiter;
+        P.mu = E->mu;
+        wl_solver_info ci{};
+        st = wl_cg_solve(c, x, b, (wl_op)E->op, E->kappa, 1, &P, &ci, stream);
+        if (st < 0) return st;
+        HIP_TRY(hipStreamSynchronize(O.s));
+        ci.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) *info = ci;
+        return st;
+    }
     std::vector<int> cols;  // physical slot of each column
     std::vector<char> used(nslot, 0);
     std::vector<double> T((size_t)m * m, 0.0), pending;
@@ -2364,33 +2430,57 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
         for (int i = 0; i < k; ++i)
             for (int j = 0; j < nr; ++j) cf[(size_t)i * nr + j] = Y[(size_t)i * k + j];
         if ((st = O.lincomb(in, outs, cf, false))) return st;
+        // classical Gram-Schmidt of the block against U, twice (one pass over U per step)
+        const int K0 = E->nvec;
+        const std::vector<const void *> us = O.space(K0), wc(outs.begin(), outs.end());
+        for (int pass = 0; pass < 2 && K0 > 0; ++pass) {
+            std::vector<cd> C;
+            if ((st = O.blockdot(us, wc, C))) return st;
+            for (auto &z : C) z = -z;
+            if ((st = O.combine_into(us, outs, C))) return st;
+        }
+        // then each vector against those already kept from this block, normalised, A applied
+        std::vector<double> rqs;
         for (int j = 0; j < nr && E->nvec < E->max_vec; ++j) {
             void *wv = outs[j];
-            for (int pass = 0; pass < 2; ++pass)
-                for (int u = 0; u < E->nvec; ++u) {
-                    cd d;
-                    if ((st = O.dot(E->U(u), wv, &d)) || (st = O.caxpy(-d, E->U(u), wv))) return st;
-                }
+            const int K = E->nvec;
+            std::vector<const void *> kept;
+            for (int i = K0; i < K; ++i) kept.push_back(E->U(i));
+            for (int pass = 0; pass < 2 && !kept.empty(); ++pass) {
+                std::vector<cd> d;
+                if ((st = O.blockdot(kept, {wv}, d))) return st;
+                for (auto &z : d) z = -z;
+                if ((st = O.combine_into(kept, {wv}, d))) return st;
+            }
             cd n2;
             if ((st = O.dot(wv, wv, &n2))) return st;
             if (!(n2.real() > 1e-20)) continue;
-            const int K = E->nvec;
             if ((st = O.scale(1.0 / std::sqrt(n2.real()), wv, E->U(K)))) return st;
             double rq = 0.0;
             if ((st = O.apply_a(E->AU(K), E->U(K), &rq))) return st;
-            std::vector<cd> Hn((size_t)(K + 1) * (K + 1));
-            for (int i = 0; i < K; ++i)
-                for (int jj = 0; jj < K; ++jj) Hn[(size_t)i * (K + 1) + jj] = E->H[(size_t)i * K + jj];
-            for (int i = 0; i < K; ++i) {
-                cd h;
-                if ((st = O.dot(E->U(i), E->AU(K), &h))) return st;
-                Hn[(size_t)i * (K + 1) + K] = h;
-                Hn[(size_t)K * (K + 1) + i] = std::conj(h);
-            }
-            Hn[(size_t)K * (K + 1) + K] = cd(rq, 0.0);
-            E->H.swap(Hn);
-            E->ritz.push_back(rq);
+            rqs.push_back(rq);
             E->nvec = K + 1;
+        }
+        // the new columns of H = U^+ A U in one pass over U
+        const int K1 = E->nvec, nn = K1 - K0;
+        if (nn > 0) {
+            std::vector<const void *> anew;
+            for (int i = K0; i < K1; ++i) anew.push_back(E->AU(i));
+            std::vector<cd> C;
+            if ((st = O.blockdot(O.space(K1), anew, C))) return st;
+            std::vector<cd> Hn((size_t)K1 * K1);
+            for (int i = 0; i < K0; ++i)
+                for (int jj = 0; jj < K0; ++jj) Hn[(size_t)i * K1 + jj] = E->H[(size_t)i * K0 + jj];
+            for (int jn = 0; jn < nn; ++jn) {
+                const int jj = K0 + jn;
+                for (int i = 0; i < jj; ++i) {
+                    Hn[(size_t)i * K1 + jj] = C[(size_t)i * nn + jn];
+                    Hn[(size_t)jj * K1 + i] = std::conj(C[(size_t)i * nn + jn]);
+                }
+                Hn[(size_t)jj * K1 + jj] = cd(rqs[jn], 0.0);
+                E->ritz.push_back(rqs[jn]);
+            }
+            E->H.swap(Hn);
         }
     }
     HIP_TRY(hipStreamSynchronize(O.s));

@@ -61,6 +61,25 @@ struct LinCombArgs {
     long n;
 };
 hipError_t blas_lincomb(const LinCombArgs &a, hipStream_t s);
+// Block of inner products C[j][o] = <in[j], w[o]> (j < nin <= 64, o < nw <= 16) of FP64
+// fields of n complex numbers, as a tall-skinny product In^+ W on the FP64 matrix
+// cores: each wave forms the 64 x 16 product of 16-element slices (four 16 x 16 x 4
+// MFMAs per slice and input tile for the complex product), the four waves of a block
+// are summed in LDS, and block b leaves re/im of (j, o) at
+// partials[(2 (j nw + o) + {0,1}) stride + b] for b < blockdot_blocks(n) <= stride.
+constexpr int BD_MAX_IN = 64, BD_MAX_W = 16;
+struct BlockDotArgs {
+    const double2 *in[BD_MAX_IN];
+    const double2 *w[BD_MAX_W];
+    int nin, nw;
+    long n;
+    double *partials;
+    long stride;
+};
+long blockdot_blocks(long n);
+hipError_t blas_blockdot(const BlockDotArgs &a, hipStream_t s);
+// out[v] = sum_b partials[v * stride + b] (b < nblk) for v < nvals, one block per value
+hipError_t reduce_rows(const double *partials, long stride, long nblk, int nvals, double *out, hipStream_t s);
 // r = b - v  (v2 = r output, v0 = b, v1 = v), ||r||^2 partials: used for true residuals
 hipError_t blas_residual(int prec, VecArgs &a, int nhalves, hipStream_t s);
 

@@ -234,6 +234,64 @@ __global__ void __launch_bounds__(256) k_lincomb(const LinCombArgs a) {
         if (o < a.nout) a.out[o][e] = acc[o];
 }
 
+typedef double wl_d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 operands: lane l gives A[l % 16][l / 16] and B[l / 16][l % 16];
+// it holds D[l / 16 + 4 i][l % 16] in component i.  The k index of a slice maps to
+// element 4 (l / 16) + t of the 16-element slice in MFMA t (the same map for A and B).
+__global__ void __launch_bounds__(256) k_blockdot(const BlockDotArgs a) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int q = lane >> 4, r = lane & 15;
+    const double2 *wp = r < a.nw ? a.w[r] : nullptr;
+    const double2 *up[4];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) up[jt] = 16 * jt + r < a.nin ? a.in[16 * jt + r] : nullptr;
+    const int ntile = (a.nin + 15) >> 4;
+    wl_d4 are[4], aim[4];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) are[jt] = aim[jt] = wl_d4{0.0, 0.0, 0.0, 0.0};
+    const long nchunk = (a.n + 15) >> 4;
+    const long nwaves = (long)gridDim.x * 4;
+    for (long c = (long)blockIdx.x * 4 + wid; c < nchunk; c += nwaves) {
+        const long e0 = c * 16 + 4 * q;
+        double2 wv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) wv[t] = (wp && e0 + t < a.n) ? wp[e0 + t] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt) {
+            if (jt >= ntile) break;
+            double2 uv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) uv[t] = (up[jt] && e0 + t < a.n) ? up[jt][e0 + t] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                are[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(uv[t].x, wv[t].x, are[jt], 0, 0, 0);
+                are[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(uv[t].y, wv[t].y, are[jt], 0, 0, 0);
+                aim[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(uv[t].x, wv[t].y, aim[jt], 0, 0, 0);
+                aim[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-uv[t].y, wv[t].x, aim[jt], 0, 0, 0);
+            }
+        }
+    }
+    // sum the four waves: red[wave][j][o][re/im]
+    __shared__ double red[4 * BD_MAX_IN * BD_MAX_W * 2];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = 16 * jt + q + 4 * i;
+            double *dst = red + (((size_t)wid * BD_MAX_IN + j) * BD_MAX_W + r) * 2;
+            dst[0] = are[jt][i];
+            dst[1] = aim[jt][i];
+        }
+    __syncthreads();
+    const int nval = 2 * a.nin * a.nw;
+    for (int v = threadIdx.x; v < nval; v += blockDim.x) {
+        const int c = v & 1, jo = v >> 1, j = jo / a.nw, o = jo % a.nw;
+        const size_t base = ((size_t)j * BD_MAX_W + o) * 2 + c, ws = (size_t)BD_MAX_IN * BD_MAX_W * 2;
+        a.partials[(long)v * a.stride + blockIdx.x] = ((red[base] + red[base + ws]) + red[base + 2 * ws]) + red[base + 3 * ws];
+    }
+}
+
 // r = b - v, partial ||r||^2
 template <int SP>
 __global__ void __launch_bounds__(256) k_residual(const VecArgs a) {
@@ -272,6 +330,12 @@ __global__ void __launch_bounds__(256) k_reduce(const double *partials, long str
         const double s = sum_partials(partials + (long)r * stride, nblk, lds);
         if (threadIdx.x == 0) out[r] = s;
     }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_rows(const double *partials, long stride, long nblk, double *out) {
+    __shared__ double lds[16];
+    const double s = sum_partials(partials + (long)blockIdx.x * stride, nblk, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // One block per right-hand side.  `count` holds the number of right-hand
@@ -422,6 +486,19 @@ hipError_t blas_lincomb(const LinCombArgs &a, hipStream_t s) {
     if (a.nin < 1 || a.nin > LC_MAX_IN || a.nout < 1 || a.nout > LC_MAX_OUT || a.n < 0) return hipErrorInvalidValue;
     if (a.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+long blockdot_blocks(long n) { return std::max(1L, std::min(512L, ((n + 15) / 16 + 3) / 4)); }
+hipError_t blas_blockdot(const BlockDotArgs &a, hipStream_t s) {
+    if (a.nin < 1 || a.nin > BD_MAX_IN || a.nw < 1 || a.nw > BD_MAX_W || a.n < 0 || !a.partials ||
+        a.stride < blockdot_blocks(a.n))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_blockdot, dim3((unsigned)blockdot_blocks(a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t reduce_rows(const double *partials, long stride, long nblk, int nvals, double *out, hipStream_t s) {
+    if (nvals < 1 || nblk < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)nvals), dim3(256), 0, s, partials, stride, nblk, out);
     return hipGetLastError();
 }
 hipError_t blas_twist(int prec, VecArgs &a, int nh, hipStream_t s) {

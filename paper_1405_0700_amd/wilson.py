@@ -126,6 +126,7 @@ _SIGS = {
     "wl_eigcg_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(SolverInfo), _vp]),
     "wl_eigcg_vectors": (ctypes.c_int, [_vp, _ip, _dp]),
+    "wl_eigcg_eigenvalues": (ctypes.c_int, [_vp, _ip, _dp]),
     "wl_dirac_tm_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_eo_prepare_tm": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -381,6 +382,14 @@ def wl_eigcg_vectors(e, max_vectors=300):
     n = ctypes.c_int()
     buf = (ctypes.c_double * max(1, max_vectors))()
     _check(lib().wl_eigcg_vectors(e, ctypes.byref(n), buf))
+    return list(buf[: n.value])
+
+
+def wl_eigcg_eigenvalues(e, max_vectors=300):
+    """Eigenvalues of H = U^+ A U (the Ritz values on the whole deflation space), ascending."""
+    n = ctypes.c_int()
+    buf = (ctypes.c_double * max(1, max_vectors))()
+    _check(lib().wl_eigcg_eigenvalues(e, ctypes.byref(n), buf))
     return list(buf[: n.value])
 
 

@@ -147,7 +147,8 @@ def main():
                          "propagator: 12 point sources, multi-RHS vs sequential; learned: train the PTC "
                          "preconditioner on 16^3x32 fields and compare FGCR with plain FP64 CG on 32^3x64; "
                          "eigcg: a sequence of right-hand sides, incremental EigCG vs plain FP64 CG")
-    ap.add_argument("--eig-kappa", type=float, default=0.135, help="eigcg: hopping parameter")
+    ap.add_argument("--eig-eps", type=float, default=0.8, help="eigcg: link roughness, U = exp(i eps H)")
+    ap.add_argument("--eig-kappa", type=float, default=0.196, help="eigcg: hopping parameter")
     ap.add_argument("--eig-mu", type=float, default=0.0, help="eigcg: twisted mass")
     ap.add_argument("--eig-rhs", type=int, default=35, help="eigcg: right-hand sides in the sequence")
     ap.add_argument("--eig-collect", type=int, default=30, help="eigcg: right-hand sides that add vectors")
@@ -605,7 +606,9 @@ def run_learned(args):
 
 def run_eigcg(args):
     """A sequence of right-hand sides of A = D_hat^+ D_hat (optionally twisted) on 24^3x48,
-    links exp(0.2iH) seed 401, Gaussian sources on the even sites (seeds 440...), all to
+    links exp(i eps H) seed 402 (default eps 0.8 with kappa 0.196, near this field's
+    critical kappa, where D_hat has small singular values and plain CG needs several
+    hundred iterations), Gaussian sources on the even sites (seeds 440...), all to
     ||b - A x|| <= 1e-8 ||b|| in FP64: plain CG (the library's captured FP64 CG) per
     right-hand side against incremental EigCG with nev = 10, m = 60, up to 300 vectors,
     collecting on the first `eig_collect` right-hand sides (the paper's protocol for its
@@ -616,7 +619,7 @@ def run_eigcg(args):
     dims, tol = (24, 24, 24, 48), 1e-8
     kappa, mu, nrhs, ncol = args.eig_kappa, args.eig_mu, args.eig_rhs, args.eig_collect
     log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
-    lat = W.Lattice.create(synth.su3_links(dims, 0.2, 401), (1, 1, 1, -1))
+    lat = W.Lattice.create(synth.su3_links(dims, args.eig_eps, 402), (1, 1, 1, -1))
     bs = [lat.pack(synth.gaussian_spinor(dims, seed=440 + k, nsites=lat.volume // 2), W.WL_EVEN)
           for k in range(nrhs)]
     x = lat.new(W.WL_EVEN)
@@ -663,9 +666,9 @@ def run_eigcg(args):
     print(json.dumps({
         "metric": "time for a sequence of right-hand sides: incremental EigCG vs plain FP64 CG", "unit": "ms",
         "higher_is_better": False,
-        "workload": "24^3x48, links exp(0.2iH) seed 401, kappa %g, mu %g, %d Gaussian even-site sources "
+        "workload": "24^3x48, links exp(%g iH) seed 402, kappa %g, mu %g, %d Gaussian even-site sources "
                     "(seeds 440-%d), tol 1e-8, A = D_hat^+ D_hat; EigCG nev 10, m 60, max 300 vectors, "
-                    "collecting on the first %d" % (kappa, mu, nrhs, 439 + nrhs, ncol),
+                    "collecting on the first %d" % (args.eig_eps, kappa, mu, nrhs, 439 + nrhs, ncol),
         "cg": {"total_ms": round(sum(cg_ms), 1), "iters": cg_it, "ms": [round(v, 1) for v in cg_ms]},
         "eigcg": {"total_ms": round(sum(eig_ms), 1), "iters": eig_it, "ms": [round(v, 1) for v in eig_ms],
                   "max_true_rel_resid": max(eig_res), "lowest_ritz": [round(r, 8) for r in sorted(ritz)[:5]]},

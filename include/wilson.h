@@ -476,7 +476,7 @@ wl_status wl_batch_autotune(wl_batch *batch, wl_prec prec, int recon, int nrhs, 
  * passes) of the new vectors against U, and the new columns of H.
  *
  * wl_eigcg_create: op, kappa and mu fix A; 1 <= nev <= 16, 2 nev + 2 <= m <= 64;
- *   allocates (m + 2 nev + 5 + 2 max_vectors) FP64 fields of op's subset.
+ *   allocates (2 m + 5 + 2 max_vectors) FP64 fields of op's subset.
  * wl_eigcg_solve: solves A x = b (x: output, the input value is ignored)
  *   to ||b - A x|| <= tol ||b|| (FP64 true residual; up to 4 restarts from it),
  *   adding nev vectors to U if collect != 0 and there is room; otherwise (no

@@ -2011,6 +2011,8 @@ bool hpd_solve(int n, const std::vector<cd> &h, std::vector<cd> &b) {
 }
 }  // namespace
 
+constexpr int EIG_RING = 128;  // >= the longest block of iterations between host reads
+
 struct wl_eigcg {
     wl_ctx *c = nullptr;
     int op = WL_OP_DHAT, nev = 10, m = 60, max_vec = 0;
@@ -2020,6 +2022,8 @@ struct wl_eigcg {
     long nelem = 0;      // complex doubles per field
     char *ubuf = nullptr, *aubuf = nullptr, *vbuf = nullptr, *wbuf = nullptr;
     double2 *coef = nullptr;
+    double *hist = nullptr;  // ring of (alpha, beta) of the tracked CG run
+    int *rec = nullptr;      // iterations recorded in the ring
     int nvec = 0;
     std::vector<cd> H;   // U^+ A U, row-major nvec x nvec
     std::vector<double> ritz;
@@ -2054,9 +2058,11 @@ extern "C" wl_status wl_eigcg_create(wl_ctx *c, wl_op op, double kappa, double m
         e = hipMalloc(&E->ubuf, E->fbytes * max_vectors);
         if (e == hipSuccess) e = hipMalloc(&E->aubuf, E->fbytes * max_vectors);
     }
-    if (e == hipSuccess) e = hipMalloc(&E->vbuf, E->fbytes * (m + 2 * nev));
+    if (e == hipSuccess) e = hipMalloc(&E->vbuf, E->fbytes * 2 * m);
     if (e == hipSuccess) e = hipMalloc(&E->wbuf, E->fbytes * 5);
     if (e == hipSuccess) e = hipMalloc(&E->coef, sizeof(double2) * LC_MAX_IN * LC_MAX_OUT);
+    if (e == hipSuccess) e = hipMalloc(&E->hist, sizeof(double) * 2 * EIG_RING);
+    if (e == hipSuccess) e = hipMalloc(&E->rec, 64);
     if (e != hipSuccess) {
         wl_eigcg_destroy(E);
         return fail(WL_ERR_NOMEM, "EigCG workspace: %s", hipGetErrorString(e));
@@ -2075,7 +2081,8 @@ extern "C" wl_status wl_eigcg_create(wl_ctx *c, wl_op op, double kappa, double m
 extern "C" wl_status wl_eigcg_destroy(wl_eigcg *E) {
     if (!E) return WL_OK;
     (void)hipDeviceSynchronize();
-    for (void *p : {(void *)E->ubuf, (void *)E->aubuf, (void *)E->vbuf, (void *)E->wbuf, (void *)E->coef})
+    for (void *p : {(void *)E->ubuf, (void *)E->aubuf, (void *)E->vbuf, (void *)E->wbuf, (void *)E->coef,
+                    (void *)E->hist, (void *)E->rec})
         if (p) (void)hipFree(p);
     delete E;
     return WL_OK;
@@ -2250,7 +2257,7 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
                                                                                           blockdot_blocks(E->nelem)))) ||
         (st = ensure_buf(c, S_SCAL, sizeof(double) * 2 * BD_MAX_IN * BD_MAX_W)))
         return st;
-    void *r = E->W(0), *p = E->W(1), *q = E->W(2);
+    void *r = E->W(0), *q = E->W(2);
     double b2 = 0.0;
     {
         cd d;
@@ -2279,7 +2286,8 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
     }
     const double target2 = tol * tol * b2;
     // search space (slots of vbuf), tridiagonal / projected matrix T, pending coupling after a restart
-    const int m = E->m, nev = E->nev, nslot = m + 2 * nev;
+    // 2 m slots: the old basis, the restarted one and the next block of new vectors
+    const int m = E->m, nev = E->nev, nslot = 2 * m;
     bool track = collect && E->nvec + nev <= E->max_vec;
     if (!track) {
         // nothing to collect: the library's CG from the init-CG guess
@@ -2296,120 +2304,197 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
         if (info) *info = ci;
         return st;
     }
+    // One tracked CG run on device scalars (the Lanczos relation holds within one
+    // uninterrupted run).  Before each iteration a kernel stores r / ||r|| in the next
+    // free slot of the search space; after it another appends the iteration's alpha
+    // and beta to a ring.  The host reads both only when the space is full (restart)
+    // or every check_every iterations, and builds T from them.
+    wl_solver_params P;
+    wl_solver_params_default(&P);
+    P.tol = tol;
+    P.maxiter = maxiter;
+    P.mu = E->mu;
+    CGRun R;
+    if ((st = cg_setup(c, x, b, E->op, E->kappa, 1, P, O.s, R))) return st;
+    // pinned host copies: the scalars at offset 0, the (alpha, beta) ring at 256 (so the
+    // reads are truly asynchronous and the host work of a restart overlaps the device)
+    static_assert(sizeof(CGScalars) <= 256, "CGScalars larger than its pinned slot");
+    if ((st = ensure_pinned(c, 256 + sizeof(double) * 2 * EIG_RING))) return st;
+    const double *hh = (const double *)((const char *)c->host_pinned + 256);
+    {
+        VecArgs v = vec_args(c, WL_F64, 1);
+        set_vec(v, 0, b, R.hb_hi);
+        v.partials = R.partials;
+        v.part_stride = R.stride;
+        HIP_TRY(blas_norm2(WL_F64, v, R.nh, R.s));
+        HIP_TRY(reduce_partials(R.partials, R.stride, R.nblk_blas, 1, R.bnorm2, R.s));
+    }
+    if ((st = true_residual(R))) return st;
+    HIP_TRY(cg_init(R.sc, 1, R.partials, R.stride, R.nblk_blas, R.bnorm2, tol, maxiter, R.done, R.s));
+    if ((st = load_residual(R))) return st;
+    HIP_TRY(hipMemsetAsync(E->rec, 0, sizeof(int), R.s));
     std::vector<int> cols;  // physical slot of each column
     std::vector<char> used(nslot, 0);
     std::vector<double> T((size_t)m * m, 0.0), pending;
-    int total = 0, restarts = 0;
-    double rho = 0.0, true2 = 0.0;
-    for (int cycle = 0;; ++cycle) {
-        // r = b - A x (FP64 true residual), p = r
-        if ((st = O.apply_a(q, x, nullptr)) || (st = O.scale(1.0, b, r)) || (st = O.axpby(-1.0, q, 1.0, r, &rho)))
-            return st;
-        true2 = rho;
-        if (rho <= target2 || total >= maxiter || cycle >= 4) break;
-        if (cycle > 0) {
-            ++restarts;
-            track = false;  // the Lanczos relation holds within one uninterrupted CG run only
+    auto take_slot = [&](int *slot) -> bool {
+        int sl = 0;
+        while (sl < nslot && used[sl]) ++sl;
+        if (sl == nslot) return false;
+        used[sl] = 1;
+        *slot = sl;
+        return true;
+    };
+    // A restart (the space is full) is scheduled at a host read and carried out after
+    // the next block of iterations has been enqueued, so that its host part (two small
+    // eigenproblems) overlaps the device work; the recombination of the old basis is
+    // enqueued behind that block, into slots reserved for it.
+    struct Restart {
+        bool due = false;
+        std::vector<double> T;      // T_m of the full space
+        std::vector<int> old_cols;  // its basis
+        std::vector<int> reserved;  // slots of the restarted basis (the first columns now)
+        double off = 0.0;           // coupling of the m-th column to the next vector
+    } rs;
+    auto do_restart = [&]() -> wl_status {
+        // the nev lowest Ritz vectors of T_m and of T_{m-1}
+        const std::vector<double> &To = rs.T;
+        std::vector<double> tm((size_t)m * m), tm1((size_t)(m - 1) * (m - 1)), w, Y, w1, Y1;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) tm[(size_t)i * m + j] = To[(size_t)i * m + j];
+        for (int i = 0; i < m - 1; ++i)
+            for (int j = 0; j < m - 1; ++j) tm1[(size_t)i * (m - 1) + j] = To[(size_t)i * m + j];
+        sym_eig(m, tm, w, Y);
+        sym_eig(m - 1, tm1, w1, Y1);
+        // Z = [Y(:, :nev), [Y1(:, :nev); 0]], orthonormalised (two Gram-Schmidt passes)
+        std::vector<std::vector<double>> Z;
+        for (int j = 0; j < 2 * nev; ++j) {
+            std::vector<double> z(m, 0.0);
+            for (int i = 0; i < m; ++i)
+                z[i] = j < nev ? Y[(size_t)i * m + j] : (i < m - 1 ? Y1[(size_t)i * (m - 1) + (j - nev)] : 0.0);
+            for (int pass = 0; pass < 2; ++pass)
+                for (auto &zz : Z) {
+                    double d = 0.0;
+                    for (int i = 0; i < m; ++i) d += zz[i] * z[i];
+                    for (int i = 0; i < m; ++i) z[i] -= d * zz[i];
+                }
+            double nz = 0.0;
+            for (int i = 0; i < m; ++i) nz += z[i] * z[i];
+            nz = std::sqrt(nz);
+            if (nz < 1e-10) continue;
+            for (int i = 0; i < m; ++i) z[i] /= nz;
+            Z.push_back(z);
         }
-        if ((st = O.scale(1.0, r, p))) return st;
-        double alpha_old = 0.0, beta_old = 0.0;
-        bool have_old = false;
-        while (rho > target2 && total < maxiter) {
-            int k = (int)cols.size();
-            if (track) {
-                int slot = 0;
-                while (used[slot]) ++slot;
-                used[slot] = 1;
-                cols.push_back(slot);
-                k = (int)cols.size();
-                if ((st = O.scale(1.0 / std::sqrt(rho), r, E->V(slot)))) return st;
+        const int kq = (int)Z.size(), nres = (int)rs.reserved.size();
+        std::vector<const void *> in(m);
+        for (int i = 0; i < m; ++i) in[i] = E->V(rs.old_cols[i]);
+        std::vector<void *> outs(kq);
+        for (int j = 0; j < kq; ++j) outs[j] = E->V(rs.reserved[j]);
+        std::vector<cd> cf((size_t)m * kq);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < kq; ++j) cf[(size_t)i * kq + j] = Z[j][i];
+        wl_status e2 = O.lincomb(in, outs, cf, false);
+        if (e2) return e2;
+        for (int sl : rs.old_cols) used[sl] = 0;
+        // reserved slots the restarted basis does not need
+        for (int j = kq; j < nres; ++j) used[rs.reserved[j]] = 0;
+        cols.erase(cols.begin() + kq, cols.begin() + nres);
+        // T <- Z^T T_m Z, and the next vector couples through the last row of Z
+        std::fill(T.begin(), T.end(), 0.0);
+        for (int a = 0; a < kq; ++a)
+            for (int bb = 0; bb < kq; ++bb) {
+                double sum = 0.0;
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < m; ++j) sum += Z[a][i] * To[(size_t)i * m + j] * Z[bb][j];
+                T[(size_t)a * m + bb] = sum;
             }
-            double pap = 0.0;
-            if ((st = O.apply_a(q, p, &pap))) return st;
-            if (!(pap > 0.0) || !std::isfinite(pap)) return fail(WL_BREAKDOWN, "EigCG breakdown: <p, A p> = %g", pap);
-            const double alpha = rho / pap;
-            double rho_new = 0.0;
-            if ((st = O.axpby(alpha, p, 1.0, x, nullptr)) || (st = O.axpby(-alpha, q, 1.0, r, &rho_new))) return st;
-            const double beta = rho_new / rho;
-            if (track) {
-                T[(size_t)(k - 1) * m + (k - 1)] = 1.0 / alpha + (have_old ? beta_old / alpha_old : 0.0);
-                if (!pending.empty()) {
-                    for (int i = 0; i < k - 1; ++i)
-                        T[(size_t)i * m + (k - 1)] = T[(size_t)(k - 1) * m + i] = pending[i];
-                    pending.clear();
+        pending.assign(kq, 0.0);
+        for (int a = 0; a < kq; ++a) pending[a] = Z[a][m - 1] * rs.off;
+        rs.due = false;
+        return WL_OK;
+    };
+    CGScalars hs{};
+    int seen = 0;  // iterations whose step lengths are in T
+    double alpha_old = 0.0, beta_old = 0.0;
+    bool have_old = false;
+    for (;;) {
+        const int block = std::max(1, std::min(P.check_every, m - (int)cols.size()));
+        size_t ncols0 = cols.size();
+        for (int j = 0; j < block; ++j) {
+            int slot = 0;
+            if (!take_slot(&slot)) return fail(WL_ERR_ARG, "EigCG search space has no free slot (internal)");
+            cols.push_back(slot);
+            VecArgs v = vec_args(c, WL_F64, 1);
+            set_vec(v, 0, R.r, R.hb_hi);
+            set_vec(v, 1, E->V(slot), R.hb_hi);
+            v.sc = R.sc;
+            v.flag = R.done;
+            HIP_TRY(blas_scale_by_rho(v, R.nh, R.s));
+            if ((st = cg_iteration(R, false))) return st;
+            HIP_TRY(cg_record(R.sc, E->hist, EIG_RING, E->rec, R.s));
+        }
+        HIP_TRY(hipMemcpyAsync(c->host_pinned, R.sc, sizeof(CGScalars), hipMemcpyDeviceToHost, R.s));
+        HIP_TRY(hipMemcpyAsync((char *)c->host_pinned + 256, E->hist, sizeof(double) * 2 * EIG_RING,
+                               hipMemcpyDeviceToHost, R.s));
+        if (rs.due) {
+            const size_t before = cols.size();
+            if ((st = do_restart())) return st;
+            ncols0 -= before - cols.size();
+        }
+        HIP_TRY(hipStreamSynchronize(R.s));
+        std::memcpy(&hs, c->host_pinned, sizeof hs);
+        if (hs.status == WL_BREAKDOWN) return fail(WL_BREAKDOWN, "EigCG breakdown: <p, A p> <= 0 or not finite");
+        // slots issued for iterations that did not run (the run stopped) were never written
+        const int nnew = hs.iter - seen;
+        const size_t keep = ncols0 + (size_t)nnew;
+        for (size_t i = keep; i < cols.size(); ++i) used[cols[i]] = 0;
+        cols.resize(keep);
+        for (int t = 0; t < nnew; ++t) {
+            const int g = seen + t, k = (int)ncols0 + t + 1;
+            const double alpha = hh[2 * (g % EIG_RING)], beta = hh[2 * (g % EIG_RING) + 1];
+            T[(size_t)(k - 1) * m + (k - 1)] = 1.0 / alpha + (have_old ? beta_old / alpha_old : 0.0);
+            if (!pending.empty()) {
+                for (int i2 = 0; i2 < k - 1; ++i2) T[(size_t)i2 * m + (k - 1)] = T[(size_t)(k - 1) * m + i2] = pending[i2];
+                pending.clear();
+            }
+            const double off = -std::sqrt(beta) / alpha;
+            if (k == m) {
+                // full: schedule the restart (only the last new column can fill the space)
+                rs.due = true;
+                rs.T = T;
+                rs.old_cols = cols;
+                rs.off = off;
+                rs.reserved.clear();
+                for (int j = 0; j < 2 * nev; ++j) {
+                    int slot = 0;
+                    if (!take_slot(&slot)) return fail(WL_ERR_ARG, "EigCG search space has no free slot (internal)");
+                    rs.reserved.push_back(slot);
                 }
-                const double off = -std::sqrt(beta) / alpha;
-                if (k == m) {
-                    // restart with the nev lowest Ritz vectors of T_m and of T_{m-1}
-                    std::vector<double> tm((size_t)m * m), tm1((size_t)(m - 1) * (m - 1)), w, Y, w1, Y1;
-                    for (int i = 0; i < m; ++i)
-                        for (int j = 0; j < m; ++j) tm[(size_t)i * m + j] = T[(size_t)i * m + j];
-                    for (int i = 0; i < m - 1; ++i)
-                        for (int j = 0; j < m - 1; ++j) tm1[(size_t)i * (m - 1) + j] = T[(size_t)i * m + j];
-                    sym_eig(m, tm, w, Y);
-                    sym_eig(m - 1, tm1, w1, Y1);
-                    // Z = [Y(:, :nev), [Y1(:, :nev); 0]], orthonormalised (two Gram-Schmidt passes)
-                    std::vector<std::vector<double>> Z;
-                    for (int j = 0; j < 2 * nev; ++j) {
-                        std::vector<double> z(m, 0.0);
-                        for (int i = 0; i < m; ++i)
-                            z[i] = j < nev ? Y[(size_t)i * m + j] : (i < m - 1 ? Y1[(size_t)i * (m - 1) + (j - nev)] : 0.0);
-                        for (int pass = 0; pass < 2; ++pass)
-                            for (auto &zz : Z) {
-                                double d = 0.0;
-                                for (int i = 0; i < m; ++i) d += zz[i] * z[i];
-                                for (int i = 0; i < m; ++i) z[i] -= d * zz[i];
-                            }
-                        double nz = 0.0;
-                        for (int i = 0; i < m; ++i) nz += z[i] * z[i];
-                        nz = std::sqrt(nz);
-                        if (nz < 1e-10) continue;
-                        for (int i = 0; i < m; ++i) z[i] /= nz;
-                        Z.push_back(z);
-                    }
-                    const int kq = (int)Z.size();
-                    std::vector<const void *> in(m);
-                    for (int i = 0; i < m; ++i) in[i] = E->V(cols[i]);
-                    std::vector<int> fresh;
-                    for (int sl = 0; sl < nslot && (int)fresh.size() < kq; ++sl)
-                        if (!used[sl]) fresh.push_back(sl);
-                    std::vector<void *> outs(kq);
-                    for (int j = 0; j < kq; ++j) outs[j] = E->V(fresh[j]);
-                    std::vector<cd> cf((size_t)m * kq);
-                    for (int i = 0; i < m; ++i)
-                        for (int j = 0; j < kq; ++j) cf[(size_t)i * kq + j] = Z[j][i];
-                    if ((st = O.lincomb(in, outs, cf, false))) return st;
-                    for (int sl : cols) used[sl] = 0;
-                    cols.clear();
-                    for (int j = 0; j < kq; ++j) {
-                        used[fresh[j]] = 1;
-                        cols.push_back(fresh[j]);
-                    }
-                    // T <- Z^T T_m Z, and the next vector couples through the last row of Z
-                    std::vector<double> tn((size_t)kq * kq, 0.0);
-                    for (int a = 0; a < kq; ++a)
-                        for (int bb = 0; bb < kq; ++bb) {
-                            double sum = 0.0;
-                            for (int i = 0; i < m; ++i)
-                                for (int j = 0; j < m; ++j) sum += Z[a][i] * T[(size_t)i * m + j] * Z[bb][j];
-                            tn[(size_t)a * kq + bb] = sum;
-                        }
-                    std::fill(T.begin(), T.end(), 0.0);
-                    for (int a = 0; a < kq; ++a)
-                        for (int bb = 0; bb < kq; ++bb) T[(size_t)a * m + bb] = tn[(size_t)a * kq + bb];
-                    pending.assign(kq, 0.0);
-                    for (int a = 0; a < kq; ++a) pending[a] = Z[a][m - 1] * off;
-                } else {
-                    T[(size_t)(k - 1) * m + k] = T[(size_t)k * m + (k - 1)] = off;
-                }
+                cols = rs.reserved;
+            } else {
+                T[(size_t)(k - 1) * m + k] = T[(size_t)k * m + (k - 1)] = off;
             }
             alpha_old = alpha;
             beta_old = beta;
             have_old = true;
-            if ((st = O.axpby(1.0, r, beta, p, nullptr))) return st;
-            rho = rho_new;
-            ++total;
         }
+        seen = hs.iter;
+        if (!hs.active) break;
+    }
+    if (rs.due && (st = do_restart())) return st;
+    int total = hs.iter, restarts = 0;
+    double rho = hs.rho, true2 = 0.0;
+    // FP64 true residual; if it misses the tolerance, finish untracked with the library's CG
+    if ((st = O.apply_a(q, x, nullptr)) || (st = O.scale(1.0, b, r)) || (st = O.axpby(-1.0, q, 1.0, r, &true2)))
+        return st;
+    if (true2 > target2 && total < maxiter) {
+        P.maxiter = maxiter - total;
+        wl_solver_info ci{};
+        st = wl_cg_solve(c, x, b, (wl_op)E->op, E->kappa, 1, &P, &ci, stream);
+        if (st < 0) return st;
+        total += ci.iters;
+        restarts += 1 + ci.restarts;
+        rho = ci.rel_resid * ci.rel_resid * b2;
+        true2 = ci.true_rel_resid * ci.true_rel_resid * b2;
     }
     // keep the nev lowest Ritz vectors of the tracked space
     if (collect && track && !cols.empty()) {

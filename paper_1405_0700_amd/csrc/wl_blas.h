@@ -78,6 +78,13 @@ struct BlockDotArgs {
 };
 long blockdot_blocks(long n);
 hipError_t blas_blockdot(const BlockDotArgs &a, hipStream_t s);
+// v1 = v0 / sqrt(sc[0].rho) for one FP64 right-hand side (the normalised residual of a
+// CG run; does nothing once *flag == 0)
+hipError_t blas_scale_by_rho(VecArgs &a, int nhalves, hipStream_t s);
+// Appends (alpha, beta) of sc[0] to hist (ring of `cap` pairs, slot (iter - 1) % cap)
+// when sc[0].iter has advanced past *recorded: run after every CG iteration, it keeps
+// each iteration's step lengths, the last one's included.
+hipError_t cg_record(const CGScalars *sc, double *hist, int cap, int *recorded, hipStream_t s);
 // out[v] = sum_b partials[v * stride + b] (b < nblk) for v < nvals, one block per value
 hipError_t reduce_rows(const double *partials, long stride, long nblk, int nvals, double *out, hipStream_t s);
 // r = b - v  (v2 = r output, v0 = b, v1 = v), ||r||^2 partials: used for true residuals

@@ -234,6 +234,30 @@ __global__ void __launch_bounds__(256) k_lincomb(const LinCombArgs a) {
         if (o < a.nout) a.out[o][e] = acc[o];
 }
 
+__global__ void __launch_bounds__(256) k_scale_by_rho(const VecArgs a) {
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.n) return;
+    const double f = 1.0 / sqrt(a.sc[0].rho);
+    cpx<double> x[12];
+    SpinorIO<WL_F64>::load(a.v[0][h], gid, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = {f * x[k].re, f * x[k].im};
+    SpinorIO<WL_F64>::store(a.v[1][h], gid, x);
+}
+
+__global__ void k_cg_record(const CGScalars *sc, double *hist, int cap, int *recorded) {
+    if (threadIdx.x != 0) return;
+    const int it = sc[0].iter;
+    if (it > *recorded) {
+        const int slot = (it - 1) % cap;
+        hist[2 * slot] = sc[0].alpha;
+        hist[2 * slot + 1] = sc[0].beta;
+        *recorded = it;
+    }
+}
+
 typedef double wl_d4 __attribute__((ext_vector_type(4)));
 
 // v_mfma_f64_16x16x4f64 operands: lane l gives A[l % 16][l / 16] and B[l / 16][l % 16];
@@ -494,6 +518,16 @@ hipError_t blas_blockdot(const BlockDotArgs &a, hipStream_t s) {
         a.stride < blockdot_blocks(a.n))
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_blockdot, dim3((unsigned)blockdot_blocks(a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t blas_scale_by_rho(VecArgs &a, int nh, hipStream_t s) {
+    if (!a.sc || a.nrhs != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scale_by_rho, vgrid(a, nh), dim3(blas_block()), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t cg_record(const CGScalars *sc, double *hist, int cap, int *recorded, hipStream_t s) {
+    if (cap < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cg_record, dim3(1), dim3(64), 0, s, sc, hist, cap, recorded);
     return hipGetLastError();
 }
 hipError_t reduce_rows(const double *partials, long stride, long nblk, int nvals, double *out, hipStream_t s) {

@@ -141,12 +141,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
-    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch", "eigcg"],
+    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch", "eigcg", "access"],
                     default="eo-cg",
                     help="eo-cg: the headline (24^3x48 FP64 e/o CG); mixed: 32^3x64 FP64 vs mixed-precision CG; "
                          "propagator: 12 point sources, multi-RHS vs sequential; learned: train the PTC "
                          "preconditioner on 16^3x32 fields and compare FGCR with plain FP64 CG on 32^3x64; "
-                         "eigcg: a sequence of right-hand sides, incremental EigCG vs plain FP64 CG")
+                         "eigcg: a sequence of right-hand sides, incremental EigCG vs plain FP64 CG; "
+                         "access: the link-spinor kernel with sequential, index-array and pointer addressing")
     ap.add_argument("--eig-eps", type=float, default=0.8, help="eigcg: link roughness, U = exp(i eps H)")
     ap.add_argument("--eig-kappa", type=float, default=0.196, help="eigcg: hopping parameter")
     ap.add_argument("--eig-mu", type=float, default=0.0, help="eigcg: twisted mass")
@@ -187,6 +188,8 @@ def main():
         return run_batch(args)
     if args.workload == "eigcg":
         return run_eigcg(args)
+    if args.workload == "access":
+        return run_access(args)
     return run_eo_cg(args)
 
 
@@ -677,6 +680,59 @@ def run_eigcg(args):
         "speedup_deflated_rhs": (round(sum(cg_ms[tail]) / sum(eig_ms[tail]), 3) if nrhs > ncol else None),
         "iteration_ratio_last": round(cg_it[-1] / max(1, eig_it[-1]), 3)}))
     lat.close()
+
+
+def run_access(args):
+    """The paper's addressing experiment on the isolated link-spinor kernel
+    psi(x_i) = U(x_i) phi(x_i) (FP64; 144 B of link + 192 B in + 192 B out per site):
+    sequential sites, sites through a random permutation index, and the same random
+    sites through precomputed address arrays, in the site-major layout and in blocks
+    of 64 sites, from 2^12 sites (cache-resident) to 2^24 (9 GB, HBM-bound)."""
+    import torch
+    from paper_1405_0700_amd import wilson as W
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(730)
+    rows = []
+    for lg in (12, 14, 16, 18, 20, 22, 24):
+        n = 1 << lg
+        u = torch.randn(n * 18, dtype=torch.float64, device="cuda", generator=gen)
+        phi = torch.randn(n * 24, dtype=torch.float64, device="cuda", generator=gen)
+        psi = torch.zeros(n * 24, dtype=torch.float64, device="cuda")
+        perm = torch.randperm(n, device="cuda", generator=gen)
+        idx = perm.to(torch.int32)
+        for layout in (0, 1):
+            def off(nc):
+                if layout == 0:
+                    return perm * (nc * 16)
+                return ((perm // 64) * 64 * nc + perm % 64) * 16
+            ptrs = torch.stack([psi.data_ptr() + off(12), u.data_ptr() + off(9), phi.data_ptr() + off(12)], 1)
+            ptrs = ptrs.reshape(-1).contiguous()
+            for mode, name, extra in ((W.WL_ACCESS_SEQ, "sequential", 0), (W.WL_ACCESS_INDEX, "index", 4),
+                                      (W.WL_ACCESS_PTR, "pointers", 24)):
+                call = lambda: W.wl_su3_apply(psi, u, phi, n, mode, layout, idx, ptrs)
+                for _ in range(3):
+                    call()
+                reps = max(5, min(2000, (40 << 20) // n))
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    call()
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) / reps * 1e3
+                rows.append({"sites": n, "layout": "site-major" if layout == 0 else "64-site blocks", "mode": name,
+                             "us": round(us, 2), "GBps": round(528 * n / us / 1e3, 1),
+                             "GBps_with_addressing": round((528 + extra) * n / us / 1e3, 1)})
+                print("[bench] %s" % rows[-1], file=sys.stderr, flush=True)
+            del ptrs
+        del u, phi, psi, perm, idx
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "link-spinor kernel GB/s by addressing scheme and size", "unit": "GB/s",
+                      "higher_is_better": True, "bytes_per_site": 528, "peak_GBps": HBM_PEAK_GBS,
+                      "workload": "psi(x_i) = U(x_i) phi(x_i), FP64, torch.randn fields and permutation "
+                                  "(generator seed 730), 2^12 .. 2^24 sites",
+                      "results": rows}))
 
 
 if __name__ == "__main__":

@@ -496,6 +496,35 @@ wl_status wl_eigcg_solve(wl_eigcg *e, void *x, const void *b, double tol, int ma
 wl_status wl_eigcg_vectors(const wl_eigcg *e, int *nvec, double *ritz);
 wl_status wl_eigcg_eigenvalues(const wl_eigcg *e, int *n, double *vals);
 
+/* ---------------------------------------------------------------- link-spinor access kernel
+ *
+ * The paper's isolated link-spinor multiplication, used there to compare ways
+ * of addressing the sites (section on overlapping communication with
+ * computation: sequential access, access through an index array, and access
+ * through pointer arrays prepared beforehand).  For i < n:
+ *     psi(x_i) = U(x_i) phi(x_i),
+ * U a 3x3 complex matrix applied to each of the four colour vectors of the
+ * spinor phi; FP64 throughout, all arrays in device memory.
+ *   mode WL_ACCESS_SEQ   : x_i = i
+ *   mode WL_ACCESS_INDEX : x_i = index[i] (int32 device array of n site numbers
+ *                          < the arrays' site count; a permutation writes every
+ *                          psi once, a repeated site is written more than once)
+ *   mode WL_ACCESS_PTR   : ptrs[3 i], ptrs[3 i + 1], ptrs[3 i + 2] (uint64 device
+ *                          array) are the device addresses of psi(x_i), U(x_i) and
+ *                          phi(x_i); psi, u, phi are not read (may be NULL)
+ *   layout 0: site x of U at u + 144 x bytes (row-major 3x3, re/im
+ *             interleaved), of phi/psi at + 192 x (spin-major, colour-minor);
+ *   layout 1: blocks of 64 sites, component k of site x at
+ *             base + ((x / 64) * 64 * nc + k * 64 + x % 64) * 16 bytes (nc = 9
+ *             for U, 12 for spinors); the arrays hold whole blocks.  In pointer
+ *             mode the address is that of component 0 (+ k * 1024 for component k).
+ * Errors: WL_ERR_ARG for n < 0 or > 2^31 - 1, a bad mode or layout, a missing
+ * index / address array, null or misaligned field pointers.  Asynchronous on
+ * `stream`. */
+typedef enum { WL_ACCESS_SEQ = 0, WL_ACCESS_INDEX = 1, WL_ACCESS_PTR = 2 } wl_access_mode;
+wl_status wl_su3_apply(void *psi, const void *u, const void *phi, long n, int mode, int layout, const int *index,
+                       const unsigned long long *ptrs, void *stream);
+
 /* ---------------------------------------------------------------- kernel timing */
 
 /* While enabled, every launch of the hopping-term kernel made through this

@@ -375,3 +375,20 @@ class EigCG:
                 self.AU.append(self.a(v))
                 self.ritz.append(float(np.vdot(v, self.AU[-1]).real))
         return x, it
+
+
+# --------------------------------------------------------------------------
+# Link-spinor multiplication over a sequence of sites (the isolated kernel of
+# the paper's addressing experiment, section on overlapping communication with
+# computation): psi(x_i) = U(x_i) phi(x_i), U acting on the colour index of each
+# of the four spin components.
+# --------------------------------------------------------------------------
+def su3_apply(u, phi, psi, sites):
+    """u: (n, 3, 3), phi and psi: (n, 4, 3) complex; sites: site numbers x_i in step order.
+    Returns a copy of psi with psi[x][s] = u[x] @ phi[x][s] for every spin s at each visited x;
+    other sites keep their values."""
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    for x in sites:
+        for s in range(4):
+            out[x, s] = u[x] @ phi[x, s]
+    return out

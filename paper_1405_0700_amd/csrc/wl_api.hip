@@ -20,6 +20,7 @@
 #include "wl_blas.h"
 #include "wl_dslash.h"
 #include "wl_ptc.h"
+#include "wl_access.h"
 
 using namespace wl;
 
@@ -2576,6 +2577,24 @@ extern "C" wl_status wl_eigcg_solve(wl_eigcg *E, void *x, const void *b, double 
     out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = out;
     if (true2 > target2) return fail(WL_NOT_CONVERGED, "EigCG did not reach the tolerance");
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ link-spinor access kernel
+extern "C" wl_status wl_su3_apply(void *psi, const void *u, const void *phi, long n, int mode, int layout,
+                                  const int *index, const unsigned long long *ptrs, void *stream) {
+    g_err.clear();
+    if (n < 0) return fail(WL_ERR_ARG, "n = %ld < 0", n);
+    if (mode < WL_ACCESS_SEQ || mode > WL_ACCESS_PTR) return fail(WL_ERR_ARG, "bad access mode %d", mode);
+    if (layout < 0 || layout > 1) return fail(WL_ERR_ARG, "bad layout %d", layout);
+    if (n == 0) return WL_OK;
+    if (mode != WL_ACCESS_PTR && (!psi || !u || !phi || !aligned16(psi) || !aligned16(u) || !aligned16(phi)))
+        return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    if (mode == WL_ACCESS_INDEX && !index) return fail(WL_ERR_ARG, "index mode without an index array");
+    if (mode == WL_ACCESS_PTR && !ptrs) return fail(WL_ERR_ARG, "pointer mode without an address array");
+    if (n > (long)INT32_MAX) return fail(WL_ERR_ARG, "n = %ld too large", n);
+    AccessArgs a{(double2 *)psi, (const double2 *)u, (const double2 *)phi, n, index, ptrs};
+    HIP_TRY(launch_su3_apply(a, mode, layout, (hipStream_t)stream));
     return WL_OK;
 }
 

@@ -26,6 +26,7 @@ WL_ERR_ARG, WL_ERR_DIMS, WL_ERR_HIP, WL_ERR_NOMEM, WL_ERR_UNSUPPORTED = -1, -2, 
 WL_F64, WL_F32, WL_F16N, WL_BF16N, WL_I16N = 0, 1, 2, 3, 4
 WL_EVEN, WL_ODD, WL_FULL = 0, 1, 2
 WL_OP_D, WL_OP_DHAT = 0, 1
+WL_ACCESS_SEQ, WL_ACCESS_INDEX, WL_ACCESS_PTR = 0, 1, 2
 
 PREC = {"f64": WL_F64, "f32": WL_F32, "f16n": WL_F16N, "bf16n": WL_BF16N, "i16n": WL_I16N}
 SUBSET = {"even": WL_EVEN, "odd": WL_ODD, "full": WL_FULL}
@@ -127,6 +128,7 @@ _SIGS = {
                                       ctypes.POINTER(SolverInfo), _vp]),
     "wl_eigcg_vectors": (ctypes.c_int, [_vp, _ip, _dp]),
     "wl_eigcg_eigenvalues": (ctypes.c_int, [_vp, _ip, _dp]),
+    "wl_su3_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_long, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "wl_dirac_tm_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_eo_prepare_tm": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -391,6 +393,12 @@ def wl_eigcg_eigenvalues(e, max_vectors=300):
     buf = (ctypes.c_double * max(1, max_vectors))()
     _check(lib().wl_eigcg_eigenvalues(e, ctypes.byref(n), buf))
     return list(buf[: n.value])
+
+
+def wl_su3_apply(psi, u, phi, n, mode=WL_ACCESS_SEQ, layout=0, index=None, ptrs=None, stream=None):
+    """psi(x_i) = U(x_i) phi(x_i) for i < n (device tensors; see wilson.h for modes and layouts)."""
+    return _check(lib().wl_su3_apply(_ptr(psi), _ptr(u), _ptr(phi), int(n), int(mode), int(layout), _ptr(index),
+                                     _ptr(ptrs), _stream(stream)))
 
 
 def _ptr_array(items):

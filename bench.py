@@ -141,13 +141,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
-    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch", "eigcg", "access"],
+    ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch", "eigcg", "access",
+                                           "split"],
                     default="eo-cg",
                     help="eo-cg: the headline (24^3x48 FP64 e/o CG); mixed: 32^3x64 FP64 vs mixed-precision CG; "
                          "propagator: 12 point sources, multi-RHS vs sequential; learned: train the PTC "
                          "preconditioner on 16^3x32 fields and compare FGCR with plain FP64 CG on 32^3x64; "
                          "eigcg: a sequence of right-hand sides, incremental EigCG vs plain FP64 CG; "
-                         "access: the link-spinor kernel with sequential, index-array and pointer addressing")
+                         "access: the link-spinor kernel with sequential, index-array and pointer addressing; "
+                         "split: the bulk / boundary split half-dslash against the fused one")
     ap.add_argument("--eig-eps", type=float, default=0.8, help="eigcg: link roughness, U = exp(i eps H)")
     ap.add_argument("--eig-kappa", type=float, default=0.196, help="eigcg: hopping parameter")
     ap.add_argument("--eig-mu", type=float, default=0.0, help="eigcg: twisted mass")
@@ -190,6 +192,8 @@ def main():
         return run_eigcg(args)
     if args.workload == "access":
         return run_access(args)
+    if args.workload == "split":
+        return run_split(args)
     return run_eo_cg(args)
 
 
@@ -733,6 +737,56 @@ def run_access(args):
                       "workload": "psi(x_i) = U(x_i) phi(x_i), FP64, torch.randn fields and permutation "
                                   "(generator seed 730), 2^12 .. 2^24 sites",
                       "results": rows}))
+
+
+def run_split(args):
+    """Half-dslash H_eo in on 24^3x48 and 32^3x64 (links exp(0.2iH) seeds 740/741, Gaussian
+    input): the fused kernel (default launch, and one thread per point), and the bulk /
+    boundary split form (t-face pack, face transfer on a second stream, bulk, boundary)
+    that a rank of a t-decomposed lattice would run.  Algorithmic bytes per output site:
+    8 links + input + output spinor."""
+    import torch
+    from paper_1405_0700_amd import synth
+    from paper_1405_0700_amd import wilson as W
+    rows = []
+    for dims, seed in (((24, 24, 24, 48), 740), ((32, 32, 32, 64), 741)):
+        lat = W.Lattice.create(synth.su3_links(dims, 0.2, seed), (1, 1, 1, -1))
+        vh = lat.volume // 2
+        src = synth.gaussian_spinor(dims, seed=seed + 100, nsites=vh)
+        default = {p: W.wl_ctx_get_launch(lat.ctx, p) for p in (W.WL_F64, W.WL_F32)}
+        for prec, recon, link_b, sp_b in ((W.WL_F64, 18, 144, 192), (W.WL_F32, 18, 72, 96), (W.WL_F32, 12, 48, 96)):
+            inp = lat.pack(src, W.WL_ODD, prec)
+            out = lat.new(W.WL_EVEN, prec)
+            calls = {
+                "fused": lambda: W.wl_dslash_apply(lat.ctx, out, inp, W.WL_EVEN, prec, recon),
+                "split": lambda: W.wl_dslash_apply_split(lat.ctx, out, inp, W.WL_EVEN, prec, recon),
+            }
+            res = {}
+            for name, tps in (("fused", None), ("fused_tps1", 1), ("split", None)):
+                if tps:
+                    W.wl_ctx_set_launch(lat.ctx, prec, 256, 1, tps)
+                else:
+                    W.wl_ctx_set_launch(lat.ctx, prec, *default[prec])
+                fn = calls["split" if name == "split" else "fused"]
+                for _ in range(5):
+                    fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(50):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) / 50 * 1e3
+                res[name] = {"us": round(us, 2), "GBps": round((8 * link_b + 2 * sp_b) * vh / us / 1e3, 1)}
+            W.wl_ctx_set_launch(lat.ctx, prec, *default[prec])
+            rows.append({"dims": list(dims), "prec": {W.WL_F64: "f64", W.WL_F32: "f32"}[prec], "recon": recon,
+                         "boundary_sites_fraction": round(2 / dims[3], 4), **res,
+                         "split_over_fused": round(res["split"]["us"] / res["fused"]["us"], 3)})
+            print("[bench] %s" % rows[-1], file=sys.stderr, flush=True)
+        lat.close()
+    print(json.dumps({"metric": "half-dslash time: bulk / boundary split with t-face transfer vs fused",
+                      "unit": "us", "higher_is_better": False, "results": rows}))
 
 
 if __name__ == "__main__":

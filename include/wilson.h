@@ -173,6 +173,27 @@ wl_status wl_dslash_dagger_apply(const wl_ctx *ctx, void *out, const void *in,
                                  wl_subset out_subset, wl_prec prec, int recon, int nrhs,
                                  void *stream);
 
+/* wl_dslash_apply_split: the same out = H in (H^+ in if dagger != 0) for one
+ * output parity (subset WL_EVEN or WL_ODD; in is the opposite parity), one
+ * right-hand side, FP64 or FP32 storage (recon 18 or 12), computed the way one
+ * rank of a lattice decomposed in t computes it with the paper's scheme for
+ * overlapping communication with computation (section of that name): the two
+ * t-faces of `in` are projected to half spinors (the backward face multiplied by
+ * U_t^+ on the sending side) and packed; they are transferred on a second
+ * stream while the bulk kernel computes every site from local data; then a
+ * boundary kernel adds the hops through the faces to the two boundary slices.
+ * On one device the periodic lattice's faces go to itself, so the transfer is a
+ * device copy standing in for the neighbour exchange.  Each site's hops are
+ * added in the order of the one-thread-per-point fused kernel, so the result
+ * equals wl_dslash_apply's with tps = 1 bit for bit (up to FMA contraction
+ * choices of the compiler).  Asynchronous on `stream`; the context keeps the
+ * face buffers (24 complex numbers per face site) and the second stream;
+ * calls that overlap in time on one context race on those buffers.
+ * Errors: WL_ERR_ARG for a FULL subset or bad pointers, WL_ERR_UNSUPPORTED for
+ * 16-bit storage. */
+wl_status wl_dslash_apply_split(const wl_ctx *ctx, void *out, const void *in, wl_subset subset, wl_prec prec, int recon,
+                                int dagger, void *stream);
+
 /* out = M in or M^+ in for op = WL_OP_D (FULL fields) or WL_OP_DHAT (EVEN
  * fields).  Uses a context-owned odd-parity temporary for WL_OP_DHAT. */
 wl_status wl_dirac_apply(wl_ctx *ctx, void *out, const void *in, wl_op op, int dagger,

@@ -21,6 +21,7 @@
 #include "wl_dslash.h"
 #include "wl_ptc.h"
 #include "wl_access.h"
+#include "wl_halo.h"
 
 using namespace wl;
 
@@ -53,6 +54,7 @@ enum Slot {
     S_PTC_H, S_PTC_GH, S_PTC_O, S_PTC_GO, S_PTC_PART, S_PTC_E2,       // PTC workspace
     S_GCR_R, S_GCR_X, S_GCR_Z, S_GCR_W, S_GCR_TMP, S_GCR_RHS,          // FGCR workspace
     S_PCG,                                                             // preconditioned CGNR workspace
+    S_FACE,                                                            // t-face send / receive buffers
     S_NSLOTS
 };
 }
@@ -90,6 +92,9 @@ struct wl_ctx {
     hipGraph_t cg_graph = nullptr;
     hipGraphExec_t cg_exec = nullptr;
     std::vector<uintptr_t> cg_graph_key;
+    // bulk / boundary split: the stream the face exchange runs on, and its events
+    hipStream_t comm_stream = nullptr;
+    hipEvent_t halo_ev[2] = {nullptr, nullptr};
 };
 
 static int timing_key(int prec, int recon, int dagger, int epi) {
@@ -341,6 +346,9 @@ extern "C" wl_status wl_ctx_destroy(wl_ctx *c) {
     for (hipEvent_t e : c->handoff)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    for (hipEvent_t e : c->halo_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->comm_stream) (void)hipStreamDestroy(c->comm_stream);
     for (int p = 0; p < 5; ++p)
         for (int r = 0; r < 2; ++r)
             if (c->gauge[p][r]) (void)hipFree(c->gauge[p][r]);
@@ -557,6 +565,52 @@ extern "C" wl_status wl_dslash_apply(const wl_ctx *c, void *out, const void *in,
                                      int recon, int nrhs, void *stream) {
     return dslash_common(c, out, in, subset, prec, recon, nrhs, stream, false);
 }
+// Bulk / boundary split of the hopping term with the t-faces exchanged through
+// buffers on a second stream while the bulk is computed (the paper's overlap
+// scheme; on one device the faces of the periodic lattice go to itself).
+extern "C" wl_status wl_dslash_apply_split(const wl_ctx *cc, void *out, const void *in, wl_subset subset,
+                                           wl_prec prec, int recon, int dagger, void *stream) {
+    g_err.clear();
+    wl_ctx *c = const_cast<wl_ctx *>(cc);
+    if (subset != WL_EVEN && subset != WL_ODD) return fail(WL_ERR_ARG, "the split form takes one output parity");
+    wl_status st = check_field_args(c, subset, prec, 1);
+    if (st) return st;
+    if (prec != WL_F64 && prec != WL_F32) return fail(WL_ERR_UNSUPPORTED, "the split form needs FP64 or FP32 storage");
+    if (!recon_ok(prec, recon)) return fail(WL_ERR_UNSUPPORTED, "prec %d with recon %d not supported", prec, recon);
+    if (!out || !in || !aligned16(out) || !aligned16(in)) return fail(WL_ERR_ARG, "null or misaligned field pointer");
+    const size_t hb = half_bytes(c, prec, 1);
+    if (overlap(out, hb, in, hb)) return fail(WL_ERR_ARG, "out and in overlap");
+    HopArgs h;
+    int np = 1;
+    if ((st = fill_hop_args(c, prec, recon, out, in, nullptr, subset, 1, 0.0, 1.0, nullptr, 0, nullptr, h, &np)))
+        return st;
+    const size_t fb = (size_t)6 * c->g.st * (prec == WL_F64 ? 16 : 8);  // one face buffer
+    const size_t fba = (fb + 255) & ~(size_t)255;
+    if ((st = ensure_buf(c, S_FACE, 4 * fba))) return st;
+    char *fbase = (char *)c->buf[S_FACE];
+    void *send_fwd = fbase, *send_bwd = fbase + fba, *recv_fwd = fbase + 2 * fba, *recv_bwd = fbase + 3 * fba;
+    if (!c->comm_stream) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->comm_stream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->halo_ev[0], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->halo_ev[1], hipEventDisableTiming));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool dag = dagger != 0;
+    const int par = subset;
+    // faces first; their transfer runs on the comm stream while the bulk computes
+    HIP_TRY(launch_face_pack(prec, recon, dag, h, par, send_fwd, send_bwd, s));
+    HIP_TRY(hipEventRecord(c->halo_ev[0], s));
+    HIP_TRY(hipStreamWaitEvent(c->comm_stream, c->halo_ev[0], 0));
+    HIP_TRY(hipMemcpyAsync(recv_fwd, send_fwd, fb, hipMemcpyDeviceToDevice, c->comm_stream));
+    HIP_TRY(hipMemcpyAsync(recv_bwd, send_bwd, fb, hipMemcpyDeviceToDevice, c->comm_stream));
+    HIP_TRY(hipEventRecord(c->halo_ev[1], c->comm_stream));
+    h.swizzle = c->cfg[prec].swizzle;
+    HIP_TRY(launch_hop_bulk(prec, recon, dag, use_nontemporal(prec, c->cfg[prec], h, 1, 0), h, par, s));
+    HIP_TRY(hipStreamWaitEvent(s, c->halo_ev[1], 0));
+    HIP_TRY(launch_hop_boundary(prec, recon, dag, h, par, recv_fwd, recv_bwd, s));
+    return WL_OK;
+}
+
 extern "C" wl_status wl_dslash_dagger_apply(const wl_ctx *c, void *out, const void *in, wl_subset subset,
                                             wl_prec prec, int recon, int nrhs, void *stream) {
     return dslash_common(c, out, in, subset, prec, recon, nrhs, stream, true);

@@ -23,13 +23,14 @@ template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a) { re
 template <typename T> __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
 // i * a
 template <typename T> __device__ __forceinline__ cpx<T> ti(cpx<T> a) { return {-a.im, a.re}; }
-// a * b
+// a * b (the fused multiply-adds are written out, so that every kernel that
+// inlines this rounds the same way, whatever the compiler would contract)
 template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
 }
 // conj(a) * b
 template <typename T> __device__ __forceinline__ cpx<T> cjmul(cpx<T> a, cpx<T> b) {
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+    return {fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re))};
 }
 // c + a * b
 template <typename T> __device__ __forceinline__ cpx<T> cfma(cpx<T> a, cpx<T> b, cpx<T> c) {

@@ -129,6 +129,8 @@ _SIGS = {
     "wl_eigcg_vectors": (ctypes.c_int, [_vp, _ip, _dp]),
     "wl_eigcg_eigenvalues": (ctypes.c_int, [_vp, _ip, _dp]),
     "wl_su3_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_long, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    "wl_dslash_apply_split": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             _vp]),
     "wl_dirac_tm_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_eo_prepare_tm": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -399,6 +401,12 @@ def wl_su3_apply(psi, u, phi, n, mode=WL_ACCESS_SEQ, layout=0, index=None, ptrs=
     """psi(x_i) = U(x_i) phi(x_i) for i < n (device tensors; see wilson.h for modes and layouts)."""
     return _check(lib().wl_su3_apply(_ptr(psi), _ptr(u), _ptr(phi), int(n), int(mode), int(layout), _ptr(index),
                                      _ptr(ptrs), _stream(stream)))
+
+
+def wl_dslash_apply_split(ctx, out, inp, subset, prec=WL_F64, recon=18, dagger=False, stream=None):
+    """H in (H^+ in) for one output parity, bulk / boundary split with t-face exchange."""
+    return _check(lib().wl_dslash_apply_split(ctx, _ptr(out), _ptr(inp), int(subset), int(prec), int(recon),
+                                              int(bool(dagger)), _stream(stream)))
 
 
 def _ptr_array(items):

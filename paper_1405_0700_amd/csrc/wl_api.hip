@@ -74,6 +74,8 @@ struct wl_ctx {
     LaunchCfg cfg[5];  // hopping-kernel launch configuration per storage precision
     // kernel timing
     bool timing = false;
+    int timing_stride = 1;  // record every timing_stride-th hopping launch
+    unsigned long timing_seq = 0;
     struct TimedLaunch {
         int key;
         hipEvent_t ev[2];
@@ -525,7 +527,7 @@ static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, voi
                                  &np, tm_x, tm_h);
     if (st) return st;
     hipEvent_t *ev = nullptr;
-    if (c->timing && !c->capturing && c->timed.size() < (1u << 16)) {
+    if (c->timing && !c->capturing && c->timed.size() < (1u << 16) && c->timing_seq++ % c->timing_stride == 0) {
         if (c->pool_used + 2 > c->event_pool.size()) {
             for (int k = 0; k < 256; ++k) {
                 hipEvent_t e;
@@ -2656,10 +2658,13 @@ extern "C" wl_status wl_su3_apply(void *psi, const void *u, const void *phi, lon
 extern "C" wl_status wl_timing_enable(wl_ctx *c, int enable) {
     g_err.clear();
     if (!c) return fail(WL_ERR_ARG, "null context");
+    if (enable < 0) return fail(WL_ERR_ARG, "enable = %d < 0", enable);
     HIP_TRY(hipDeviceSynchronize());
     c->timed.clear();
     c->pool_used = 0;
     c->timing = enable != 0;
+    c->timing_stride = enable > 0 ? enable : 1;
+    c->timing_seq = 0;
     return WL_OK;
 }
 

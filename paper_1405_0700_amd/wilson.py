@@ -574,8 +574,9 @@ def wl_ctx_get_launch(ctx, prec):
     return cfg.as_tuple()
 
 
-def wl_timing_enable(ctx, enable=True):
-    return _check(lib().wl_timing_enable(ctx, int(bool(enable))))
+def wl_timing_enable(ctx, enable=True, every=1):
+    """Record every `every`-th hopping launch (enable=False: stop)."""
+    return _check(lib().wl_timing_enable(ctx, int(every) if enable else 0))
 
 
 def wl_timing_read(ctx, prec, recon, dagger, epilogue):

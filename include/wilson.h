@@ -117,7 +117,14 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *   tchunk  processing order of the output sites: 0 = even/odd index order
  *           (t slowest); k > 0 = the lattice is cut into chunks of k time
  *           slices and each chunk is walked with z slowest, so that the
- *           neighbours in t and z of a site are read close together in time
+ *           neighbours in t and z of a site are read close together in time;
+ *           k < 0 = chunks of -k z-planes over all t, each walked with t
+ *           slowest (with the swizzle and Lz = 8 (-k) each XCD walks its own
+ *           z-range, its sites' t-neighbours a few planes apart).  Values that
+ *           do not cut the lattice (|k| >= the extent) mean 0.
+ *           WL_TCHUNK_AUTO (the default): -(Lz / 8) when Lz is a multiple of 8
+ *           and at least 16, else 0 (measured: the FP64 half-dslash 8-10 %
+ *           faster at 24^3x48 and 32^3x64, the 12-rhs FP32 one 14 %)
  *   nt      1: non-temporal hints on the link loads and output stores (they
  *           keep the single-use link stream from evicting re-read spinors from
  *           L2, but also bypass the Infinity Cache); 0: off; -1: on when the
@@ -130,6 +137,7 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  * summation order of the 8 hops and rpt the compiler's contraction of
  * multiply-adds (rounding only).  Defaults are chosen per
  * precision by measurement (see wl_ctx_get_launch). */
+#define WL_TCHUNK_AUTO (-1048576) /* tchunk: the processing order chosen from the lattice */
 typedef struct {
     int block;
     int swizzle;

@@ -329,11 +329,11 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
     }
     c->gauge[WL_F64][0] = d;
     // measured defaults (MI355X, 24^3x48 and 32^3x64 lattices)
-    c->cfg[WL_F64] = {128, 1, 2, 0, -1};
-    c->cfg[WL_F32] = {128, 1, 2, 0, -1};
-    c->cfg[WL_F16N] = {256, 1, 1, 0, -1};
-    c->cfg[WL_BF16N] = {256, 1, 1, 0, -1};
-    c->cfg[WL_I16N] = {256, 1, 1, 0, -1};
+    c->cfg[WL_F64] = {128, 1, 2, WL_TCHUNK_AUTO, -1};
+    c->cfg[WL_F32] = {128, 1, 2, WL_TCHUNK_AUTO, -1};
+    c->cfg[WL_F16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1};
+    c->cfg[WL_BF16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1};
+    c->cfg[WL_I16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1};
     c->slab[WL_F64][0] = slab;
     *out = c;
     return WL_OK;
@@ -1847,11 +1847,11 @@ extern "C" wl_status wl_autotune(wl_ctx *c, wl_prec prec, int recon, int nrhs, c
             for (int tps : {1, 2})
                 for (int rpt : {1, 2, 3, 4})
                 for (int swz : {0, 1})
-                    for (int tch : {0, 2, 4})
+                    for (int tch : {0, 4, WL_TCHUNK_AUTO})
                         for (int nt : {0, 1}) {
                             if (tps == 2 && !two) continue;
                             if (rpt > 1 && (tps != 1 || nrhs % rpt)) continue;
-                            if (tch >= c->dims[3]) continue;
+                            if (tch > 0 && tch >= c->dims[3]) continue;
                             LaunchCfg g;
                             g.block = block;
                             g.tps = tps;
@@ -2700,7 +2700,6 @@ extern "C" wl_status wl_ctx_set_launch(wl_ctx *c, wl_prec prec, const wl_launch 
     if (l->tps != 1 && l->tps != 2) return fail(WL_ERR_ARG, "tps %d not in {1, 2}", l->tps);
     if (l->tps == 2 && prec != WL_F64 && prec != WL_F32)
         return fail(WL_ERR_UNSUPPORTED, "two threads per point needs FP64 or FP32 storage");
-    if (l->tchunk < 0) return fail(WL_ERR_ARG, "tchunk %d < 0", l->tchunk);
     if (l->nt < -1 || l->nt > 1) return fail(WL_ERR_ARG, "nt %d not in {-1, 0, 1}", l->nt);
     if (l->rpt < 1 || l->rpt > 4) return fail(WL_ERR_ARG, "rpt %d not in 1..4", l->rpt);
     if (l->rpt > 1 && l->tps != 1) return fail(WL_ERR_ARG, "rpt > 1 needs tps = 1");

@@ -32,8 +32,10 @@ struct LaunchCfg {
     int swizzle = 1;   // give each XCD one contiguous range of blocks
     int tps = 1;       // threads per output point: 1, or 2 (forward / backward hops in
                        // the two halves of a wavefront; FP64 and FP32 storage only)
-    int tchunk = 0;    // processing order: 0 = e/o index order; k = chunks of k time
-                       // slices, each walked with z slowest
+    int tchunk = WL_TCHUNK_AUTO;  // processing order: 0 = e/o index order; k > 0 = chunks of k
+                       // time slices, each walked with z slowest; k < 0 = chunks of -k
+                       // z-planes over all t, each walked with t slowest; AUTO: -(Lz/8)
+                       // when Lz is a multiple of 8 and >= 16, else 0
     int nt = -1;       // non-temporal link loads / output stores: 1 on, 0 off,
                        // -1 on when the launch's working set exceeds 200 MB
     int rpt = 1;       // right-hand sides per thread (each link load reused for all

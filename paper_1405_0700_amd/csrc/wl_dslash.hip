@@ -131,8 +131,18 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
     if (block <= 0 || block > 256 || block % 64) return hipErrorInvalidValue;
     const int tps = effective_tps(prec, cfg);
     a.swizzle = cfg.swizzle;
-    a.tchunk = cfg.tchunk > 0 && cfg.tchunk < a.g.L[3] ? cfg.tchunk : 0;
-    a.chunk_sites = a.tchunk * a.g.L[2] * a.g.sz;
+    int tch = cfg.tchunk;
+    if (tch == WL_TCHUNK_AUTO) tch = a.g.L[2] % 8 == 0 && a.g.L[2] >= 16 ? -(a.g.L[2] / 8) : 0;
+    if (tch > 0 && tch < a.g.L[3]) {
+        a.tchunk = tch;
+        a.chunk_sites = a.tchunk * a.g.L[2] * a.g.sz;
+    } else if (tch < 0 && -tch < a.g.L[2]) {
+        a.tchunk = tch;
+        a.chunk_sites = -a.tchunk * a.g.L[3] * a.g.sz;
+    } else {
+        a.tchunk = 0;
+        a.chunk_sites = 0;
+    }
     const int rpt = effective_rpt(cfg, a.nrhs, tps);
     if (rpt > 1 && (a.nrhs > 256 || block < 64)) return hipErrorInvalidValue;
     dim3 grid((unsigned)hop_launch_blocks(tps, cfg, a.npts, a.nrhs), (unsigned)nparity);

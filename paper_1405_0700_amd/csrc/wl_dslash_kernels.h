@@ -272,9 +272,21 @@ __device__ __forceinline__ void hop_rt(const HopArgs &a, int par, int i, int xh,
 
 // e/o index of the site at position ps of the processing order
 __device__ __forceinline__ int site_of(const HopArgs &a, long ps) {
-    if (a.tchunk <= 0) return (int)ps;
+    if (a.tchunk == 0) return (int)ps;
     const Geom &g = a.g;
     const int plane = g.sz;  // (Lx/2) * Ly sites of one (z, t)
+    if (a.tchunk < 0) {
+        // chunks of -tchunk z-planes over all t, each walked with t slowest
+        const int k = -a.tchunk;
+        const long chunk = ps / a.chunk_sites;
+        const int r = (int)(ps - chunk * a.chunk_sites);
+        const int z0 = (int)chunk * k;
+        const int kz = min(k, g.L[2] - z0);  // the last chunk may be thinner
+        const int t = r / (kz * plane);
+        const int q = r - t * kz * plane;
+        const int zl = q / plane;
+        return (q - zl * plane) + plane * (z0 + zl) + g.st * t;
+    }
     const long chunk = ps / a.chunk_sites;
     const int r = (int)(ps - chunk * a.chunk_sites);
     const int t0 = (int)chunk * a.tchunk;

@@ -27,6 +27,7 @@ WL_F64, WL_F32, WL_F16N, WL_BF16N, WL_I16N = 0, 1, 2, 3, 4
 WL_EVEN, WL_ODD, WL_FULL = 0, 1, 2
 WL_OP_D, WL_OP_DHAT = 0, 1
 WL_ACCESS_SEQ, WL_ACCESS_INDEX, WL_ACCESS_PTR = 0, 1, 2
+WL_TCHUNK_AUTO = -1048576
 
 PREC = {"f64": WL_F64, "f32": WL_F32, "f16n": WL_F16N, "bf16n": WL_BF16N, "i16n": WL_I16N}
 SUBSET = {"even": WL_EVEN, "odd": WL_ODD, "full": WL_FULL}
@@ -562,7 +563,7 @@ def wl_ptc_step(net, lr, stream=None) -> float:
     return loss.value
 
 
-def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=0, nt=-1, rpt=1):
+def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=WL_TCHUNK_AUTO, nt=-1, rpt=1):
     cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt), int(rpt))
     return _check(lib().wl_ctx_set_launch(ctx, prec, ctypes.addressof(cfg)))
 

@@ -361,7 +361,8 @@ def test_cg_free_field_plane_wave_one_iteration():
 # ------------------------------------------------------------------ launch configurations
 @pytest.mark.parametrize("prec", [W.WL_F64, W.WL_F32])
 @pytest.mark.parametrize("block,swizzle,tps,tchunk,nt", [(64, 0, 1, 0, 0), (256, 1, 2, 0, 1), (128, 0, 2, 3, -1),
-                                                         (192, 1, 1, 4, 1), (64, 1, 2, 5, 0), (256, 1, 1, 1, 1)])
+                                                         (192, 1, 1, 4, 1), (64, 1, 2, 5, 0), (256, 1, 1, 1, 1),
+                                                         (128, 1, 2, -1, 1), (256, 0, 1, -3, -1), (64, 1, 1, -2, 0)])
 def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
     dims = (6, 10, 4, 14)
     kappa = 0.13
@@ -447,7 +448,7 @@ def test_rhs_per_thread_matches_one_point_per_thread(prec, recon, nrhs, rpt):
 
 def test_launch_config_rejects_bad_values():
     _, lat = setup((4, 4, 4, 4))
-    for args in [(W.WL_F64, 32, 0, 1), (W.WL_F64, 320, 0, 1), (W.WL_F64, 256, 0, 3), (W.WL_F64, 256, 0, 1, -1),
+    for args in [(W.WL_F64, 32, 0, 1), (W.WL_F64, 320, 0, 1), (W.WL_F64, 256, 0, 3),
                  (W.WL_F64, 256, 0, 1, 0, 2), (W.WL_F64, 256, 0, 1, 0, 0, 5), (W.WL_F64, 256, 0, 2, 0, 0, 2)]:
         with pytest.raises(W.WilsonError) as e:
             W.wl_ctx_set_launch(lat.ctx, *args)

@@ -607,6 +607,7 @@ extern "C" wl_status wl_dslash_apply_split(const wl_ctx *cc, void *out, const vo
     HIP_TRY(hipMemcpyAsync(recv_bwd, send_bwd, fb, hipMemcpyDeviceToDevice, c->comm_stream));
     HIP_TRY(hipEventRecord(c->halo_ev[1], c->comm_stream));
     h.swizzle = c->cfg[prec].swizzle;
+    set_processing_order(h, c->cfg[prec].tchunk);
     HIP_TRY(launch_hop_bulk(prec, recon, dag, use_nontemporal(prec, c->cfg[prec], h, 1, 0), h, par, s));
     HIP_TRY(hipStreamWaitEvent(s, c->halo_ev[1], 0));
     HIP_TRY(launch_hop_boundary(prec, recon, dag, h, par, recv_fwd, recv_bwd, s));

@@ -44,6 +44,8 @@ struct LaunchCfg {
 
 // whether a launch uses the non-temporal hints
 bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int nparity, int epi);
+// a.tchunk / a.chunk_sites for a LaunchCfg tchunk value (WL_TCHUNK_AUTO resolved from the lattice)
+void set_processing_order(HopArgs &a, int tchunk);
 
 // Enqueue out = a x + b H in (H^+ if dagger) over `nparity` output parities.
 // Returns hipSuccess or the launch error.

@@ -125,13 +125,9 @@ hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int nparity,
-                      const LaunchCfg &cfg, hipStream_t stream) {
-    const int block = cfg.block;
-    if (block <= 0 || block > 256 || block % 64) return hipErrorInvalidValue;
-    const int tps = effective_tps(prec, cfg);
-    a.swizzle = cfg.swizzle;
-    int tch = cfg.tchunk;
+// a.tchunk / a.chunk_sites for a LaunchCfg tchunk value (AUTO resolved from the lattice)
+void set_processing_order(HopArgs &a, int tchunk) {
+    int tch = tchunk;
     if (tch == WL_TCHUNK_AUTO) tch = a.g.L[2] % 8 == 0 && a.g.L[2] >= 16 ? -(a.g.L[2] / 8) : 0;
     if (tch > 0 && tch < a.g.L[3]) {
         a.tchunk = tch;
@@ -143,6 +139,15 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
         a.tchunk = 0;
         a.chunk_sites = 0;
     }
+}
+
+hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int nparity,
+                      const LaunchCfg &cfg, hipStream_t stream) {
+    const int block = cfg.block;
+    if (block <= 0 || block > 256 || block % 64) return hipErrorInvalidValue;
+    const int tps = effective_tps(prec, cfg);
+    a.swizzle = cfg.swizzle;
+    set_processing_order(a, cfg.tchunk);
     const int rpt = effective_rpt(cfg, a.nrhs, tps);
     if (rpt > 1 && (a.nrhs > 256 || block < 64)) return hipErrorInvalidValue;
     dim3 grid((unsigned)hop_launch_blocks(tps, cfg, a.npts, a.nrhs), (unsigned)nparity);

@@ -37,16 +37,17 @@ __global__ void __launch_bounds__(256) k_face_pack(const HopArgs a, int par,
     }
 }
 
-// One thread per output site: the spatial hops and the t hops that stay in the
-// local volume.  Interior slices are finished (scaled and stored); the two
+// One thread per output site (in the launch's processing order): the spatial
+// hops and the t hops that stay in the local volume.  Interior slices are finished (scaled and stored); the two
 // boundary slices store their partial sums, cut where the fused order reaches
 // the first hop through a face (before t+ on the last slice, before t- on the
 // first).
 template <int SP, int GP, int RECON, bool DAG, bool NT>
 __global__ void __launch_bounds__(256) k_hop_bulk(const HopArgs a, int par) {
     using T = typename SpinorIO<SP>::real;
-    const long i = logical_block(a.swizzle) * blockDim.x + threadIdx.x;
-    if (i >= a.npts) return;
+    const long ps = logical_block(a.swizzle) * blockDim.x + threadIdx.x;
+    if (ps >= a.npts) return;
+    const long i = site_of(a, ps);
     int c[4];
     eo_coords(a.g, (int)i, par, c);
     const int xh = c[0] >> 1, lt = a.g.L[3];

@@ -112,8 +112,10 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *   swizzle 1: reorder blocks so that each of the 8 XCDs (each with its own L2)
  *           processes one contiguous range of the processing order; 0: hardware order
  *   tps     threads per output point: 1 (one thread does all 8 hops) or 2 (the
- *           forward and backward hops run in the two halves of a wavefront;
- *           FP64 and FP32 storage only, else WL_ERR_UNSUPPORTED)
+ *           forward and backward hops run in the two halves of a wavefront,
+ *           each half storing two spin components; with 16-bit storage the
+ *           halves first agree on the point's norm, so the stored bytes are
+ *           those of the one-thread store)
  *   tchunk  processing order of the output sites: 0 = even/odd index order
  *           (t slowest); k > 0 = the lattice is cut into chunks of k time
  *           slices and each chunk is walked with z slowest, so that the

@@ -2699,8 +2699,6 @@ extern "C" wl_status wl_ctx_set_launch(wl_ctx *c, wl_prec prec, const wl_launch 
     if (l->block < 64 || l->block > 256 || l->block % 64)
         return fail(WL_ERR_ARG, "block %d not in {64, 128, 192, 256}", l->block);
     if (l->tps != 1 && l->tps != 2) return fail(WL_ERR_ARG, "tps %d not in {1, 2}", l->tps);
-    if (l->tps == 2 && prec != WL_F64 && prec != WL_F32)
-        return fail(WL_ERR_UNSUPPORTED, "two threads per point needs FP64 or FP32 storage");
     if (l->nt < -1 || l->nt > 1) return fail(WL_ERR_ARG, "nt %d not in {-1, 0, 1}", l->nt);
     if (l->rpt < 1 || l->rpt > 4) return fail(WL_ERR_ARG, "rpt %d not in 1..4", l->rpt);
     if (l->rpt > 1 && l->tps != 1) return fail(WL_ERR_ARG, "rpt > 1 needs tps = 1");

@@ -224,6 +224,40 @@ template <int P> struct SpinorIO16 {
         }
         st_out<NT, float>(norm_ptr(base, i), s);
     }
+    // Spin half hf (components 6 hf .. 6 hf + 5): half 0 is unit 0 and the low 8
+    // bytes of unit 1, half 1 the high 8 bytes of unit 1 and unit 2.
+    __device__ static void load_half(const void *base, long i, int hf, cpx<float> v[6]) {
+        const uint4 *p = units(base, i);
+        const float s = *norm_ptr(base, i);
+        const uint4 f = p[(hf ? 2 : 0) * BLK];
+        const uint2 q = ((const uint2 *)(p + BLK))[hf];
+        const uint32_t w[6] = {hf ? q.x : f.x, hf ? q.y : f.y, hf ? f.x : f.z,
+                               hf ? f.y : f.w, hf ? f.z : q.x, hf ? f.w : q.y};
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            v[j] = {s * Half16<P>::dec((uint16_t)(w[j] & 0xffffu)), s * Half16<P>::dec((uint16_t)(w[j] >> 16))};
+    }
+    // Stores spin half hf with the point's norm s (the largest component over
+    // both halves, found by the caller), encoded exactly as store() does; v is
+    // replaced by the values as stored.  The hf = 0 half writes the norm.
+    template <bool NT = false>
+    __device__ static void store_half_shared(void *base, long i, int hf, cpx<float> v[6], float s) {
+        if (!(s >= 1.17549435e-38f)) s = 0.f;
+        const float inv = s > 0.f ? 1.0f / s : 0.f;
+        uint32_t w[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const uint16_t lo = Half16<P>::enc(v[j].re * inv), hi = Half16<P>::enc(v[j].im * inv);
+            w[j] = (uint32_t)lo | ((uint32_t)hi << 16);
+            v[j] = {s * Half16<P>::dec(lo), s * Half16<P>::dec(hi)};
+        }
+        uint4 *p = (uint4 *)units(base, i);
+        const v4u full = hf ? v4u{w[2], w[3], w[4], w[5]} : v4u{w[0], w[1], w[2], w[3]};
+        const v2u part = hf ? v2u{w[0], w[1]} : v2u{w[4], w[5]};
+        st_out<NT, v4u>(p + (hf ? 2 : 0) * BLK, full);
+        st_out<NT, v2u>((v2u *)(p + BLK) + hf, part);
+        if (hf == 0) st_out<NT, float>(norm_ptr(base, i), s);
+    }
 };
 template <> struct SpinorIO<WL_F16N> : SpinorIO16<WL_F16N> {};
 template <> struct SpinorIO<WL_BF16N> : SpinorIO16<WL_BF16N> {};

@@ -31,7 +31,7 @@ struct LaunchCfg {
     int block = 256;   // threads per block (multiple of 64, <= 256)
     int swizzle = 1;   // give each XCD one contiguous range of blocks
     int tps = 1;       // threads per output point: 1, or 2 (forward / backward hops in
-                       // the two halves of a wavefront; FP64 and FP32 storage only)
+                       // the two halves of a wavefront)
     int tchunk = WL_TCHUNK_AUTO;  // processing order: 0 = e/o index order; k > 0 = chunks of k
                        // time slices, each walked with z slowest; k < 0 = chunks of -k
                        // z-planes over all t, each walked with t slowest; AUTO: -(Lz/8)

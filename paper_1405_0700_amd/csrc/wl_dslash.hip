@@ -21,11 +21,9 @@ namespace wl {
 
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 static void launch_one(int tps, dim3 grid, dim3 block, hipStream_t s, const HopArgs &a) {
-    if constexpr (SP == WL_F64 || SP == WL_F32) {
-        if (tps == 2) {
-            hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>), grid, block, 0, s, a);
-            return;
-        }
+    if (tps == 2) {
+        hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>), grid, block, 0, s, a);
+        return;
     }
     hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI, NT>), grid, block, 0, s, a);
 }
@@ -63,7 +61,8 @@ bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int npari
 }
 
 int effective_tps(int prec, const LaunchCfg &cfg) {
-    return (prec == WL_F64 || prec == WL_F32) && cfg.tps == 2 ? 2 : 1;
+    (void)prec;
+    return cfg.tps == 2 ? 2 : 1;
 }
 
 template <int SP, int GP, int RECON, int TPS>

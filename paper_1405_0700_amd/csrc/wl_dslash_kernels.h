@@ -525,11 +525,29 @@ __device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, lon
 #pragma unroll
             for (int k = 0; k < 6; ++k) res[k] = b * res[k];
         }
-        SpinorIO<SP>::template store_half<NT>(a.out[par], pt, hf, res);
-        if constexpr (EPI & EPI_NORM) {
-            if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(a.out[par], pt, hf, res);
+    }
+    if constexpr (SP == WL_F64 || SP == WL_F32) {
+        if (active) {
+            SpinorIO<SP>::template store_half<NT>(a.out[par], pt, hf, res);
+            if constexpr (EPI & EPI_NORM) {
+                if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(a.out[par], pt, hf, res);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
+                for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
+            }
+        }
+    } else {
+        // 16-bit storage: one norm per point, the largest component of both halves
+        float m = 0.f;
+        if (active)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) m = fmaxf(m, fmaxf(fabsf(res[k].re), fabsf(res[k].im)));
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+        if (active) {
+            SpinorIO<SP>::template store_half_shared<NT>(a.out[par], pt, hf, res, m);
+            if constexpr (EPI & EPI_NORM) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
+            }
         }
     }
     *gid_out = gid;

@@ -453,6 +453,53 @@ def test_launch_config_rejects_bad_values():
         with pytest.raises(W.WilsonError) as e:
             W.wl_ctx_set_launch(lat.ctx, *args)
         assert e.value.status == W.WL_ERR_ARG
-    with pytest.raises(W.WilsonError) as e:
-        W.wl_ctx_set_launch(lat.ctx, W.WL_F16N, 256, 0, 2)
-    assert e.value.status == W.WL_ERR_UNSUPPORTED
+
+
+
+@pytest.mark.parametrize("prec", [W.WL_F16N, W.WL_BF16N, W.WL_I16N])
+def test_two_threads_per_point_16bit(prec):
+    """16-bit storage with two threads per point: the two halves agree on the point's norm before
+    they encode, so each output equals the one-thread result up to the different summation order
+    of the 8 hops (at most one storage step of the site's largest component) and matches the
+    oracle to the format's tolerance; the fused-norm epilogue drives a mixed CG to 1e-10."""
+    dims = (6, 10, 4, 14)
+    kappa = 0.13
+    ph = random_phases(83)
+    u, lat = setup(dims, seed=84, phases=ph)
+    phi = synth.gaussian_spinor(dims, seed=85)
+    saved = W.wl_ctx_get_launch(lat.ctx, prec)
+    step = {W.WL_F16N: 2.0 ** -10, W.WL_BF16N: 2.0 ** -7, W.WL_I16N: 1.0 / 16383}[prec]
+    try:
+        res = {}
+        for tps in (1, 2):
+            W.wl_ctx_set_launch(lat.ctx, prec, 128, 1, tps)
+            inp = lat.pack(phi, W.WL_FULL, prec)
+            outs = []
+            for dagger in (False, True):
+                o = lat.new(W.WL_FULL, prec)
+                (W.wl_dslash_dagger_apply if dagger else W.wl_dslash_apply)(lat.ctx, o, inp, W.WL_FULL, prec, 12)
+                outs.append(o)
+            o = lat.new(W.WL_FULL, prec)
+            W.wl_dirac_apply(lat.ctx, o, inp, W.WL_OP_D, False, kappa, prec, 12)
+            outs.append(o)
+            torch.cuda.synchronize()
+            res[tps] = [lat.unpack(x, W.WL_FULL, prec).reshape(phi.shape) for x in outs]
+        wants = [orc.hop(phi, u, ph), orc.hop(phi, u, ph, dagger=True), orc.dirac(phi, u, kappa, ph)]
+        for a, b, want in zip(res[1], res[2], wants):
+            smax = np.max(np.abs(np.stack([a.real, a.imag])), axis=(0, -1, -2), keepdims=True)[0]
+            assert np.all(np.abs(b - a) <= 2 * step * smax + 1e-30)
+            assert rel(b, want) < TOL[prec]
+        # mixed CG with the two-thread kernels (norm epilogue, reliable updates) converges
+        W.wl_ctx_set_launch(lat.ctx, prec, 128, 1, 2)
+        b = synth.gaussian_spinor(dims, seed=86)
+        pe, po = orc.eo_split(b, dims)
+        p = W.wl_solver_params_default()
+        p.prec, p.recon, p.tol = prec, 12, 1e-10
+        x = lat.new(W.WL_EVEN)
+        st, info = W.wl_cg_solve(lat.ctx, x, lat.pack(pe, W.WL_EVEN), W.WL_OP_DHAT, kappa, params=p)
+        assert st == W.WL_OK
+        xe = lat.unpack(x, W.WL_EVEN)
+        a_ = lambda v: orc.schur(orc.schur(v, u, kappa, ph), u, kappa, ph, dagger=True)
+        assert rel(a_(xe), pe) <= 1.05e-10
+    finally:
+        W.wl_ctx_set_launch(lat.ctx, prec, *saved)

@@ -470,12 +470,24 @@ __device__ __forceinline__ void block_sum_by_rhs(double v, int rhs, int nrhs, do
     lds[threadIdx.x] = v;
     lrhs[threadIdx.x] = rhs;
     __syncthreads();
-    if ((int)threadIdx.x < nrhs) {
-        const int r = threadIdx.x;
+    // stage 1: thread t sums right-hand side t % nrhs over slice t / nrhs of the
+    // block (q slices of len entries); stage 2: one thread per right-hand side adds
+    // its q slice sums.  A fixed order, ~len + q serial steps instead of blockDim.
+    const int nt = blockDim.x, q = nt / nrhs, len = (nt + q - 1) / q;
+    const int t = threadIdx.x;
+    double part = 0.0;
+    if (t < q * nrhs) {
+        const int r = t % nrhs, k0 = (t / nrhs) * len, k1 = min(k0 + len, nt);
+        for (int k = k0; k < k1; ++k)
+            if (lrhs[k] == r) part += lds[k];
+    }
+    __syncthreads();
+    if (t < q * nrhs) lds[t] = part;
+    __syncthreads();
+    if (t < nrhs) {
         double s = 0.0;
-        for (int t = 0; t < (int)blockDim.x; ++t)
-            if (lrhs[t] == r) s += lds[t];
-        out[(long)r * stride] = s;
+        for (int j = 0; j < q; ++j) s += lds[j * nrhs + t];
+        out[(long)t * stride] = s;
     }
     __syncthreads();
 }

@@ -60,15 +60,15 @@ def step_bytes(vh: int, iters: int, restarts: int) -> int:
         p = r copy                                  384
       per CG iteration:
         q = D_hat p (hop, hop+x, fused norm)      1536 + 1728
-        s = D_hat^+ q                             1536 + 1728
-        x += a p, r -= a s (x, r read+write; p, s read)   1152
-        p = r + b p                                 576
+        r -= a D_hat^+ q (hop, hop+x with r read+write in place of the output, fused norm)
+                                                  1536 + 1728 + 192
+        x += a p, p = r + b p (x, p read+write; r read)    960
       eo_reconstruct (hop + x read)               1728
     per even site; the single-block scalar kernels are not counted.
     """
     h, hx = SITE_BYTES["hop"], SITE_BYTES["hop_xpay"]
     true_res = 2 * h + 2 * hx + 576
-    per_iter = 2 * h + 2 * hx + 1152 + 576
+    per_iter = 2 * h + 2 * hx + 192 + 960
     fixed = hx + (h + hx) + 192 + hx
     per_cycle = 2 * true_res + 384
     return vh * (fixed + (1 + restarts) * per_cycle + iters * per_iter)

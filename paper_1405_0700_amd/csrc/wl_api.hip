@@ -100,7 +100,7 @@ struct wl_ctx {
 };
 
 static int timing_key(int prec, int recon, int dagger, int epi) {
-    return ((prec * 2 + (recon == 12 ? 1 : 0)) * 2 + (dagger ? 1 : 0)) * 4 + epi;
+    return ((prec * 2 + (recon == 12 ? 1 : 0)) * 2 + (dagger ? 1 : 0)) * 8 + epi;
 }
 
 static bool prec_ok(int p) { return p >= WL_F64 && p <= WL_I16N; }
@@ -520,12 +520,25 @@ static wl_status fill_hop_args(wl_ctx *c, int prec, int recon, void *out, const 
 static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, void *out, const void *in,
                           const void *x, int out_subset, int nrhs, double a, double b, double *partials,
                           long part_stride, const int *flag, hipStream_t s, long *nblk_out = nullptr,
-                          double tm_x = 0.0, double tm_h = 0.0) {
+                          double tm_x = 0.0, double tm_h = 0.0, void *cg_r = nullptr,
+                          const CGScalars *cg_sc = nullptr) {
     HopArgs h;
     int np = 1;
     wl_status st = fill_hop_args(c, prec, recon, out, in, x, out_subset, nrhs, a, b, partials, part_stride, flag, h,
                                  &np, tm_x, tm_h);
     if (st) return st;
+    if (epi & EPI_CGR) {
+        // the residual has the output's subset and storage
+        const size_t hb = half_bytes(c, prec, nrhs);
+        if (out_subset == WL_FULL) {
+            h.r[0] = cg_r;
+            h.r[1] = (char *)cg_r + hb;
+        } else {
+            h.r[out_subset] = cg_r;
+        }
+        h.alpha = (const char *)cg_sc + offsetof(CGScalars, alpha);
+        h.alpha_stride = sizeof(CGScalars);
+    }
     hipEvent_t *ev = nullptr;
     if (c->timing && !c->capturing && c->timed.size() < (1u << 16) && c->timing_seq++ % c->timing_stride == 0) {
         if (c->pool_used + 2 > c->event_pool.size()) {
@@ -636,6 +649,24 @@ static wl_status apply_m(wl_ctx *c, int op, bool dag, double kappa, int prec, in
     if (st) return st;
     return hop_core(c, prec, recon, dag, epi, out, tmp, in, WL_EVEN, nrhs, 1.0, -kappa * kappa, partials, stride,
                     flag, s, nblk, nu, 0.0);
+}
+
+// r -= alpha M^+ in with ||r||^2 partials (the last stage of CG's A p, fused with the
+// residual update; alpha per rhs from sc): the operator applications of apply_m(dag)
+// with the final one's result folded into r instead of being stored.
+static wl_status apply_mdag_update_r(wl_ctx *c, int op, double kappa, int prec, int recon, int nrhs, void *r,
+                                     const void *in, void *tmp, double *partials, long stride, const int *flag,
+                                     hipStream_t s, long *nblk, double mu, const CGScalars *sc) {
+    const int epi = EPI_XPAY | EPI_NORM | EPI_CGR;
+    const double nu = -2.0 * kappa * mu;
+    if (op == WL_OP_D)
+        return hop_core(c, prec, recon, true, epi, r, in, in, WL_FULL, nrhs, 1.0, -kappa, partials, stride, flag, s,
+                        nblk, nu, 0.0, r, sc);
+    wl_status st = hop_core(c, prec, recon, true, 0, tmp, in, nullptr, WL_ODD, nrhs, 0.0, 1.0 / (1.0 + nu * nu),
+                            nullptr, 0, flag, s, nullptr, 0.0, -nu);
+    if (st) return st;
+    return hop_core(c, prec, recon, true, epi, r, tmp, in, WL_EVEN, nrhs, 1.0, -kappa * kappa, partials, stride, flag,
+                    s, nblk, nu, 0.0, r, sc);
 }
 
 static wl_status dirac_common(wl_ctx *c, void *out, const void *in, wl_op op, int dagger, double kappa, double mu,
@@ -941,6 +972,24 @@ static wl_status cg_iteration(CGRun &R, bool reliable) {
                            R.done, R.s, &nblk, R.mu);
     if (st) return st;
     HIP_TRY(cg_alpha(R.sc, R.nrhs, R.partials, R.stride, nblk, R.done, R.s));
+    const LaunchCfg &cfg = R.c->cfg[R.prec];
+    if (!reliable && effective_rpt(cfg, R.nrhs, effective_tps(R.prec, cfg)) == 1) {
+        // the last operator stage updates r in place (r -= alpha A p, ||r||^2) instead of
+        // storing A p; then x += alpha p and p = r + beta p in one pass
+        long nblk2 = 0;
+        if ((st = apply_mdag_update_r(R.c, R.op, R.kappa, R.prec, R.recon, R.nrhs, R.r, R.q, R.tmp, R.partials,
+                                      R.stride, R.done, R.s, &nblk2, R.mu, R.sc)))
+            return st;
+        HIP_TRY(cg_beta(R.sc, R.nrhs, R.partials, R.stride, nblk2, R.done, 0, R.s));
+        VecArgs u = vec_args(R.c, R.prec, R.nrhs);
+        set_vec(u, 0, R.x, R.hb_hi);
+        set_vec(u, 1, R.p, R.hb_lo);
+        set_vec(u, 2, R.r, R.hb_lo);
+        u.sc = R.sc;
+        u.flag = nullptr;  // must also run after the last system's final step
+        HIP_TRY(cg_update_xp(R.prec, u, R.nh, R.s));
+        return WL_OK;
+    }
     st = apply_m(R.c, R.op, true, R.kappa, R.prec, R.recon, R.nrhs, R.sv, R.q, R.tmp, nullptr, 0, R.done, R.s,
                  nullptr, R.mu);
     if (st) return st;
@@ -2673,7 +2722,7 @@ extern "C" wl_status wl_timing_read(wl_ctx *c, wl_prec prec, int recon, int dagg
                                     double *total_ms) {
     g_err.clear();
     if (!c || !count || !total_ms) return fail(WL_ERR_ARG, "null argument");
-    if (!prec_ok(prec) || !recon_ok(prec, recon) || epilogue < 0 || epilogue > 3)
+    if (!prec_ok(prec) || !recon_ok(prec, recon) || epilogue < 0 || epilogue > 7)
         return fail(WL_ERR_ARG, "bad kernel selector");
     const int key = timing_key(prec, recon, dagger != 0, epilogue);
     int n = 0;

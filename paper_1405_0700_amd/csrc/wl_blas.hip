@@ -151,6 +151,37 @@ __global__ void __launch_bounds__(256) k_cg_p(const VecArgs a) {
     }
 }
 
+// The rest of an iteration whose residual was updated in the hopping epilogue:
+// x += alpha p (x FP64, where this iteration took a step: alpha != 0, which also
+// covers a system that stopped at its beta step), then p = r + beta p (systems
+// still iterating).  v0 = x, v1 = p, v2 = r.  Launched without the active-count
+// gate (the count is already 0 after the last system's final step).
+template <int SP>
+__global__ void __launch_bounds__(256) k_cg_xp(const VecArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    WL_FLAG_EXIT
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.n) return;
+    const CGScalars &sc = a.sc[(int)(gid % a.nrhs)];
+    const double alpha = sc.alpha;
+    if (alpha == 0.0) return;
+    cpx<T> p[12];
+    SpinorIO<SP>::load(a.v[1][h], gid, p);
+    cpx<double> x[12];
+    SpinorIO<WL_F64>::load(a.v[0][h], gid, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = {fma(alpha, (double)p[k].re, x[k].re), fma(alpha, (double)p[k].im, x[k].im)};
+    SpinorIO<WL_F64>::store(a.v[0][h], gid, x);
+    if (!sc.active) return;
+    const T beta = (T)sc.beta;
+    cpx<T> r[12];
+    SpinorIO<SP>::load(a.v[2][h], gid, r);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = {fma(beta, p[k].re, r[k].re), fma(beta, p[k].im, r[k].im)};
+    SpinorIO<SP>::store(a.v[1][h], gid, p);
+}
+
 template <int DP, int SP, bool ACC>
 __global__ void __launch_bounds__(256) k_convert(const VecArgs a) {
     using TS = typename SpinorIO<SP>::real;
@@ -366,7 +397,12 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double *partials, lon
 // sides still iterating; a system leaves the count when it stops.
 __global__ void __launch_bounds__(256) k_cg_alpha(CGScalars *sc, const double *partials, long stride, long nblk,
                                                   const int *count) {
-    if (count && *count == 0) return;
+    // alpha = 0 marks an iteration that takes no step (read by the x update that
+    // follows a fused residual update, which must run after the last system stops)
+    if (count && *count == 0) {
+        if (threadIdx.x == 0) sc[blockIdx.x].alpha = 0.0;
+        return;
+    }
     __shared__ double lds[16];
     const int r = blockIdx.x;
     CGScalars &c = sc[r];
@@ -519,6 +555,10 @@ hipError_t blas_blockdot(const BlockDotArgs &a, hipStream_t s) {
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_blockdot, dim3((unsigned)blockdot_blocks(a.n)), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+hipError_t cg_update_xp(int prec, VecArgs &a, int nh, hipStream_t s) {
+    dim3 grid = vgrid(a, nh);
+    WL_DISPATCH_PREC(prec, k_cg_xp)
 }
 hipError_t blas_scale_by_rho(VecArgs &a, int nh, hipStream_t s) {
     if (!a.sc || a.nrhs != 1) return hipErrorInvalidValue;

@@ -5,7 +5,11 @@
 
 namespace wl {
 
-enum : int { EPI_XPAY = 1, EPI_NORM = 2 };
+// EPI_CGR (always with EPI_XPAY | EPI_NORM): the result y = a x + b H in is not
+// stored; instead the CG residual r -= alpha y is updated in place (alpha of the
+// point's rhs from the solver's device scalars; nothing happens where alpha = 0)
+// and ||r||^2 is reduced.  One-point-per-thread kernels only (rpt = 1).
+enum : int { EPI_XPAY = 1, EPI_NORM = 2, EPI_CGR = 4 };
 
 struct HopArgs {
     Geom g;
@@ -25,6 +29,9 @@ struct HopArgs {
     int swizzle;          // map consecutive blocks to the same XCD
     int tchunk;           // processing order (see LaunchCfg)
     int chunk_sites;      // sites of a full chunk: tchunk * Lz * (Lx/2) * Ly
+    void *r[2];           // EPI_CGR: the residual field of parity 0 / 1 (same storage as out)
+    const char *alpha;    // EPI_CGR: alpha of rhs k at alpha + k * alpha_stride (a double)
+    long alpha_stride;
 };
 
 struct LaunchCfg {

@@ -37,6 +37,9 @@ static hipError_t launch_epi(int epi, int tps, HopArgs &a, dim3 grid, dim3 block
     case EPI_XPAY | EPI_NORM:
         launch_one<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM, NT>(tps, grid, block, s, a);
         break;
+    case EPI_XPAY | EPI_NORM | EPI_CGR:
+        launch_one<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM | EPI_CGR, NT>(tps, grid, block, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -148,7 +151,7 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
     a.swizzle = cfg.swizzle;
     set_processing_order(a, cfg.tchunk);
     const int rpt = effective_rpt(cfg, a.nrhs, tps);
-    if (rpt > 1 && (a.nrhs > 256 || block < 64)) return hipErrorInvalidValue;
+    if (rpt > 1 && (a.nrhs > 256 || block < 64 || (epi & EPI_CGR))) return hipErrorInvalidValue;
     dim3 grid((unsigned)hop_launch_blocks(tps, cfg, a.npts, a.nrhs), (unsigned)nparity);
     dim3 blk(block);
     const bool nt = use_nontemporal(prec, cfg, a, nparity, epi);

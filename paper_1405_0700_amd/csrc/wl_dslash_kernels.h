@@ -345,6 +345,21 @@ __device__ __forceinline__ double hop_point(const HopArgs &a, int par, long gid)
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = b * acc[k];
     }
+    if constexpr (EPI & EPI_CGR) {
+        // r -= alpha y in place, ||r||^2 (y itself is not stored)
+        const double alpha = *(const double *)(a.alpha + (long)rhs * a.alpha_stride);
+        if (alpha == 0.0) return nrm;
+        cpx<T> rv[12];
+        SpinorIO<SP>::load(a.r[par], pt, rv);
+        const T al = (T)alpha;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) rv[k] = {fma(-al, acc[k].re, rv[k].re), fma(-al, acc[k].im, rv[k].im)};
+        SpinorIO<SP>::store(a.r[par], pt, rv);
+        if constexpr (SP != WL_F64) SpinorIO<SP>::load(a.r[par], pt, rv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nrm += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
+        return nrm;
+    }
     SpinorIO<SP>::template store<NT>(a.out[par], pt, acc);
     if constexpr (EPI & EPI_NORM) {
         if constexpr (SP == WL_F64) {
@@ -526,11 +541,29 @@ __device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, lon
             for (int k = 0; k < 6; ++k) res[k] = b * res[k];
         }
     }
-    if constexpr (SP == WL_F64 || SP == WL_F32) {
+    // what is stored where: y = res in out, or (EPI_CGR) r - alpha y in r
+    void *dst = a.out[par];
+    bool doit = active;
+    constexpr bool NTS = NT && !(EPI & EPI_CGR);  // the residual is read again at once
+    if constexpr (EPI & EPI_CGR) {
+        dst = a.r[par];
         if (active) {
-            SpinorIO<SP>::template store_half<NT>(a.out[par], pt, hf, res);
+            const double alpha = *(const double *)(a.alpha + (long)(gid % a.nrhs) * a.alpha_stride);
+            doit = alpha != 0.0;
+            if (doit) {
+                cpx<T> rv[6];
+                SpinorIO<SP>::load_half(a.r[par], pt, hf, rv);
+                const T al = (T)alpha;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) res[k] = {fma(-al, res[k].re, rv[k].re), fma(-al, res[k].im, rv[k].im)};
+            }
+        }
+    }
+    if constexpr (SP == WL_F64 || SP == WL_F32) {
+        if (doit) {
+            SpinorIO<SP>::template store_half<NTS>(dst, pt, hf, res);
             if constexpr (EPI & EPI_NORM) {
-                if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(a.out[par], pt, hf, res);
+                if constexpr (SP != WL_F64) SpinorIO<SP>::load_half(dst, pt, hf, res);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;
             }
@@ -538,12 +571,12 @@ __device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, lon
     } else {
         // 16-bit storage: one norm per point, the largest component of both halves
         float m = 0.f;
-        if (active)
+        if (doit)
 #pragma unroll
             for (int k = 0; k < 6; ++k) m = fmaxf(m, fmaxf(fabsf(res[k].re), fabsf(res[k].im)));
         m = fmaxf(m, __shfl_xor(m, 32, 64));
-        if (active) {
-            SpinorIO<SP>::template store_half_shared<NT>(a.out[par], pt, hf, res, m);
+        if (doit) {
+            SpinorIO<SP>::template store_half_shared<NTS>(dst, pt, hf, res, m);
             if constexpr (EPI & EPI_NORM) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) nrm += (double)res[k].re * res[k].re + (double)res[k].im * res[k].im;

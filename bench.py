@@ -161,7 +161,7 @@ def main():
                     help="only run a plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); %d requested" % args.gpus, file=sys.stderr)
+        print("bench.py: this benchmark runs on exactly one GPU (--gpus 1); %d requested" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -244,7 +244,10 @@ class EoSolver:
         return ev0.elapsed_time(ev1) / steps, infos
 
 
-MIXED = [("f32_18", 1, 18), ("f32_12", 1, 12), ("f16n_12", 2, 12), ("bf16n_12", 3, 12), ("i16n_12", 4, 12)]
+# the same solve with other storage: FP64 with 12-real links (the third row rebuilt, exact up to rounding), then
+# reduced-precision inner storage with FP64 reliable updates
+MIXED = [("f64_12", 0, 12), ("f32_18", 1, 18), ("f32_12", 1, 12), ("f16n_12", 2, 12), ("bf16n_12", 3, 12),
+         ("i16n_12", 4, 12)]
 
 
 def run_eo_cg(args):

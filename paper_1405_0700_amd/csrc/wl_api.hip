@@ -517,6 +517,21 @@ static wl_status fill_hop_args(wl_ctx *c, int prec, int recon, void *out, const 
     return WL_OK;
 }
 
+// EPI_CGR: the residual r (the output's subset and storage) updated in place with
+// alpha of rhs k read from sc[k]
+static void set_cg_residual(const wl_ctx *c, int prec, int nrhs, int out_subset, void *cg_r, const CGScalars *cg_sc,
+                            HopArgs &h) {
+    const size_t hb = half_bytes(c, prec, nrhs);
+    if (out_subset == WL_FULL) {
+        h.r[0] = cg_r;
+        h.r[1] = (char *)cg_r + hb;
+    } else {
+        h.r[out_subset] = cg_r;
+    }
+    h.alpha = (const char *)cg_sc + offsetof(CGScalars, alpha);
+    h.alpha_stride = sizeof(CGScalars);
+}
+
 static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, void *out, const void *in,
                           const void *x, int out_subset, int nrhs, double a, double b, double *partials,
                           long part_stride, const int *flag, hipStream_t s, long *nblk_out = nullptr,
@@ -527,18 +542,7 @@ static wl_status hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, voi
     wl_status st = fill_hop_args(c, prec, recon, out, in, x, out_subset, nrhs, a, b, partials, part_stride, flag, h,
                                  &np, tm_x, tm_h);
     if (st) return st;
-    if (epi & EPI_CGR) {
-        // the residual has the output's subset and storage
-        const size_t hb = half_bytes(c, prec, nrhs);
-        if (out_subset == WL_FULL) {
-            h.r[0] = cg_r;
-            h.r[1] = (char *)cg_r + hb;
-        } else {
-            h.r[out_subset] = cg_r;
-        }
-        h.alpha = (const char *)cg_sc + offsetof(CGScalars, alpha);
-        h.alpha_stride = sizeof(CGScalars);
-    }
+    if (epi & EPI_CGR) set_cg_residual(c, prec, nrhs, out_subset, cg_r, cg_sc, h);
     hipEvent_t *ev = nullptr;
     if (c->timing && !c->capturing && c->timed.size() < (1u << 16) && c->timing_seq++ % c->timing_stride == 0) {
         if (c->pool_used + 2 > c->event_pool.size()) {
@@ -1414,13 +1418,17 @@ extern "C" wl_status wl_batch_timing_read(wl_batch *B, int *count, double *total
 // even hop with the epilogue).  With partials, ||out_k||^2 partials per rhs go
 // to partials[k] (stride[k]) and nblk[k] receives their count.  flags[k]: the
 // active count of system k's solver (tiles of a system whose count is 0 are
-// skipped), or null.
+// skipped), or null.  With cg_sc (dag, partials set): the last stage does not store
+// M_k^+ in_k but updates out_k = r_k -= alpha_k M_k^+ in_k in place, alpha_k per rhs
+// from cg_sc[k], and the partials are those of ||r_k||^2.
 static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa, int prec, int recon, int nrhs,
                              void *const *out, const void *const *in, void *const *tmp, double *const *partials,
-                             const long *stride, int *const *flags, long *nblk, hipStream_t s, double mu = 0.0) {
+                             const long *stride, int *const *flags, long *nblk, hipStream_t s, double mu = 0.0,
+                             const CGScalars *const *cg_sc = nullptr) {
     const int n = (int)B->ctx.size();
     const int nst = op == WL_OP_D ? 1 : 2;
     const int tps = (prec == WL_F64 || prec == WL_F32) && B->tps == 2 ? 2 : 1;
+    if (cg_sc && (!dag || !partials)) return fail(WL_ERR_ARG, "the residual update needs M^+ and norm partials");
     for (int stage = 0; stage < nst; ++stage) {
         BatchArgs A;
         std::memset(&A, 0, sizeof A);
@@ -1429,7 +1437,7 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
         long tiles = 0;
         double ws = 0.0;
         const bool last = stage == nst - 1;
-        const int epi = last ? (EPI_XPAY | (partials ? EPI_NORM : 0)) : 0;
+        const int epi = last ? (EPI_XPAY | (partials ? EPI_NORM : 0) | (cg_sc ? EPI_CGR : 0)) : 0;
         for (int k = 0; k < n; ++k) {
             wl_ctx *c = B->ctx[k];
             HopArgs &h = A.sys[k];
@@ -1450,6 +1458,7 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
                 st = fill_hop_args(c, prec, recon, out[k], tmp[k], in[k], WL_EVEN, nrhs, 1.0, -kappa[k] * kappa[k], pk,
                                    sk, flag, h, &np, nu, 0.0);
             if (st) return st;
+            if (epi & EPI_CGR) set_cg_residual(c, prec, nrhs, op == WL_OP_D ? WL_FULL : WL_EVEN, out[k], cg_sc[k], h);
             A.per_par[k] = hop_blocks(h.npts, B->block, tps);
             A.start[k] = tiles;
             tiles += A.per_par[k] * np;
@@ -1543,6 +1552,33 @@ static wl_status batch_iteration(wl_batch *B, std::vector<CGRun> &R, const std::
     if (st) return st;
     for (int k = 0; k < n; ++k)
         HIP_TRY(cg_alpha(R[k].sc, R[k].nrhs, R[k].partials, R[k].stride, nblk[k], R[k].done, R[k].s));
+    bool fused = true;
+    for (int k = 0; k < n; ++k) fused = fused && !ru[k];
+    if (fused) {
+        // as in the single-system iteration: the last stage updates r_k in place
+        // (r -= alpha A p, ||r||^2), then beta and x += alpha p, p = r + beta p
+        std::vector<void *> r(n);
+        std::vector<const CGScalars *> sc(n);
+        for (int k = 0; k < n; ++k) {
+            r[k] = R[k].r;
+            sc[k] = R[k].sc;
+        }
+        st = batch_apply(B, R0.op, true, kap.data(), R0.prec, R0.recon, R0.nrhs, r.data(),
+                         (const void *const *)q.data(), tmp.data(), part.data(), stride.data(), flags.data(),
+                         nblk.data(), R0.s, R0.mu, sc.data());
+        if (st) return st;
+        for (int k = 0; k < n; ++k) {
+            HIP_TRY(cg_beta(R[k].sc, R[k].nrhs, R[k].partials, R[k].stride, nblk[k], R[k].done, 0, R[k].s));
+            VecArgs u = vec_args(R[k].c, R[k].prec, R[k].nrhs);
+            set_vec(u, 0, R[k].x, R[k].hb_hi);
+            set_vec(u, 1, R[k].p, R[k].hb_lo);
+            set_vec(u, 2, R[k].r, R[k].hb_lo);
+            u.sc = R[k].sc;
+            u.flag = nullptr;  // must also run after the system's final step
+            HIP_TRY(cg_update_xp(R[k].prec, u, R[k].nh, R[k].s));
+        }
+        return WL_OK;
+    }
     st = batch_apply(B, R0.op, true, kap.data(), R0.prec, R0.recon, R0.nrhs, sv.data(), (const void *const *)q.data(),
                      tmp.data(), nullptr, nullptr, flags.data(), nullptr, R0.s, R0.mu);
     if (st) return st;

@@ -71,20 +71,24 @@ int effective_tps(int prec, const LaunchCfg &cfg) {
 template <int SP, int GP, int RECON, int TPS>
 static hipError_t launch_batch_tt(bool dag, bool nt, int epi, const BatchArgs &B, dim3 grid, dim3 blk, hipStream_t s) {
 #define WL_BATCH_CASE(D, E, N) hipLaunchKernelGGL((hop_batch_kernel<SP, GP, RECON, D, E, N, TPS>), grid, blk, 0, s, B)
-    const int key = (dag ? 4 : 0) | (nt ? 8 : 0) | epi;
+    // epilogue bits 0-2, then dagger, then non-temporal stores
+    constexpr int DG = 8, NS = 16, CGR = EPI_XPAY | EPI_NORM | EPI_CGR;
+    const int key = (dag ? DG : 0) | (nt ? NS : 0) | epi;
     switch (key) {
     case 0: WL_BATCH_CASE(false, 0, false); break;
     case EPI_XPAY: WL_BATCH_CASE(false, EPI_XPAY, false); break;
     case EPI_XPAY | EPI_NORM: WL_BATCH_CASE(false, EPI_XPAY | EPI_NORM, false); break;
-    case 4: WL_BATCH_CASE(true, 0, false); break;
-    case 4 | EPI_XPAY: WL_BATCH_CASE(true, EPI_XPAY, false); break;
-    case 4 | EPI_XPAY | EPI_NORM: WL_BATCH_CASE(true, EPI_XPAY | EPI_NORM, false); break;
-    case 8: WL_BATCH_CASE(false, 0, true); break;
-    case 8 | EPI_XPAY: WL_BATCH_CASE(false, EPI_XPAY, true); break;
-    case 8 | EPI_XPAY | EPI_NORM: WL_BATCH_CASE(false, EPI_XPAY | EPI_NORM, true); break;
-    case 12: WL_BATCH_CASE(true, 0, true); break;
-    case 12 | EPI_XPAY: WL_BATCH_CASE(true, EPI_XPAY, true); break;
-    case 12 | EPI_XPAY | EPI_NORM: WL_BATCH_CASE(true, EPI_XPAY | EPI_NORM, true); break;
+    case DG: WL_BATCH_CASE(true, 0, false); break;
+    case DG | EPI_XPAY: WL_BATCH_CASE(true, EPI_XPAY, false); break;
+    case DG | EPI_XPAY | EPI_NORM: WL_BATCH_CASE(true, EPI_XPAY | EPI_NORM, false); break;
+    case DG | CGR: WL_BATCH_CASE(true, CGR, false); break;
+    case NS: WL_BATCH_CASE(false, 0, true); break;
+    case NS | EPI_XPAY: WL_BATCH_CASE(false, EPI_XPAY, true); break;
+    case NS | EPI_XPAY | EPI_NORM: WL_BATCH_CASE(false, EPI_XPAY | EPI_NORM, true); break;
+    case NS | DG: WL_BATCH_CASE(true, 0, true); break;
+    case NS | DG | EPI_XPAY: WL_BATCH_CASE(true, EPI_XPAY, true); break;
+    case NS | DG | EPI_XPAY | EPI_NORM: WL_BATCH_CASE(true, EPI_XPAY | EPI_NORM, true); break;
+    case NS | DG | CGR: WL_BATCH_CASE(true, CGR, true); break;
     default: return hipErrorInvalidValue;
     }
 #undef WL_BATCH_CASE

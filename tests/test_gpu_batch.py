@@ -110,8 +110,9 @@ def test_batch_launch_shape_does_not_change_results_and_counters_reset(batch):
             assert torch.equal(res[k], results[0][k])
 
 
-@pytest.mark.parametrize("use_graph", [0, 1])
-def test_batch_cg_mixed_precision_solves_every_system(batch, use_graph):
+@pytest.mark.parametrize("prec,recon,use_graph", [(W.WL_F32, 18, 0), (W.WL_F32, 18, 1), (W.WL_F64, 18, 1),
+                                                   (W.WL_F64, 12, 0), (W.WL_F16N, 12, 1), (W.WL_BF16N, 12, 0)])
+def test_batch_cg_mixed_precision_solves_every_system(batch, prec, recon, use_graph):
     b, lats, gauges = batch
     nrhs = 4
     kappas = [s[3] for s in SYSTEMS]
@@ -126,7 +127,7 @@ def test_batch_cg_mixed_precision_solves_every_system(batch, use_graph):
         rhs.append(lat.pack(rhs_c, W.WL_EVEN, W.WL_F64, nrhs))
         xs.append(lat.new(W.WL_EVEN, W.WL_F64, nrhs))
     p = W.wl_solver_params_default()
-    p.prec, p.recon, p.use_graph, p.tol = W.WL_F32, 18, use_graph, 1e-10
+    p.prec, p.recon, p.use_graph, p.tol = prec, recon, use_graph, 1e-10
     st, info = W.wl_batch_cg_solve(b, xs, rhs, W.WL_OP_DHAT, kappas, nrhs, p)
     assert st == W.WL_OK
     for k, (lat, u, (dims, _, _, kappa)) in enumerate(zip(lats, gauges, SYSTEMS)):
@@ -134,6 +135,33 @@ def test_batch_cg_mixed_precision_solves_every_system(batch, use_graph):
         for r in range(nrhs):
             a = orc.schur(orc.schur(x[r], u, kappa, AP), u, kappa, AP, dagger=True)
             assert rel(a, bhats[k][r]) <= 1.05e-10, (k, r)
+            assert info[k][r]["true_rel_resid"] <= 1e-10 and info[k][r]["iters"] > 0
+    print("iterations per system:", [[i["iters"] for i in s] for s in info])
+
+
+@pytest.mark.parametrize("prec", [W.WL_F64, W.WL_F32])
+def test_batch_cg_full_operator_solves_every_system(batch, prec):
+    # M = D on the whole lattice: the fused residual update covers both parities
+    b, lats, gauges = batch
+    nrhs = 2
+    kappas = [s[3] for s in SYSTEMS]
+    xs, rhs, want = [], [], []
+    for lat, u, (dims, _, seed, kappa) in zip(lats, gauges, SYSTEMS):
+        etas = [synth.gaussian_spinor(dims, seed=seed * 11 + r) for r in range(nrhs)]
+        rhs_c = np.stack([orc.dirac(e, u, kappa, AP, dagger=True).reshape(-1, 4, 3) for e in etas])
+        want.append(rhs_c)
+        rhs.append(lat.pack(rhs_c, W.WL_FULL, W.WL_F64, nrhs))
+        xs.append(lat.new(W.WL_FULL, W.WL_F64, nrhs))
+    p = W.wl_solver_params_default()
+    p.prec, p.tol = prec, 1e-10
+    st, info = W.wl_batch_cg_solve(b, xs, rhs, W.WL_OP_D, kappas, nrhs, p)
+    assert st == W.WL_OK
+    for k, (lat, u, (dims, _, _, kappa)) in enumerate(zip(lats, gauges, SYSTEMS)):
+        x = lat.unpack(xs[k], W.WL_FULL, W.WL_F64, nrhs)
+        for r in range(nrhs):
+            xr = x[r].reshape(dims[::-1] + (4, 3))
+            a = orc.dirac(orc.dirac(xr, u, kappa, AP), u, kappa, AP, dagger=True)
+            assert rel(a.reshape(-1, 4, 3), want[k][r]) <= 1.05e-10, (k, r)
             assert info[k][r]["true_rel_resid"] <= 1e-10 and info[k][r]["iters"] > 0
     print("iterations per system:", [[i["iters"] for i in s] for s in info])
 

@@ -110,10 +110,22 @@ def test_batch_launch_shape_does_not_change_results_and_counters_reset(batch):
             assert torch.equal(res[k], results[0][k])
 
 
-@pytest.mark.parametrize("prec,recon,use_graph", [(W.WL_F32, 18, 0), (W.WL_F32, 18, 1), (W.WL_F64, 18, 1),
-                                                   (W.WL_F64, 12, 0), (W.WL_F16N, 12, 1), (W.WL_BF16N, 12, 0)])
-def test_batch_cg_mixed_precision_solves_every_system(batch, prec, recon, use_graph):
+@pytest.mark.parametrize("prec,recon,use_graph,nt,tps", [
+    (W.WL_F32, 18, 0, -1, 1), (W.WL_F32, 18, 1, -1, 1), (W.WL_F64, 18, 1, -1, 1), (W.WL_F64, 12, 0, -1, 1),
+    (W.WL_F16N, 12, 1, -1, 1), (W.WL_BF16N, 12, 0, -1, 1),
+    # non-temporal stores and two threads per point, as chosen for large lattices
+    (W.WL_F32, 18, 1, 1, 2), (W.WL_F64, 18, 0, 1, 2), (W.WL_F16N, 12, 0, 1, 1)])
+def test_batch_cg_mixed_precision_solves_every_system(batch, prec, recon, use_graph, nt, tps):
     b, lats, gauges = batch
+    saved = W.wl_batch_get_launch(b)
+    W.wl_batch_set_launch(b, saved[0], saved[1], nt, tps)
+    try:
+        _batch_cg_case(b, lats, gauges, prec, recon, use_graph)
+    finally:
+        W.wl_batch_set_launch(b, *saved)
+
+
+def _batch_cg_case(b, lats, gauges, prec, recon, use_graph):
     nrhs = 4
     kappas = [s[3] for s in SYSTEMS]
     xs, rhs, bhats = [], [], []

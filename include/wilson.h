@@ -469,13 +469,15 @@ wl_status wl_batch_timing_read(wl_batch *batch, int *count, double *total_ms);
  * both parities, on scratch fields the call allocates and frees) for every
  * launch shape of the sweep -- block 64/128/256, one or two threads per point
  * (FP64/FP32 storage) or 2-4 right-hand sides per thread (when nrhs allows),
- * XCD swizzle off/on, processing order by e/o index or by chunks of 2 or 4
- * time slices, non-temporal hints off/on -- with HIP
+ * XCD swizzle off/on, processing order by e/o index, by chunks of 4 time
+ * slices or by z-ranges (WL_TCHUNK_AUTO), non-temporal hints off/on -- with HIP
  * events (average of 5 launches after a warm-up), picks the fastest and makes
  * it the context's launch configuration for `prec`.  Results are cached in
  * the process and, if cache_path is not NULL, appended to that text file
  * (one line per key: GPU architecture, extents, prec, recon, nrhs); a later
  * call with a cached key applies the entry without timing (*from_cache = 1).
+ * A file entry that is not a valid launch shape (as wl_ctx_set_launch would
+ * reject it) is ignored and the key tuned again; so are unreadable lines.
  * chosen, best_us (microseconds per launch) and from_cache may be NULL.
  * Synchronous. */
 wl_status wl_autotune(wl_ctx *ctx, wl_prec prec, int recon, int nrhs, const char *cache_path, wl_launch *chosen,
@@ -483,7 +485,8 @@ wl_status wl_autotune(wl_ctx *ctx, wl_prec prec, int recon, int nrhs, const char
 /* The same for a batch: persistent workgroups (1..8 per compute unit, scaled
  * by 256 / block), threads per tile 64/128/256, non-temporal hints and one or
  * two threads per point, timed on the persistent launch of D over every
- * system; the result becomes the batch's launch configuration. */
+ * system; the result becomes the batch's launch configuration.  Cache entries
+ * that wl_batch_set_launch would reject are ignored. */
 wl_status wl_batch_autotune(wl_batch *batch, wl_prec prec, int recon, int nrhs, const char *cache_path,
                             int *workgroups, int *block, int *nt, int *tps, double *best_us, int *from_cache);
 

@@ -272,12 +272,14 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
         (void)hipGetLastError();
         return fail(WL_ERR_HIP, "no HIP device available (%s)", hipGetErrorString(e));
     }
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
     wl_ctx *c = new wl_ctx();
     std::memcpy(c->dims, dims, sizeof c->dims);
     std::memcpy(c->phases, phases, sizeof c->phases);
     c->V = V;
     c->Vh = V / 2;
-    HIP_TRY(hipGetDevice(&c->device));
+    c->device = device;
     Geom &g = c->g;
     for (int m = 0; m < 4; ++m) g.L[m] = dims[m];
     g.lxh = dims[0] / 2;
@@ -1363,14 +1365,30 @@ extern "C" wl_status wl_batch_destroy(wl_batch *B) {
     return WL_OK;
 }
 
+// why a launch shape is not accepted, or null (also applied to autotuner cache entries)
+static const char *launch_problem(int block, int tps, int nt, int rpt) {
+    if (block < 64 || block > 256 || block % 64) return "block not in {64, 128, 192, 256}";
+    if (tps != 1 && tps != 2) return "tps not in {1, 2}";
+    if (nt < -1 || nt > 1) return "nt not in {-1, 0, 1}";
+    if (rpt < 1 || rpt > 4) return "rpt not in 1..4";
+    if (rpt > 1 && tps != 1) return "rpt > 1 needs tps = 1";
+    return nullptr;
+}
+
+static const char *batch_launch_problem(int workgroups, int block, int nt, int tps) {
+    if (workgroups < 8 || workgroups % 8 || workgroups > 65536) return "workgroups not a multiple of 8 in 8..65536";
+    if (block < 64 || block > 256 || block % 64) return "block not in {64, 128, 192, 256}";
+    if (nt < -1 || nt > 1) return "nt not in {-1, 0, 1}";
+    if (tps != 1 && tps != 2) return "tps not in {1, 2}";
+    return nullptr;
+}
+
 extern "C" wl_status wl_batch_set_launch(wl_batch *B, int workgroups, int block, int nt, int tps) {
     g_err.clear();
     if (!B) return fail(WL_ERR_ARG, "null batch");
-    if (workgroups < 8 || workgroups % 8 || workgroups > 65536)
-        return fail(WL_ERR_ARG, "workgroups %d: a multiple of 8 in 8..65536", workgroups);
-    if (block < 64 || block > 256 || block % 64) return fail(WL_ERR_ARG, "block %d not in {64, 128, 192, 256}", block);
-    if (nt < -1 || nt > 1) return fail(WL_ERR_ARG, "nt %d not in {-1, 0, 1}", nt);
-    if (tps != 1 && tps != 2) return fail(WL_ERR_ARG, "tps %d not in {1, 2}", tps);
+    if (const char *why = batch_launch_problem(workgroups, block, nt, tps))
+        return fail(WL_ERR_ARG, "batch launch (workgroups %d, block %d, nt %d, tps %d): %s", workgroups, block, nt,
+                    tps, why);
     B->nwg = workgroups;
     B->block = block;
     B->nt = nt;
@@ -1908,7 +1926,9 @@ extern "C" wl_status wl_autotune(wl_ctx *c, wl_prec prec, int recon, int nrhs, c
     LaunchCfg best;
     double best_t = 0.0;
     int cached = 0;
-    if (cache_lookup(key, cache_path, vals) && vals.size() >= 7) {
+    // a cache entry that is not a valid launch shape is ignored (and tuned again)
+    if (cache_lookup(key, cache_path, vals) && vals.size() >= 7 &&
+        !launch_problem((int)vals[0], (int)vals[2], (int)vals[4], (int)vals[5])) {
         best.block = (int)vals[0];
         best.swizzle = (int)vals[1];
         best.tps = (int)vals[2];
@@ -1921,8 +1941,14 @@ extern "C" wl_status wl_autotune(wl_ctx *c, wl_prec prec, int recon, int nrhs, c
         // the solvers' launch: out = x - kappa H in over both parities, on scratch fields
         const size_t full = 2 * half_bytes(c, prec, nrhs);
         void *buf = nullptr;
-        HIP_TRY(hipMalloc(&buf, 3 * full));
-        HIP_TRY(hipMemset(buf, 0, 3 * full));
+        if (hipMalloc(&buf, 3 * full) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(WL_ERR_NOMEM, "autotune scratch of %zu bytes", 3 * full);
+        }
+        if (hipMemset(buf, 0, 3 * full) != hipSuccess) {
+            (void)hipFree(buf);
+            return fail(WL_ERR_HIP, "autotune scratch clear failed");
+        }
         char *in = (char *)buf, *out = in + full, *x = out + full;
         const LaunchCfg saved = c->cfg[prec];
         const bool saved_timing = c->timing;
@@ -1935,6 +1961,7 @@ extern "C" wl_status wl_autotune(wl_ctx *c, wl_prec prec, int recon, int nrhs, c
                 for (int swz : {0, 1})
                     for (int tch : {0, 4, WL_TCHUNK_AUTO})
                         for (int nt : {0, 1}) {
+                            if (st) break;  // the first failure ends the sweep
                             if (tps == 2 && !two) continue;
                             if (rpt > 1 && (tps != 1 || nrhs % rpt)) continue;
                             if (tch > 0 && tch >= c->dims[3]) continue;
@@ -1998,7 +2025,8 @@ extern "C" wl_status wl_batch_autotune(wl_batch *B, wl_prec prec, int recon, int
     std::vector<double> vals;
     int bw = B->nwg, bb = B->block, bn = B->nt, bt = B->tps, cached = 0;
     double best_t = 0.0;
-    if (cache_lookup(key, cache_path, vals) && vals.size() >= 5) {
+    if (cache_lookup(key, cache_path, vals) && vals.size() >= 5 &&
+        !batch_launch_problem((int)vals[0], (int)vals[1], (int)vals[2], (int)vals[3])) {
         bw = (int)vals[0];
         bb = (int)vals[1];
         bn = (int)vals[2];
@@ -2781,12 +2809,8 @@ extern "C" wl_status wl_ctx_set_launch(wl_ctx *c, wl_prec prec, const wl_launch 
     g_err.clear();
     if (!c || !l) return fail(WL_ERR_ARG, "null argument");
     if (!prec_ok(prec)) return fail(WL_ERR_ARG, "bad precision %d", (int)prec);
-    if (l->block < 64 || l->block > 256 || l->block % 64)
-        return fail(WL_ERR_ARG, "block %d not in {64, 128, 192, 256}", l->block);
-    if (l->tps != 1 && l->tps != 2) return fail(WL_ERR_ARG, "tps %d not in {1, 2}", l->tps);
-    if (l->nt < -1 || l->nt > 1) return fail(WL_ERR_ARG, "nt %d not in {-1, 0, 1}", l->nt);
-    if (l->rpt < 1 || l->rpt > 4) return fail(WL_ERR_ARG, "rpt %d not in 1..4", l->rpt);
-    if (l->rpt > 1 && l->tps != 1) return fail(WL_ERR_ARG, "rpt > 1 needs tps = 1");
+    if (const char *why = launch_problem(l->block, l->tps, l->nt, l->rpt))
+        return fail(WL_ERR_ARG, "launch (block %d, tps %d, nt %d, rpt %d): %s", l->block, l->tps, l->nt, l->rpt, why);
     LaunchCfg &g = c->cfg[prec];
     g.block = l->block;
     g.swizzle = l->swizzle ? 1 : 0;
@@ -2844,13 +2868,15 @@ extern "C" wl_status wl_ptc_create(int channels, const double *w1, const double 
         wl_ptc_destroy(n);
         return fail(WL_ERR_NOMEM, "hipMalloc of PTC weights failed: %s", hipGetErrorString(e));
     }
-    HIP_TRY(hipMemcpy(n->w, host.data(), nr * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(n->grad, 0, nr * sizeof(double)));
-    HIP_TRY(hipMemset(n->m, 0, nr * sizeof(float)));
-    HIP_TRY(hipMemset(n->v, 0, nr * sizeof(float)));
-    HIP_TRY(hipMemset(n->loss, 0, sizeof(double)));
-    HIP_TRY(launch_to_bf16(n->w, n->wb, nr, 0));
-    HIP_TRY(hipDeviceSynchronize());
+    if ((e = hipMemcpy(n->w, host.data(), nr * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(n->grad, 0, nr * sizeof(double))) != hipSuccess ||
+        (e = hipMemset(n->m, 0, nr * sizeof(float))) != hipSuccess ||
+        (e = hipMemset(n->v, 0, nr * sizeof(float))) != hipSuccess ||
+        (e = hipMemset(n->loss, 0, sizeof(double))) != hipSuccess || (e = launch_to_bf16(n->w, n->wb, nr, 0)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        wl_ptc_destroy(n);
+        return fail(WL_ERR_HIP, "PTC weight initialisation failed: %s", hipGetErrorString(e));
+    }
     *out = n;
     return WL_OK;
 }

@@ -241,6 +241,12 @@ def test_autotune_picks_a_valid_launch_and_caches_it(tmp_path):
         f.write("%s | 64 0 1 0 0 3 12.5\n" % key)
     cfg3, us3, cached3 = W.wl_autotune(lat.ctx, W.WL_F32, 18, 3, cache)
     assert cached3 and cfg3 == (64, 0, 1, 0, 0, 3) and us3 == 12.5
+    # an entry that is not a valid launch shape (block 1000) is ignored and the shape tuned again
+    with open(cache, "a") as f:
+        f.write("%s | 1000 0 1 0 0 1 1.0\n" % key.replace("nrhs 3", "nrhs 2"))
+    cfg4, us4, cached4 = W.wl_autotune(lat.ctx, W.WL_F32, 18, 2, cache)
+    assert not cached4 and cfg4[0] in (64, 128, 256) and us4 > 0
+    assert W.wl_ctx_get_launch(lat.ctx, W.WL_F32) == cfg4
     lat.close()
 
 
@@ -252,4 +258,10 @@ def test_batch_autotune(batch, tmp_path):
     assert W.wl_batch_get_launch(b) == (wg, blk, nt, tps)
     again = W.wl_batch_autotune(b, W.WL_F32, 18, 2, tmp_path / "b.txt")
     assert again[2] and again[0] == (wg, blk, nt, tps)
+    # an invalid cache entry (12 workgroups: not a multiple of 8) is ignored and the batch tuned again
+    key = (tmp_path / "b.txt").read_text().strip().splitlines()[-1].split(" | ")[0].replace("nrhs 2", "nrhs 1")
+    with open(tmp_path / "b.txt", "a") as f:
+        f.write("%s | 12 256 0 1 1.0\n" % key)
+    (wg5, blk5, nt5, tps5), us5, cached5 = W.wl_batch_autotune(b, W.WL_F32, 18, 1, tmp_path / "b.txt")
+    assert not cached5 and wg5 % 8 == 0 and us5 > 0
     W.wl_batch_set_launch(b, *before)

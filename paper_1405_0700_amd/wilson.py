@@ -210,10 +210,17 @@ def _check(status):
 
 
 def _ptr(x):
+    """Device address of a field argument: a raw int is passed through, a torch
+    tensor must live on the GPU and be contiguous (a host address or a strided
+    view would be read by the kernels as device memory of the documented layout)."""
     if x is None:
         return None
     if isinstance(x, int):
         return x
+    if not getattr(x, "is_cuda", False):
+        raise ValueError("field arguments must be device tensors (got %s)" % getattr(x, "device", type(x).__name__))
+    if not x.is_contiguous():
+        raise ValueError("field arguments must be contiguous tensors")
     return x.data_ptr()
 
 

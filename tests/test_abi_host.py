@@ -77,3 +77,15 @@ def test_no_device_is_an_error_not_a_crash():
     assert st == W.WL_ERR_HIP
     assert out.value is None
     assert "device" in W.last_error()
+
+
+def test_binding_rejects_host_and_strided_tensors():
+    # the binding checks field tensors before any library call: a host address or a
+    # strided view would be read by the kernels as device memory of the field layout
+    import torch
+    host = torch.zeros(64, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="device"):
+        W.wl_dslash_apply(None, host, host, W.WL_EVEN)
+    with pytest.raises(ValueError, match="device"):
+        W.wl_cg_solve(None, host, host, W.WL_OP_DHAT, 0.1)
+    assert W._ptr(None) is None and W._ptr(4096) == 4096

@@ -50,6 +50,7 @@ enum Slot {
     S_TMP_OP = 0,  // odd temporary of wl_dirac_apply
     S_R, S_P, S_Q, S_S, S_TMP,           // solver fields in the inner precision
     S_RHI, S_THI, S_TMPHI,               // FP64 fields for true residuals
+    S_XLO,                               // FP32 accumulator of x steps between refreshes (mixed precision)
     S_PARTIALS, S_SCAL, S_BNORM, S_FLAG,
     S_PTC_H, S_PTC_GH, S_PTC_O, S_PTC_GO, S_PTC_PART, S_PTC_E2,       // PTC workspace
     S_GCR_R, S_GCR_X, S_GCR_Z, S_GCR_W, S_GCR_TMP, S_GCR_RHS,          // FGCR workspace
@@ -890,6 +891,10 @@ struct CGRun {
     hipStream_t s;
     size_t hb_lo, hb_hi;
     void *x, *r, *p, *q, *sv, *tmp;  // inner precision (x is FP64)
+    // mixed precision: the fused iterations add alpha p to this FP32 field, which
+    // true_residual folds into x (the only reader of x) before it uses x
+    void *xlo;
+    size_t hb_xlo;
     const void *b;
     void *rhi, *thi, *tmphi;
     double *partials;
@@ -903,9 +908,24 @@ struct CGRun {
 };
 }  // namespace
 
+// x += x_lo, x_lo = 0 (mixed precision; every read of x follows this)
+static wl_status fold_x(CGRun &R) {
+    if (!R.xlo) return WL_OK;
+    VecArgs v = vec_args(R.c, WL_F32, R.nrhs);
+    set_vec(v, 0, R.xlo, R.hb_xlo);
+    set_vec(v, 1, R.x, R.hb_hi);
+    HIP_TRY(blas_convert(WL_F64, WL_F32, true, v, R.nh, R.s));
+    VecArgs z = vec_args(R.c, WL_F32, R.nrhs);
+    set_vec(z, 0, R.xlo, R.hb_xlo);
+    HIP_TRY(blas_zero(WL_F32, z, R.nh, R.s));
+    return WL_OK;
+}
+
 // t = A x = M^+ M x in FP64; r_hi = b - t; partials of ||r_hi||^2
 static wl_status true_residual(CGRun &R) {
-    wl_status st = apply_m(R.c, R.op, false, R.kappa, WL_F64, 18, R.nrhs, R.thi, R.x, R.tmphi, nullptr, 0, nullptr,
+    wl_status st = fold_x(R);
+    if (st) return st;
+    st = apply_m(R.c, R.op, false, R.kappa, WL_F64, 18, R.nrhs, R.thi, R.x, R.tmphi, nullptr, 0, nullptr,
                            R.s, nullptr, R.mu);
     if (st) return st;
     st = apply_m(R.c, R.op, true, R.kappa, WL_F64, 18, R.nrhs, R.rhi, R.thi, R.tmphi, nullptr, 0, nullptr, R.s,
@@ -988,12 +1008,12 @@ static wl_status cg_iteration(CGRun &R, bool reliable) {
             return st;
         HIP_TRY(cg_beta(R.sc, R.nrhs, R.partials, R.stride, nblk2, R.done, 0, R.s));
         VecArgs u = vec_args(R.c, R.prec, R.nrhs);
-        set_vec(u, 0, R.x, R.hb_hi);
+        set_vec(u, 0, R.xlo ? R.xlo : R.x, R.xlo ? R.hb_xlo : R.hb_hi);
         set_vec(u, 1, R.p, R.hb_lo);
         set_vec(u, 2, R.r, R.hb_lo);
         u.sc = R.sc;
         u.flag = nullptr;  // must also run after the last system's final step
-        HIP_TRY(cg_update_xp(R.prec, u, R.nh, R.s));
+        HIP_TRY(cg_update_xp(R.prec, R.xlo ? WL_F32 : WL_F64, u, R.nh, R.s));
         return WL_OK;
     }
     st = apply_m(R.c, R.op, true, R.kappa, R.prec, R.recon, R.nrhs, R.sv, R.q, R.tmp, nullptr, 0, R.done, R.s,
@@ -1010,7 +1030,8 @@ static std::vector<uintptr_t> graph_key(const CGRun &R) {
     std::memcpy(&kb, &R.kappa, sizeof kb);
     std::memcpy(&mb, &R.mu, sizeof mb);
     return {(uintptr_t)R.op, (uintptr_t)R.prec, (uintptr_t)R.recon, (uintptr_t)R.nrhs, (uintptr_t)kb, (uintptr_t)mb,
-            (uintptr_t)R.x, (uintptr_t)R.r, (uintptr_t)R.p, (uintptr_t)R.q, (uintptr_t)R.sv, (uintptr_t)R.tmp,
+            (uintptr_t)R.x, (uintptr_t)R.xlo, (uintptr_t)R.r, (uintptr_t)R.p, (uintptr_t)R.q, (uintptr_t)R.sv,
+            (uintptr_t)R.tmp,
             (uintptr_t)R.partials, (uintptr_t)R.stride, (uintptr_t)R.sc, (uintptr_t)R.done,
             (uintptr_t)R.nblk_blas, (uintptr_t)g.block, (uintptr_t)g.swizzle, (uintptr_t)g.tps,
             (uintptr_t)g.tchunk, (uintptr_t)(g.nt + 1), (uintptr_t)g.rpt};
@@ -1099,7 +1120,16 @@ static wl_status cg_setup(wl_ctx *c, void *x, const void *b, int op, double kapp
     R.bnorm2 = (double *)c->buf[S_BNORM];
     R.done = (int *)c->buf[S_FLAG];
     R.nblk_blas = blas_blocks(c->Vh * (long)nrhs) * nh;
-    if (P.prec == WL_F64) R.r = R.rhi;  // FP64 CG iterates directly on the FP64 residual
+    if (P.prec == WL_F64) {
+        R.r = R.rhi;  // FP64 CG iterates directly on the FP64 residual
+    } else {
+        R.hb_xlo = half_bytes(c, WL_F32, nrhs);
+        if ((st = ensure_buf(c, S_XLO, R.hb_xlo * nh))) return st;
+        R.xlo = c->buf[S_XLO];
+        VecArgs z = vec_args(c, WL_F32, nrhs);
+        set_vec(z, 0, R.xlo, R.hb_xlo);
+        HIP_TRY(blas_zero(WL_F32, z, nh, s));
+    }
     return WL_OK;
 }
 
@@ -1588,12 +1618,12 @@ static wl_status batch_iteration(wl_batch *B, std::vector<CGRun> &R, const std::
         for (int k = 0; k < n; ++k) {
             HIP_TRY(cg_beta(R[k].sc, R[k].nrhs, R[k].partials, R[k].stride, nblk[k], R[k].done, 0, R[k].s));
             VecArgs u = vec_args(R[k].c, R[k].prec, R[k].nrhs);
-            set_vec(u, 0, R[k].x, R[k].hb_hi);
+            set_vec(u, 0, R[k].xlo ? R[k].xlo : R[k].x, R[k].xlo ? R[k].hb_xlo : R[k].hb_hi);
             set_vec(u, 1, R[k].p, R[k].hb_lo);
             set_vec(u, 2, R[k].r, R[k].hb_lo);
             u.sc = R[k].sc;
             u.flag = nullptr;  // must also run after the system's final step
-            HIP_TRY(cg_update_xp(R[k].prec, u, R[k].nh, R[k].s));
+            HIP_TRY(cg_update_xp(R[k].prec, R[k].xlo ? WL_F32 : WL_F64, u, R[k].nh, R[k].s));
         }
         return WL_OK;
     }

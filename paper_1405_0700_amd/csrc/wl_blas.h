@@ -43,9 +43,10 @@ hipError_t cg_update_xr(int prec, int xprec, VecArgs &a, int nhalves, hipStream_
 // p = r + beta p (beta = sc[rhs].beta): v0 = r, v1 = p
 hipError_t cg_update_p(int prec, VecArgs &a, int nhalves, hipStream_t s);
 // after a hopping launch with EPI_CGR updated r: x += alpha p (where alpha != 0), then
-// p = r + beta p (active systems): v0 = x (FP64), v1 = p, v2 = r.  Launch it without a
-// flag; cg_alpha zeroes alpha in iterations that take no step.
-hipError_t cg_update_xp(int prec, VecArgs &a, int nhalves, hipStream_t s);
+// p = r + beta p (active systems): v0 = x (FP64 solution, or an FP32 accumulator:
+// xprec), v1 = p, v2 = r.  Launch it without a flag; cg_alpha zeroes alpha in
+// iterations that take no step.
+hipError_t cg_update_xp(int prec, int xprec, VecArgs &a, int nhalves, hipStream_t s);
 // v1 (prec dprec) = v0 (prec sprec), or v1 += v0 if accumulate
 hipError_t blas_convert(int dprec, int sprec, bool accumulate, VecArgs &a, int nhalves, hipStream_t s);
 // v1 += (a + i b) v0

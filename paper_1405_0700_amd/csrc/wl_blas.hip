@@ -152,13 +152,17 @@ __global__ void __launch_bounds__(256) k_cg_p(const VecArgs a) {
 }
 
 // The rest of an iteration whose residual was updated in the hopping epilogue:
-// x += alpha p (x FP64, where this iteration took a step: alpha != 0, which also
-// covers a system that stopped at its beta step), then p = r + beta p (systems
-// still iterating).  v0 = x, v1 = p, v2 = r.  Launched without the active-count
-// gate (the count is already 0 after the last system's final step).
-template <int SP>
+// x += alpha p (where this iteration took a step: alpha != 0, which also covers a
+// system that stopped at its beta step), then p = r + beta p (systems still
+// iterating).  v0 = x, v1 = p, v2 = r.  x is the FP64 solution (XP = FP64) or, in
+// mixed precision, an FP32 accumulator of the steps since the last FP64 refresh
+// (XP = FP32), which the solver adds to the FP64 solution before reading it.
+// Launched without the active-count gate (the count is already 0 after the last
+// system's final step).
+template <int SP, int XP>
 __global__ void __launch_bounds__(256) k_cg_xp(const VecArgs a) {
     using T = typename SpinorIO<SP>::real;
+    using TX = typename SpinorIO<XP>::real;
     WL_FLAG_EXIT
     const int h = blockIdx.y;
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,11 +172,12 @@ __global__ void __launch_bounds__(256) k_cg_xp(const VecArgs a) {
     if (alpha == 0.0) return;
     cpx<T> p[12];
     SpinorIO<SP>::load(a.v[1][h], gid, p);
-    cpx<double> x[12];
-    SpinorIO<WL_F64>::load(a.v[0][h], gid, x);
+    cpx<TX> x[12];
+    SpinorIO<XP>::load(a.v[0][h], gid, x);
+    const TX ax = (TX)alpha;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) x[k] = {fma(alpha, (double)p[k].re, x[k].re), fma(alpha, (double)p[k].im, x[k].im)};
-    SpinorIO<WL_F64>::store(a.v[0][h], gid, x);
+    for (int k = 0; k < 12; ++k) x[k] = {fma(ax, (TX)p[k].re, x[k].re), fma(ax, (TX)p[k].im, x[k].im)};
+    SpinorIO<XP>::store(a.v[0][h], gid, x);
     if (!sc.active) return;
     const T beta = (T)sc.beta;
     cpx<T> r[12];
@@ -556,9 +561,13 @@ hipError_t blas_blockdot(const BlockDotArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_blockdot, dim3((unsigned)blockdot_blocks(a.n)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
-hipError_t cg_update_xp(int prec, VecArgs &a, int nh, hipStream_t s) {
+hipError_t cg_update_xp(int prec, int xprec, VecArgs &a, int nh, hipStream_t s) {
     dim3 grid = vgrid(a, nh);
-    WL_DISPATCH_PREC(prec, k_cg_xp)
+    if (xprec == WL_F32) {
+        WL_DISPATCH_PREC(prec, k_cg_xp, , WL_F32)
+    }
+    if (xprec != WL_F64) return hipErrorInvalidValue;
+    WL_DISPATCH_PREC(prec, k_cg_xp, , WL_F64)
 }
 hipError_t blas_scale_by_rho(VecArgs &a, int nh, hipStream_t s) {
     if (!a.sc || a.nrhs != 1) return hipErrorInvalidValue;

@@ -85,6 +85,29 @@ def test_mixed_precision_cg_reaches_fp64_tolerance(prec, recon):
     assert info[0]["reliable_updates"] >= 1
 
 
+@pytest.mark.parametrize("prec,recon,use_graph,maxiter", [(W.WL_F32, 18, 0, 9), (W.WL_F16N, 12, 1, 13),
+                                                           (W.WL_F32, 12, 1, 30)])
+def test_mixed_precision_returns_the_whole_iterate_when_stopped_early(prec, recon, use_graph, maxiter):
+    # between FP64 refreshes the steps go to an FP32 accumulator; a solve that stops at
+    # maxiter (before or after a refresh) must still return x with every step in it: the
+    # residual it reports is the one of the returned x
+    dims = (8, 8, 8, 16)
+    kappa = 0.135
+    u, lat = lattice(dims, 0.2, 301)
+    eta = synth.gaussian_spinor(dims, seed=303)
+    rhs = schur_rhs(lat, u, eta, kappa, dims)
+    p = W.wl_solver_params_default()
+    p.prec, p.recon, p.use_graph, p.maxiter, p.max_restarts, p.tol = prec, recon, use_graph, maxiter, 0, 1e-12
+    p.reliable_every = 20
+    x = lat.new(W.WL_EVEN)
+    st, info = W.wl_cg_solve(lat.ctx, x, lat.pack(rhs, W.WL_EVEN), W.WL_OP_DHAT, kappa, params=p)
+    assert st == W.WL_NOT_CONVERGED and 0 < info[0]["iters"] <= maxiter
+    r = oracle_normal_resid(u, kappa, lat.unpack(x, W.WL_EVEN), rhs)
+    print("prec", prec, "maxiter", maxiter, info[0], "oracle residual", r)
+    assert r < 0.5  # the iterate has moved well away from x = 0 (relative residual 1)
+    assert abs(r - info[0]["true_rel_resid"]) <= 1e-9 * r
+
+
 def test_mixed_precision_matches_fp64_solution():
     dims = (8, 8, 8, 16)
     kappa = 0.135

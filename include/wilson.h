@@ -286,7 +286,9 @@ typedef struct {
  * Mixed precision: the FP64 residual is refreshed every reliable_every
  * iterations and whenever ||r|| has dropped by reliable_delta since the last
  * refresh; the iteration of that drop is predicted from the observed decay of
- * ||r|| (no device-to-host read in between). */
+ * ||r|| (no device-to-host read in between).  Between refreshes the solution's
+ * steps are summed in an FP32 workspace field of the context and added to the
+ * FP64 x at each refresh and before the solve returns. */
 void wl_solver_params_default(wl_solver_params *p);
 
 /* Conjugate gradient on the normal equations M^+ M x = b, M = D or D_hat.

@@ -439,7 +439,8 @@ def run_batch(args):
     """Uneven batch: 16^3x32, 24^3x48 and 32^3x64 (links exp(0.2iH), seeds 411-413), 4 Gaussian
     right-hand sides each (seeds 421-423), kappa 0.135, e/o CG on the normal equations to 1e-10,
     FP32 inner with FP64 reliable updates and a graph-captured iteration: all three systems in
-    one batched solve (one persistent launch per hopping stage) vs the three solved one after
+    one batched solve (one persistent launch per hopping stage; then the autotuned launch, which
+    may be one launch per system; then one launch per system) vs the three solved one after
     another; plus the persistent D_hat launch over all three against three separate launches."""
     import numpy as np
     import torch
@@ -519,6 +520,13 @@ def run_batch(args):
     res["batched_tuned_launch"] = tuned
     res["batched_worst_true_resid_tuned"] = true_resid()
     log("batched (tuned launch %s) %.1f ms" % (tuned, ms_t))
+    # lockstep with one launch per system and stage (workgroups 0)
+    W.wl_batch_set_launch(batch, 0, *default_launch[1:])
+    ms_p, (st, info) = timed(batched)
+    res["batched_per_system_launches_ms"] = round(ms_p, 2)
+    res["batched_worst_true_resid_per_system"] = true_resid()
+    log("batched (per-system launches) %.1f ms" % ms_p)
+    W.wl_batch_set_launch(batch, *default_launch)
     # the persistent D_hat over all three systems against three separate D_hat applications
     ins = [l.new(W.WL_EVEN, W.WL_F32, nrhs) for l in lats]
     for t_ in ins:

@@ -438,7 +438,11 @@ wl_status wl_batch_destroy(wl_batch *batch);
  * threads per tile (64..256, a multiple of 64; default 256), non-temporal
  * hints (1 on, 0 off, -1 by working-set size, the default) and threads per
  * output point (1, the default; 2: forward and backward hops in the two halves
- * of a wavefront, for FP64 / FP32 storage only, measured slower here). */
+ * of a wavefront, for FP64 / FP32 storage only, measured slower here).
+ * workgroups = 0 replaces the persistent launch by one launch per system and
+ * stage, each with its context's own launch configuration (block, nt and tps
+ * are then unused; the batch timing calls record nothing, the contexts' own
+ * timing does): faster when every system fills the GPU by itself. */
 wl_status wl_batch_set_launch(wl_batch *batch, int workgroups, int block, int nt, int tps);
 wl_status wl_batch_get_launch(const wl_batch *batch, int *workgroups, int *block, int *nt, int *tps);
 
@@ -484,11 +488,12 @@ wl_status wl_batch_timing_read(wl_batch *batch, int *count, double *total_ms);
  * Synchronous. */
 wl_status wl_autotune(wl_ctx *ctx, wl_prec prec, int recon, int nrhs, const char *cache_path, wl_launch *chosen,
                       double *best_us, int *from_cache);
-/* The same for a batch: persistent workgroups (1..8 per compute unit, scaled
- * by 256 / block), threads per tile 64/128/256, non-temporal hints and one or
- * two threads per point, timed on the persistent launch of D over every
- * system; the result becomes the batch's launch configuration.  Cache entries
- * that wl_batch_set_launch would reject are ignored. */
+/* The same for a batch: one launch per system (workgroups 0, the contexts'
+ * current shapes) against the persistent launch with 1..8 workgroups per
+ * compute unit (scaled by 256 / block), threads per tile 64/128/256,
+ * non-temporal hints and one or two threads per point, all timed on D over
+ * every system; the result becomes the batch's launch configuration.  Cache
+ * entries that wl_batch_set_launch would reject are ignored. */
 wl_status wl_batch_autotune(wl_batch *batch, wl_prec prec, int recon, int nrhs, const char *cache_path,
                             int *workgroups, int *block, int *nt, int *tps, double *best_us, int *from_cache);
 

@@ -1406,7 +1406,8 @@ static const char *launch_problem(int block, int tps, int nt, int rpt) {
 }
 
 static const char *batch_launch_problem(int workgroups, int block, int nt, int tps) {
-    if (workgroups < 8 || workgroups % 8 || workgroups > 65536) return "workgroups not a multiple of 8 in 8..65536";
+    if (workgroups != 0 && (workgroups < 8 || workgroups % 8 || workgroups > 65536))
+        return "workgroups not 0 or a multiple of 8 in 8..65536";
     if (block < 64 || block > 256 || block % 64) return "block not in {64, 128, 192, 256}";
     if (nt < -1 || nt > 1) return "nt not in {-1, 0, 1}";
     if (tps != 1 && tps != 2) return "tps not in {1, 2}";
@@ -1477,6 +1478,23 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
     const int nst = op == WL_OP_D ? 1 : 2;
     const int tps = (prec == WL_F64 || prec == WL_F32) && B->tps == 2 ? 2 : 1;
     if (cg_sc && (!dag || !partials)) return fail(WL_ERR_ARG, "the residual update needs M^+ and norm partials");
+    if (B->nwg == 0) {
+        // one launch per system and stage, each with its context's own launch shape
+        for (int k = 0; k < n; ++k) {
+            wl_ctx *c = B->ctx[k];
+            void *tk = tmp ? tmp[k] : nullptr;
+            const int *fk = flags ? flags[k] : nullptr;
+            long nb = 0;
+            wl_status st = cg_sc ? apply_mdag_update_r(c, op, kappa[k], prec, recon, nrhs, out[k], in[k], tk,
+                                                       partials[k], stride[k], fk, s, &nb, mu, cg_sc[k])
+                                 : apply_m(c, op, dag, kappa[k], prec, recon, nrhs, out[k], in[k], tk,
+                                           partials ? partials[k] : nullptr, partials ? stride[k] : 0, fk, s,
+                                           &nb, mu);
+            if (st) return st;
+            if (nblk) nblk[k] = nb;
+        }
+        return WL_OK;
+    }
     for (int stage = 0; stage < nst; ++stage) {
         BatchArgs A;
         std::memset(&A, 0, sizeof A);
@@ -1601,7 +1619,12 @@ static wl_status batch_iteration(wl_batch *B, std::vector<CGRun> &R, const std::
     for (int k = 0; k < n; ++k)
         HIP_TRY(cg_alpha(R[k].sc, R[k].nrhs, R[k].partials, R[k].stride, nblk[k], R[k].done, R[k].s));
     bool fused = true;
-    for (int k = 0; k < n; ++k) fused = fused && !ru[k];
+    for (int k = 0; k < n; ++k) {
+        fused = fused && !ru[k];
+        // per-system launches take the fused form only with one rhs per thread
+        const LaunchCfg &g = R[k].c->cfg[R[k].prec];
+        if (B->nwg == 0) fused = fused && effective_rpt(g, R[k].nrhs, effective_tps(R[k].prec, g)) == 1;
+    }
     if (fused) {
         // as in the single-system iteration: the last stage updates r_k in place
         // (r -= alpha A p, ||r||^2), then beta and x += alpha p, p = r + beta p
@@ -2080,6 +2103,25 @@ extern "C" wl_status wl_batch_autotune(wl_batch *B, wl_prec prec, int recon, int
         const bool saved_timing = B->timing;
         B->timing = false;
         best_t = 1e30;
+        // first candidate: one launch per system with each context's own shape
+        B->nwg = 0;
+        {
+            double us = 0.0;
+            st = time_launches(
+                [&]() {
+                    return batch_apply(B, WL_OP_D, false, kap.data(), prec, recon, nrhs, outs.data(),
+                                       (const void *const *)ins.data(), nullptr, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr);
+                },
+                5, nullptr, &us);
+            if (!st) {
+                best_t = us;
+                bw = 0;
+                bb = sb;
+                bn = sn;
+                bt = st2;
+            }
+        }
         for (int tpv : {1, 2})
         for (int per_cu : {1, 2, 3, 4, 6, 8})
             for (int blk : {64, 128, 256})

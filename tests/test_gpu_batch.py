@@ -89,6 +89,34 @@ def test_batch_operator_matches_single_context_and_oracle(batch, op, dagger, nrh
                 assert rel(got[r], want) < 1e-13
 
 
+@pytest.mark.parametrize("op", [W.WL_OP_D, W.WL_OP_DHAT])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_batch_per_system_launches_equal_the_single_context_operator(batch, op, nrhs):
+    # workgroups 0: each system is applied by its own context's launches, bit for bit
+    b, lats, gauges = batch
+    saved = W.wl_batch_get_launch(b)
+    W.wl_batch_set_launch(b, 0, saved[1], saved[2], saved[3])
+    assert W.wl_batch_get_launch(b)[0] == 0
+    subset = W.WL_FULL if op == W.WL_OP_D else W.WL_EVEN
+    kappas = [s[3] for s in SYSTEMS]
+    ins, outs = [], []
+    for lat, (dims, _, seed, _) in zip(lats, SYSTEMS):
+        n = synth.volume(dims) // (1 if subset == W.WL_FULL else 2)
+        f = np.stack([synth.gaussian_spinor(dims, seed=seed * 13 + r, nsites=n) for r in range(nrhs)])
+        ins.append(lat.pack(f if nrhs > 1 else f[0], subset, W.WL_F64, nrhs))
+        outs.append(lat.new(subset, W.WL_F64, nrhs))
+    try:
+        for dagger in (False, True):
+            W.wl_batch_dirac_apply(b, outs, ins, op, dagger, kappas, W.WL_F64, 18, nrhs)
+            for k, lat in enumerate(lats):
+                ref = lat.new(subset, W.WL_F64, nrhs)
+                W.wl_dirac_apply(lat.ctx, ref, ins[k], op, dagger, kappas[k], W.WL_F64, 18, nrhs)
+                torch.cuda.synchronize()
+                assert torch.equal(outs[k], ref), (k, dagger)
+    finally:
+        W.wl_batch_set_launch(b, *saved)
+
+
 def test_batch_launch_shape_does_not_change_results_and_counters_reset(batch):
     b, lats, _ = batch
     kappas = [s[3] for s in SYSTEMS]
@@ -114,11 +142,16 @@ def test_batch_launch_shape_does_not_change_results_and_counters_reset(batch):
     (W.WL_F32, 18, 0, -1, 1), (W.WL_F32, 18, 1, -1, 1), (W.WL_F64, 18, 1, -1, 1), (W.WL_F64, 12, 0, -1, 1),
     (W.WL_F16N, 12, 1, -1, 1), (W.WL_BF16N, 12, 0, -1, 1),
     # non-temporal stores and two threads per point, as chosen for large lattices
-    (W.WL_F32, 18, 1, 1, 2), (W.WL_F64, 18, 0, 1, 2), (W.WL_F16N, 12, 0, 1, 1)])
+    (W.WL_F32, 18, 1, 1, 2), (W.WL_F64, 18, 0, 1, 2), (W.WL_F16N, 12, 0, 1, 1),
+    # nt = None: one launch per system (workgroups 0) with the contexts' own shapes
+    (W.WL_F32, 18, 1, None, 1), (W.WL_F16N, 12, 0, None, 1), (W.WL_F64, 18, 0, None, 1)])
 def test_batch_cg_mixed_precision_solves_every_system(batch, prec, recon, use_graph, nt, tps):
     b, lats, gauges = batch
     saved = W.wl_batch_get_launch(b)
-    W.wl_batch_set_launch(b, saved[0], saved[1], nt, tps)
+    if nt is None:
+        W.wl_batch_set_launch(b, 0, saved[1], saved[2], saved[3])
+    else:
+        W.wl_batch_set_launch(b, saved[0], saved[1], nt, tps)
     try:
         _batch_cg_case(b, lats, gauges, prec, recon, use_graph)
     finally:
@@ -254,7 +287,8 @@ def test_batch_autotune(batch, tmp_path):
     b, lats, _ = batch
     before = W.wl_batch_get_launch(b)
     (wg, blk, nt, tps), us, cached = W.wl_batch_autotune(b, W.WL_F32, 18, 2, tmp_path / "b.txt")
-    assert not cached and us > 0 and wg % 8 == 0 and blk in (64, 128, 256) and nt in (0, 1) and tps in (1, 2)
+    # workgroups 0: one launch per system (then nt and tps are the batch's unused settings)
+    assert not cached and us > 0 and wg % 8 == 0 and blk in (64, 128, 256) and nt in (-1, 0, 1) and tps in (1, 2)
     assert W.wl_batch_get_launch(b) == (wg, blk, nt, tps)
     again = W.wl_batch_autotune(b, W.WL_F32, 18, 2, tmp_path / "b.txt")
     assert again[2] and again[0] == (wg, blk, nt, tps)

@@ -427,11 +427,11 @@ wl_status wl_pcgnr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, cons
  * merged into ONE persistent launch per operator stage: the blocks of points
  * of all systems form one work list, split into eight contiguous ranges (one
  * per XCD, so that an XCD's L2 sees neighbouring tiles of one lattice), which
- * a fixed grid of resident workgroups drains through atomic counters; the
- * counters are left at zero for the next launch, so the launch can be
- * replayed inside a graph.  The batch owns a non-blocking stream used for
- * graph capture and a few bytes of device memory; it does not own the
- * contexts, which must outlive it.  Calls on one batch are not thread-safe. */
+ * a fixed grid of resident workgroups of that XCD takes round-robin (every
+ * tile costs the same; no device state persists between launches, so a
+ * launch can be replayed inside a graph).  The batch owns a non-blocking
+ * stream used for graph capture; it does not own the contexts, which must
+ * outlive it.  Calls on one batch are not thread-safe. */
 wl_status wl_batch_create(wl_ctx *const *ctxs, int nsys, wl_batch **out);
 wl_status wl_batch_destroy(wl_batch *batch);
 /* Persistent workgroups (a multiple of 8; default 3 per compute unit),

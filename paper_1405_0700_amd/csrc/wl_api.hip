@@ -1335,7 +1335,6 @@ struct wl_batch {
     int device = 0;
     hipStream_t s = nullptr;              // own non-blocking stream (graph capture)
     hipEvent_t handoff[2] = {nullptr, nullptr};
-    int *counter = nullptr;               // 9 work counters, 128 bytes apart
     int nwg = 0, block = 256, nt = -1;    // persistent workgroups, threads per tile, non-temporal
     int tps = 1;                          // threads per point (2: FP64 / FP32 storage only)
     hipGraph_t graph = nullptr;
@@ -1363,8 +1362,6 @@ extern "C" wl_status wl_batch_create(wl_ctx *const *ctxs, int nsys, wl_batch **o
     B->device = ctxs[0]->device;
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device);
-    if (e == hipSuccess) e = hipMalloc(&B->counter, sizeof(int) * 9 * 32);
-    if (e == hipSuccess) e = hipMemset(B->counter, 0, sizeof(int) * 9 * 32);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&B->handoff[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&B->handoff[1], hipEventDisableTiming);
@@ -1390,7 +1387,6 @@ extern "C" wl_status wl_batch_destroy(wl_batch *B) {
     for (hipEvent_t e : B->handoff)
         if (e) (void)hipEventDestroy(e);
     if (B->s) (void)hipStreamDestroy(B->s);
-    if (B->counter) (void)hipFree(B->counter);
     delete B;
     return WL_OK;
 }
@@ -1499,7 +1495,6 @@ static wl_status batch_apply(wl_batch *B, int op, bool dag, const double *kappa,
         BatchArgs A;
         std::memset(&A, 0, sizeof A);
         A.nsys = n;
-        A.counter = B->counter;
         long tiles = 0;
         double ws = 0.0;
         const bool last = stage == nst - 1;

@@ -63,9 +63,7 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
 // body).  sys[k] is filled like a single launch's HopArgs (out_par0 = first
 // output parity); tiles of system k: per_par[k] blocks of `block` points per
 // output parity, np[k] parities; start[k] = first tile of system k in the
-// concatenated list, start[nsys] = ntiles.  counter: 9 ints, each on its own
-// 128-byte line (stride 32), zero before the first launch; the kernel leaves
-// them zero.
+// concatenated list, start[nsys] = ntiles.
 constexpr int BATCH_MAX = 8;
 struct BatchArgs {
     HopArgs sys[BATCH_MAX];
@@ -73,7 +71,6 @@ struct BatchArgs {
     long per_par[BATCH_MAX];
     int nsys;
     long ntiles;
-    int *counter;
 };
 // nwg: persistent workgroups (a multiple of 8); epi without EPI_NORM alone; tps 2
 // (two threads per point, FP64/FP32 storage only): a tile holds block / 2 points

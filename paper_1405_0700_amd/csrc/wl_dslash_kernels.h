@@ -475,14 +475,6 @@ __global__ void __launch_bounds__(256) hop_kernel_mr(const HopArgs a) {
     }
 }
 
-// Persistent launch over the tiles (blocks of points) of several systems.  The
-// tiles of all systems form one list, cut into eight contiguous ranges, one
-// per XCD (the hardware hands workgroup w to XCD w % 8); the workgroups of an
-// XCD take the tiles of its range in order from that range's atomic counter,
-// so an XCD's L2 sees neighbouring tiles of the same lattice.  After the last
-// workgroup has taken its final (past-the-end) tile it resets the counters, so
-// the launch can be repeated (or replayed in a graph) without clearing them.
-
 // Two threads per output point: lanes 0-31 of a wavefront take the forward
 // hops of 32 consecutive points, lanes 32-63 the backward hops of the same
 // points; the partial sums are exchanged across the halves and each half
@@ -602,27 +594,20 @@ __global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
     }
 }
 
-// Next tile of this workgroup's XCD range, the same value in every lane: the
-// barriers before and after the slot keep it from being overwritten while
-// read, and readfirstlane makes the value (and every branch on it) uniform to
-// the compiler, so that the barriers of the loop body are never under control
-// flow it must treat as divergent.
-__device__ __forceinline__ int next_tile(int *counter, int r0, int *slot) {
-    __syncthreads();
-    if (threadIdx.x == 0) *slot = r0 + atomicAdd(counter, 1);
-    __syncthreads();
-    return __builtin_amdgcn_readfirstlane(*slot);
-}
-
+// Persistent launch over the tiles of all systems: the tile list is cut into
+// eight contiguous ranges, one per XCD (the hardware places workgroup b on XCD
+// b mod 8), and the workgroups of an XCD take its tiles round-robin.  Every tile
+// costs the same, so a static schedule balances as well as a shared counter
+// would, without serialising every claim on one atomic address.  The tile index
+// is derived from blockIdx only, so all control flow around the barriers of the
+// norm epilogue is uniform.
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT, int TPS>
 __global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
-    __shared__ int slot;
     __shared__ double lds[256];
     __shared__ int lrhs[TPS == 2 ? 256 : 1];
-    const int xcd = blockIdx.x % 8;
+    const int xcd = blockIdx.x % 8, j = blockIdx.x / 8, nper = gridDim.x / 8;  // gridDim.x: a multiple of 8
     const int r0 = (int)(B.ntiles * xcd / 8), r1 = (int)(B.ntiles * (xcd + 1) / 8);
-    int tile = next_tile(B.counter + xcd * 32, r0, &slot);
-    while (tile < r1) {
+    for (int tile = r0 + j; tile < r1; tile += nper) {
         int sy = 0;
         while (sy + 1 < B.nsys && tile >= B.start[sy + 1]) ++sy;
         const HopArgs &a = B.sys[sy];
@@ -642,14 +627,6 @@ __global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
                 const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, gid);
                 if constexpr (EPI & EPI_NORM) block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + local, a.part_stride);
             }
-        }
-        tile = next_tile(B.counter + xcd * 32, r0, &slot);
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(B.counter + 8 * 32, 1) == (int)gridDim.x - 1) {
-            for (int k = 0; k <= 8; ++k) atomicExch(B.counter + k * 32, 0);
-            __threadfence();
         }
     }
 }

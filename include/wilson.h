@@ -135,7 +135,11 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *           tps = 1) a thread computes rpt consecutive right-hand sides of one
  *           site and applies each link it loads to all of them; a launch whose
  *           nrhs is not a multiple of rpt uses one point per thread.
- * Results do not depend on block, swizzle, tchunk or nt; tps changes the
+ *   occ     0: no cap; k in 1..8: about k waves per SIMD at most (the launch
+ *           reserves unused LDS per block so that fewer blocks fit on a compute
+ *           unit; fewer points in flight keep the re-read neighbour spinors
+ *           within the XCD's L2).  Default 4 for the 16-bit formats, 0 else.
+ * Results do not depend on block, swizzle, tchunk, nt or occ; tps changes the
  * summation order of the 8 hops and rpt the compiler's contraction of
  * multiply-adds (rounding only).  Defaults are chosen per
  * precision by measurement (see wl_ctx_get_launch). */
@@ -147,6 +151,7 @@ typedef struct {
     int tchunk;
     int nt;
     int rpt;
+    int occ;
 } wl_launch;
 wl_status wl_ctx_set_launch(wl_ctx *ctx, wl_prec prec, const wl_launch *cfg);
 wl_status wl_ctx_get_launch(const wl_ctx *ctx, wl_prec prec, wl_launch *cfg);
@@ -300,13 +305,15 @@ void wl_solver_params_default(wl_solver_params *p);
 wl_status wl_cg_solve(wl_ctx *ctx, void *x, const void *b, wl_op op, double kappa, int nrhs,
                       const wl_solver_params *params, wl_solver_info *info, void *stream);
 
-/* Plain FP64 CG for M x = eta with M = D (FULL fields), through the normal
- * equations D^+ D x = D^+ eta, stopped on the residual of the system itself:
- * ||eta - D x|| <= tol ||eta|| (recomputed in FP64; the normal-equation
- * tolerance is tightened and the CG continued until it holds).  params as for
- * wl_cg_solve; info->iters counts all CG iterations.  Synchronous. */
-wl_status wl_cgnr_solve(wl_ctx *ctx, void *x, const void *eta, double kappa, const wl_solver_params *params,
-                        wl_solver_info *info, void *stream);
+/* Plain FP64 CG for M x = eta with M = D (FULL fields of nrhs right-hand
+ * sides), through the normal equations D^+ D x = D^+ eta, stopped on the
+ * residual of the system itself, ||eta - D x|| <= tol ||eta|| for every rhs
+ * (reading C-7: the criterion every solver of D x = eta is compared on;
+ * recomputed in FP64; the normal-equation tolerance is tightened and the CG
+ * continued until it holds).  params as for wl_cg_solve; info: nrhs entries
+ * (may be NULL), iters counts all CG iterations.  Synchronous. */
+wl_status wl_cgnr_solve(wl_ctx *ctx, void *x, const void *eta, double kappa, int nrhs,
+                        const wl_solver_params *params, wl_solver_info *info, void *stream);
 
 /* Flexible GCR with restarts, right-preconditioned by the PTC network.
  * One cycle keeps up to `restart` search directions: z = M(r), w = D z,
@@ -352,9 +359,18 @@ wl_status wl_ptc_destroy(wl_ptc *net);
  * (either pointer may be NULL).  Synchronous. */
 wl_status wl_ptc_get_weights(const wl_ptc *net, double *w1, double *w2);
 wl_status wl_ptc_get_grads(const wl_ptc *net, double *g1, double *g2);
+/* Adam's first and second moments of the real parameters (Re W, Im W) to host
+ * FP64 arrays laid out like the weights (layer 1 then layer 2, each entry a
+ * (re-part moment, im-part moment) pair; m1 / v1 hold 2 x 9 x C x 16 values,
+ * m2 / v2 the same); any pointer may be NULL.  Synchronous. */
+wl_status wl_ptc_get_moments(const wl_ptc *net, double *m1, double *m2, double *v1, double *v2);
 
-/* out = M(in): the two layers with the BF16 weights (1-channel FULL FP32 fields). */
-wl_status wl_ptc_apply(wl_ctx *ctx, const wl_ptc *net, void *out, const void *in, void *stream);
+/* out = M(in) (adjoint == 0) or M^+(in): the two layers with the BF16
+ * weights, applied alike to each of nrhs right-hand sides (FULL FP32 fields of
+ * nrhs, points (site, rhs) with rhs fastest; the right-hand sides of a site
+ * share its link loads). */
+wl_status wl_ptc_apply(wl_ctx *ctx, const wl_ptc *net, void *out, const void *in, int nrhs, int adjoint,
+                       void *stream);
 
 /* One layer with explicit FP32 device weights `weights` of shape
  * (9, cout_f, cin_f, 4, 4): adjoint == 0 computes out (cout channels) from in
@@ -393,16 +409,21 @@ wl_status wl_ptc_step(wl_ptc *net, double lr, double *loss, void *stream);
 /* ---------------------------------------------------------------- preconditioned CGNR
  *
  * CG on the normal equations of the right-preconditioned system D M y = b,
- * x = M y, with M the PTC network of `net` (or M = 1 for net == NULL): each
- * iteration applies D M and its adjoint M^+ D^+, so (D M)^+ (D M) is Hermitian
- * positive definite whatever the spectrum of D (restarted GCR on D stalls once
- * D's spectrum surrounds the origin, as it does past the critical kappa).
- * The inner iteration runs in FP32 (fields, D, the network) with FP64 dot
- * products, on the correction of the FP64 residual, until that residual has
- * dropped by inner_tol; then x += M y in FP64 and the residual is recomputed
- * in FP64 (defect correction).  Two outer cycles that reduce ||b - D x| by
- * less than the factor `stagnation`, breakdown or maxiter hand the solve to
- * plain FP64 CG (wl_cgnr_solve) if `fallback`. */
+ * x = M y (readings R-20 and C-16), with M the PTC network of `net` (or M = 1
+ * for net == NULL): each iteration applies D M and its adjoint M^+ D^+, so
+ * (D M)^+ (D M) is Hermitian positive definite whatever the spectrum of D
+ * (restarted GCR on D stalls once D's spectrum surrounds the origin, as it
+ * does past the critical kappa).  nrhs right-hand sides share every operator
+ * and network application (the links and weights are read once for all);
+ * each has its own scalars, kept on the device.  The inner iteration runs in
+ * FP32 (fields, D, the network) with FP64 dot products, on the correction of
+ * the FP64 residual, until that residual has dropped by inner_tol; then
+ * x += M y in FP64 and the residual is recomputed in FP64 (defect
+ * correction).  Every rhs stops on ||b - D x|| <= tol ||b|| (reading C-7).
+ * Two outer cycles that reduce a rhs's ||b - D x|| by less than the factor
+ * `stagnation`, breakdown or maxiter mark it failed; failed rhs hand the
+ * solve to plain FP64 CG (wl_cgnr_solve, continuing every rhs from its x) if
+ * `fallback`.  A zero right-hand side returns x = 0. */
 typedef struct {
     double tol;        /* stop when ||b - D x|| <= tol ||b||                      */
     int maxiter;       /* inner iterations in total                              */
@@ -414,10 +435,10 @@ typedef struct {
 /* tol 1e-10, maxiter 20000, inner_tol 1e-5, fallback 1, stagnation 0.5 */
 void wl_pcgnr_params_default(wl_pcgnr_params *p);
 
-/* Solve D x = b (FULL FP64 fields; x in: initial guess, out: solution).
- * Synchronous; info as for wl_fgcr_solve (iters = inner iterations,
- * restarts = outer cycles). */
-wl_status wl_pcgnr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, const wl_ptc *net,
+/* Solve D x = b (FULL FP64 fields of nrhs right-hand sides; x in: initial
+ * guess, out: solution).  Synchronous; info: nrhs entries or NULL (iters =
+ * inner iterations, restarts = outer cycles, fallback / fallback_iters). */
+wl_status wl_pcgnr_solve(wl_ctx *ctx, void *x, const void *b, double kappa, const wl_ptc *net, int nrhs,
                          const wl_pcgnr_params *params, wl_solver_info *info, void *stream);
 
 /* ---------------------------------------------------------------- batches of systems

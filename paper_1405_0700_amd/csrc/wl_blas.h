@@ -122,4 +122,43 @@ hipError_t cg_stash_rho(CGScalars *sc, int nrhs, const double *partials, long st
 hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                    const double *bnorm2, double tol, int maxiter, int *done, hipStream_t s);
 
+// ------------------------------------------------------------------ inner CG on (D M)^+ (D M) y = (D M)^+ rho0
+// FP32 fields of nrhs right-hand sides; per-rhs scalars on the device:
+//   gam = ||s||^2 with s = (D M)^+ rho, alpha = gam / ||D M p||^2, beta = gam' / gam,
+//   rho2 = ||rho||^2 of the system residual rho = rho0 - D M y, stop2 its stopping level.
+struct PcgScalars {
+    double gam, alpha, beta, rho2, stop2;
+    int active;     // 1 while this rhs iterates
+    int iters;      // inner iterations taken by this rhs in the current cycle
+    int breakdown;  // a non-positive or non-finite step length or norm stopped it
+    int pad;
+};
+struct PcgVec {
+    void *y[2], *p[2], *rho[2], *q[2];  // per half of a FULL field
+    long n;                             // points per half
+    int nrhs;
+    PcgScalars *sc;
+    double *partials;
+    long part_stride;
+};
+// start of a cycle: gam = sum(partials) (||s||^2), rho2 = rho2_start[r], stop2 = stop2[r]; active where
+// live[r] and rho2 > stop2 and gam > 0; *count = number of active rhs
+hipError_t pcg_start(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk,
+                     const double *rho2_start, const double *stop2, const int *live, int *count, hipStream_t s);
+// alpha = gam / sum(partials) (||D M p||^2) for active rhs (0 else; breakdown stops the rhs)
+hipError_t pcg_alpha(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *count,
+                     hipStream_t s);
+// y += alpha p, rho -= alpha q, partials of ||rho||^2 (rhs with alpha = 0 unchanged)
+hipError_t pcg_update_yr(const PcgVec &v, hipStream_t s);
+// rho2 = sum(partials); an active rhs stops once rho2 <= stop2 (or rho2 is not finite); iters += 1
+hipError_t pcg_check(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *count,
+                     hipStream_t s);
+// beta = sum(partials) / gam (the new ||s||^2), gam = that, for active rhs
+hipError_t pcg_beta(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *count,
+                    hipStream_t s);
+// p = s + beta p for active rhs (v.p = p, v.q = s)
+hipError_t pcg_update_p(const PcgVec &v, hipStream_t s);
+// zero the points of the right-hand sides r with mask[r] != 0 in a FULL field of nrhs (storage prec)
+hipError_t blas_zero_masked(int prec, void *f, size_t half, long n, int nrhs, const int *mask, hipStream_t s);
+
 }  // namespace wl

@@ -377,13 +377,26 @@ __global__ void __launch_bounds__(256) k_residual(const VecArgs a) {
 }
 
 // ------------------------------------------------------------------ single-block reductions
+// Single-block reductions of per-block partial sums run with RED_THREADS threads: each
+// thread keeps four independent sums (its loads are in flight together instead of one
+// dependent chain), combined in a fixed order, then the block sum; bitwise reproducible.
+constexpr int RED_THREADS = 1024;
+
 __device__ double sum_partials(const double *p, long nblk, double *lds) {
-    double s = 0.0;
-    for (long b = threadIdx.x; b < nblk; b += blockDim.x) s += p[b];
-    return block_sum(s, lds);  // valid in thread 0
+    const long st = blockDim.x;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    long b = threadIdx.x;
+    for (; b + 3 * st < nblk; b += 4 * st) {
+        s0 += p[b];
+        s1 += p[b + st];
+        s2 += p[b + 2 * st];
+        s3 += p[b + 3 * st];
+    }
+    for (; b < nblk; b += st) s0 += p[b];
+    return block_sum((s0 + s1) + (s2 + s3), lds);  // valid in thread 0
 }
 
-__global__ void __launch_bounds__(256) k_reduce(const double *partials, long stride, long nblk, int nvals,
+__global__ void __launch_bounds__(RED_THREADS) k_reduce(const double *partials, long stride, long nblk, int nvals,
                                                 double *out) {
     __shared__ double lds[16];
     for (int r = 0; r < nvals; ++r) {
@@ -392,7 +405,7 @@ __global__ void __launch_bounds__(256) k_reduce(const double *partials, long str
     }
 }
 
-__global__ void __launch_bounds__(256) k_reduce_rows(const double *partials, long stride, long nblk, double *out) {
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_rows(const double *partials, long stride, long nblk, double *out) {
     __shared__ double lds[16];
     const double s = sum_partials(partials + (long)blockIdx.x * stride, nblk, lds);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
@@ -400,7 +413,7 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const double *partials, lon
 
 // One block per right-hand side.  `count` holds the number of right-hand
 // sides still iterating; a system leaves the count when it stops.
-__global__ void __launch_bounds__(256) k_cg_alpha(CGScalars *sc, const double *partials, long stride, long nblk,
+__global__ void __launch_bounds__(RED_THREADS) k_cg_alpha(CGScalars *sc, const double *partials, long stride, long nblk,
                                                   const int *count) {
     // alpha = 0 marks an iteration that takes no step (read by the x update that
     // follows a fused residual update, which must run after the last system stops)
@@ -430,7 +443,7 @@ __global__ void __launch_bounds__(256) k_cg_alpha(CGScalars *sc, const double *p
     }
 }
 
-__global__ void __launch_bounds__(256) k_cg_beta(CGScalars *sc, const double *partials, long stride, long nblk,
+__global__ void __launch_bounds__(RED_THREADS) k_cg_beta(CGScalars *sc, const double *partials, long stride, long nblk,
                                                  int *count, int mode) {
     if (*count == 0) return;
     __shared__ double lds[16];
@@ -476,7 +489,7 @@ __global__ void __launch_bounds__(256) k_cg_beta(CGScalars *sc, const double *pa
     }
 }
 
-__global__ void __launch_bounds__(256) k_cg_stash(CGScalars *sc, const double *partials, long stride, long nblk,
+__global__ void __launch_bounds__(RED_THREADS) k_cg_stash(CGScalars *sc, const double *partials, long stride, long nblk,
                                                   const int *count) {
     if (count && *count == 0) return;
     __shared__ double lds[16];
@@ -487,7 +500,7 @@ __global__ void __launch_bounds__(256) k_cg_stash(CGScalars *sc, const double *p
     if (threadIdx.x == 0) c.rho_iter = s;
 }
 
-__global__ void __launch_bounds__(256) k_cg_init(CGScalars *sc, int nrhs, const double *partials, long stride,
+__global__ void __launch_bounds__(RED_THREADS) k_cg_init(CGScalars *sc, int nrhs, const double *partials, long stride,
                                                  long nblk, const double *bnorm2, double tol, int maxiter,
                                                  int *count) {
     __shared__ double lds[16];
@@ -581,7 +594,7 @@ hipError_t cg_record(const CGScalars *sc, double *hist, int cap, int *recorded, 
 }
 hipError_t reduce_rows(const double *partials, long stride, long nblk, int nvals, double *out, hipStream_t s) {
     if (nvals < 1 || nblk < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)nvals), dim3(256), 0, s, partials, stride, nblk, out);
+    hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)nvals), dim3(RED_THREADS), 0, s, partials, stride, nblk, out);
     return hipGetLastError();
 }
 hipError_t blas_twist(int prec, VecArgs &a, int nh, hipStream_t s) {
@@ -648,28 +661,207 @@ hipError_t blas_convert(int dprec, int sprec, bool acc, VecArgs &a, int nh, hipS
 
 hipError_t reduce_partials(const double *partials, long stride, long nblk, int nvals, double *out,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, stride, nblk, nvals, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, partials, stride, nblk, nvals, out);
     return hipGetLastError();
 }
 hipError_t cg_alpha(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                     const int *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(nrhs), dim3(256), 0, s, sc, partials, stride, nblk, flag);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(nrhs), dim3(RED_THREADS), 0, s, sc, partials, stride, nblk, flag);
     return hipGetLastError();
 }
 hipError_t cg_beta(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *done,
                    int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(nrhs), dim3(256), 0, s, sc, partials, stride, nblk, done, mode);
+    hipLaunchKernelGGL(k_cg_beta, dim3(nrhs), dim3(RED_THREADS), 0, s, sc, partials, stride, nblk, done, mode);
     return hipGetLastError();
 }
 hipError_t cg_stash_rho(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk, const int *flag,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_stash, dim3(nrhs), dim3(256), 0, s, sc, partials, stride, nblk, flag);
+    hipLaunchKernelGGL(k_cg_stash, dim3(nrhs), dim3(RED_THREADS), 0, s, sc, partials, stride, nblk, flag);
     return hipGetLastError();
 }
 hipError_t cg_init(CGScalars *sc, int nrhs, const double *partials, long stride, long nblk,
                    const double *bnorm2, double tol, int maxiter, int *done, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, s, sc, nrhs, partials, stride, nblk, bnorm2, tol,
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(RED_THREADS), 0, s, sc, nrhs, partials, stride, nblk, bnorm2, tol,
                        maxiter, done);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ inner CG of the preconditioned normal equations
+__global__ void __launch_bounds__(RED_THREADS) k_pcg_start(PcgScalars *sc, const double *partials, long stride,
+                                                            long nblk, const double *rho2_start, const double *stop2,
+                                                            const int *live, int *count) {
+    __shared__ double lds[16];
+    const int r = blockIdx.x;
+    const double g = sum_partials(partials + (long)r * stride, nblk, lds);
+    if (threadIdx.x == 0) {
+        PcgScalars &c = sc[r];
+        c.gam = g;
+        c.alpha = 0.0;
+        c.beta = 0.0;
+        c.rho2 = rho2_start[r];
+        c.stop2 = stop2[r];
+        c.iters = 0;
+        c.breakdown = 0;
+        c.active = live[r] && c.rho2 > c.stop2 ? 1 : 0;
+        if (c.active && (!(g > 0.0) || !isfinite(g))) {
+            c.active = 0;
+            c.breakdown = 1;
+        }
+        if (c.active) atomicAdd(count, 1);
+    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_pcg_alpha(PcgScalars *sc, const double *partials, long stride,
+                                                            long nblk, int *count) {
+    __shared__ double lds[16];
+    const int r = blockIdx.x;
+    PcgScalars &c = sc[r];
+    if (!c.active) {
+        if (threadIdx.x == 0) c.alpha = 0.0;
+        return;
+    }
+    const double q2 = sum_partials(partials + (long)r * stride, nblk, lds);
+    if (threadIdx.x == 0) {
+        if (!(q2 > 0.0) || !isfinite(q2)) {
+            c.alpha = 0.0;
+            c.active = 0;
+            c.breakdown = 1;
+            atomicSub(count, 1);
+        } else {
+            c.alpha = c.gam / q2;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pcg_update_yr(const PcgVec v) {
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (gid < v.n) {
+        const int rhs = (int)(gid % v.nrhs);
+        const double alpha = v.sc[rhs].alpha;
+        cpx<float> r[12];
+        SpinorIO<WL_F32>::load(v.rho[h], gid, r);
+        if (alpha != 0.0) {
+            cpx<float> y[12], p[12], q[12];
+            SpinorIO<WL_F32>::load(v.y[h], gid, y);
+            SpinorIO<WL_F32>::load(v.p[h], gid, p);
+            SpinorIO<WL_F32>::load(v.q[h], gid, q);
+            const float al = (float)alpha;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                y[k] = {fmaf(al, p[k].re, y[k].re), fmaf(al, p[k].im, y[k].im)};
+                r[k] = {fmaf(-al, q[k].re, r[k].re), fmaf(-al, q[k].im, r[k].im)};
+            }
+            SpinorIO<WL_F32>::store(v.y[h], gid, y);
+            SpinorIO<WL_F32>::store(v.rho[h], gid, r);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nrm += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
+    }
+    __shared__ double lds[256];
+    block_sum_rhs(nrm, gid, v.nrhs, lds, v.partials + (long)blockIdx.y * gridDim.x + blockIdx.x, v.part_stride);
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_pcg_check(PcgScalars *sc, const double *partials, long stride,
+                                                            long nblk, int *count) {
+    __shared__ double lds[16];
+    const int r = blockIdx.x;
+    PcgScalars &c = sc[r];
+    if (!c.active) return;
+    const double s2 = sum_partials(partials + (long)r * stride, nblk, lds);
+    if (threadIdx.x == 0) {
+        c.rho2 = s2;
+        c.iters += 1;
+        if (!isfinite(s2)) c.breakdown = 1;
+        if (!isfinite(s2) || s2 <= c.stop2) {
+            c.active = 0;
+            atomicSub(count, 1);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_pcg_beta(PcgScalars *sc, const double *partials, long stride,
+                                                           long nblk, int *count) {
+    __shared__ double lds[16];
+    const int r = blockIdx.x;
+    PcgScalars &c = sc[r];
+    if (!c.active) return;
+    const double g1 = sum_partials(partials + (long)r * stride, nblk, lds);
+    if (threadIdx.x == 0) {
+        if (!isfinite(g1)) {
+            c.beta = 0.0;
+            c.active = 0;
+            c.breakdown = 1;
+            atomicSub(count, 1);
+        } else {
+            c.beta = g1 / c.gam;
+            c.gam = g1;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pcg_update_p(const PcgVec v) {
+    const int h = blockIdx.y;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= v.n) return;
+    const PcgScalars &c = v.sc[(int)(gid % v.nrhs)];
+    if (!c.active) return;
+    const float beta = (float)c.beta;
+    cpx<float> sv[12], p[12];
+    SpinorIO<WL_F32>::load(v.q[h], gid, sv);
+    SpinorIO<WL_F32>::load(v.p[h], gid, p);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = {fmaf(beta, p[k].re, sv[k].re), fmaf(beta, p[k].im, sv[k].im)};
+    SpinorIO<WL_F32>::store(v.p[h], gid, p);
+}
+
+hipError_t pcg_start(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk,
+                     const double *rho2_start, const double *stop2, const int *live, int *count, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_start, dim3(nrhs), dim3(RED_THREADS), 0, s, sc, partials, stride, nblk, rho2_start,
+                       stop2, live, count);
+    return hipGetLastError();
+}
+hipError_t pcg_alpha(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *count,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(nrhs), dim3(RED_THREADS), 0, s, sc, partials, stride, nblk, count);
+    return hipGetLastError();
+}
+hipError_t pcg_update_yr(const PcgVec &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_update_yr, dim3((unsigned)blas_blocks(v.n), 2), dim3(256), 0, s, v);
+    return hipGetLastError();
+}
+hipError_t pcg_check(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *count,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_check, dim3(nrhs), dim3(RED_THREADS), 0, s, sc, partials, stride, nblk, count);
+    return hipGetLastError();
+}
+hipError_t pcg_beta(PcgScalars *sc, int nrhs, const double *partials, long stride, long nblk, int *count,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_beta, dim3(nrhs), dim3(RED_THREADS), 0, s, sc, partials, stride, nblk, count);
+    return hipGetLastError();
+}
+hipError_t pcg_update_p(const PcgVec &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_update_p, dim3((unsigned)blas_blocks(v.n), 2), dim3(256), 0, s, v);
+    return hipGetLastError();
+}
+
+template <int SP>
+__global__ void __launch_bounds__(256) k_zero_masked(char *f, size_t half, long n, int nrhs, const int *mask) {
+    using T = typename SpinorIO<SP>::real;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n || !mask[gid % nrhs]) return;
+    cpx<T> z[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) z[k] = {T(0), T(0)};
+    SpinorIO<SP>::store(f + blockIdx.y * half, gid, z);
+}
+
+hipError_t blas_zero_masked(int prec, void *f, size_t half, long n, int nrhs, const int *mask, hipStream_t s) {
+    dim3 grid((unsigned)blas_blocks(n), 2);
+    if (prec == WL_F64) hipLaunchKernelGGL(k_zero_masked<WL_F64>, grid, dim3(256), 0, s, (char *)f, half, n, nrhs, mask);
+    else if (prec == WL_F32) hipLaunchKernelGGL(k_zero_masked<WL_F32>, grid, dim3(256), 0, s, (char *)f, half, n, nrhs, mask);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

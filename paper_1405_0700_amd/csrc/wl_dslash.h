@@ -32,6 +32,7 @@ struct HopArgs {
     void *r[2];           // EPI_CGR: the residual field of parity 0 / 1 (same storage as out)
     const char *alpha;    // EPI_CGR: alpha of rhs k at alpha + k * alpha_stride (a double)
     long alpha_stride;
+    unsigned shm;         // dynamic LDS bytes reserved per block (host side: caps the occupancy)
 };
 
 struct LaunchCfg {
@@ -47,7 +48,15 @@ struct LaunchCfg {
                        // -1 on when the launch's working set exceeds 200 MB
     int rpt = 1;       // right-hand sides per thread (each link load reused for all
                        // of them); used when nrhs % rpt == 0 and tps == 1
+    int occ = 0;       // 0: no cap; k in 1..8: about k waves per SIMD at most (unused LDS is
+                       // reserved per block, so that fewer blocks fit on a CU; fewer
+                       // points in flight keep the re-read neighbours of multi-rhs
+                       // launches within L2)
 };
+
+// dynamic LDS bytes per block that cap a launch of `block` threads at `occ`
+// waves per SIMD (160 KB of LDS per CU, 4 SIMDs); 0 for no cap
+unsigned occupancy_lds(int occ, int block, unsigned static_lds);
 
 // whether a launch uses the non-temporal hints
 bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int nparity, int epi);

@@ -15,6 +15,8 @@
 // fastest, consecutive threads handle consecutive points, and consecutive
 // blocks are optionally remapped so that each XCD (which has its own L2) works
 // on one contiguous range of sites and the neighbour re-reads hit its L2.
+#include <algorithm>
+
 #include "wl_dslash_kernels.h"
 
 namespace wl {
@@ -22,10 +24,10 @@ namespace wl {
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 static void launch_one(int tps, dim3 grid, dim3 block, hipStream_t s, const HopArgs &a) {
     if (tps == 2) {
-        hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>), grid, block, a.shm, s, a);
         return;
     }
-    hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI, NT>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI, NT>), grid, block, a.shm, s, a);
 }
 
 template <int SP, int GP, int RECON, bool DAG, bool NT>
@@ -61,6 +63,16 @@ bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int npari
     const double pts = (double)padded(a.npts) * nparity;
     const double ws = 8.0 * (double)a.slab_bytes + pts * spinor_point_bytes(prec) * ((epi & EPI_XPAY) ? 3 : 2);
     return ws > 200e6;
+}
+
+unsigned occupancy_lds(int occ, int block, unsigned static_lds) {
+    if (occ <= 0) return 0;
+    const int waves = block / 64;
+    const int per_cu = std::max(1, 4 * occ / waves);  // blocks per CU
+    const unsigned total = 160u * 1024u / per_cu;
+    // the static LDS of the kernel (block sums) counts against the same budget
+    const unsigned dyn = total > static_lds + 256 ? (total - static_lds) & ~255u : 256u;
+    return dyn;
 }
 
 int effective_tps(int prec, const LaunchCfg &cfg) {
@@ -159,6 +171,8 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
     dim3 grid((unsigned)hop_launch_blocks(tps, cfg, a.npts, a.nrhs), (unsigned)nparity);
     dim3 blk(block);
     const bool nt = use_nontemporal(prec, cfg, a, nparity, epi);
+    // the block sums of the norm epilogue use up to 4 KB of static LDS (8 KB with rpt 4)
+    a.shm = occupancy_lds(cfg.occ, block, 8192);
     switch (rpt) {
     case 2: return launch_hop_r2(prec, recon, dagger, nt, epi, a, grid, blk, stream);
     case 3: return launch_hop_r3(prec, recon, dagger, nt, epi, a, grid, blk, stream);

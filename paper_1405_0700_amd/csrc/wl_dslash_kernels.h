@@ -638,11 +638,11 @@ __global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
 template <int SP, int GP, int RECON, bool DAG, bool NT, int R>
 static hipError_t launch_r_epi(int epi, const HopArgs &a, dim3 grid, dim3 blk, hipStream_t s) {
     switch (epi) {
-    case 0: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, 0, NT, R>), grid, blk, 0, s, a); break;
-    case EPI_XPAY: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_XPAY, NT, R>), grid, blk, 0, s, a); break;
-    case EPI_NORM: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_NORM, NT, R>), grid, blk, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, 0, NT, R>), grid, blk, a.shm, s, a); break;
+    case EPI_XPAY: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_XPAY, NT, R>), grid, blk, a.shm, s, a); break;
+    case EPI_NORM: hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_NORM, NT, R>), grid, blk, a.shm, s, a); break;
     case EPI_XPAY | EPI_NORM:
-        hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM, NT, R>), grid, blk, 0, s, a);
+        hipLaunchKernelGGL((hop_kernel_mr<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM, NT, R>), grid, blk, a.shm, s, a);
         break;
     default: return hipErrorInvalidValue;
     }

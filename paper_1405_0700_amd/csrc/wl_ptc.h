@@ -9,9 +9,11 @@ constexpr int PTC_NPATH = 9;
 constexpr int PTC_MAXC = 16;  // most channels of a layer
 
 // One PTC layer on FULL FP32 fields.  A field of C channels is C consecutive
-// single-rhs FULL fields (channel-major: channel b, parity par starts at byte
-// (2 b + par) * half), so the threads of a wave, one per site, read and write
-// consecutive points of each channel.
+// FULL fields of nrhs right-hand sides each (channel-major: channel b, parity
+// par starts at byte (2 b + par) * half; inside, points (site, rhs) with rhs
+// fastest, as every multi-rhs field), so the threads of a wave, one per point,
+// read and write consecutive points of each channel; the right-hand sides of
+// a site share its links.  The network acts on every right-hand side alike.
 //   out[a](x) = sum_b sum_p W_p^{ab} (T_p in[b])(x),  or its adjoint
 // g_in[b] = sum_a sum_p T_p^+ W_p^{ab +} g_out[a]  (adjoint != 0; then
 // `cout`/`cin` are the channel counts of the adjoint map and the weights keep
@@ -27,6 +29,7 @@ struct PtcArgs {
     int cout, cin;      // channels of this launch's output / input
     int adjoint;
     long vh;
+    int nrhs;           // right-hand sides per channel (1 for the training kernels)
 };
 
 hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16_weights, hipStream_t s);

@@ -115,21 +115,22 @@ __global__ void __launch_bounds__(256) k_ptc_layer(const PtcArgs a) {
         wl[k] = e;
     }
     __syncthreads();
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.vh) return;
+    const long pt = (long)blockIdx.x * blockDim.x + threadIdx.x;  // point (site, rhs)
+    if (pt >= a.vh * a.nrhs) return;
+    const int i = (int)(pt / a.nrhs), rhs = (int)(pt - (long)i * a.nrhs);
     int c[4];
-    eo_coords(a.g, (int)i, par, c);
+    eo_coords(a.g, i, par, c);
     cpx<float> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
     for (int q = 0; q < PTC_NPATH; ++q) {
-        const PathHop h = ptc_hop(a.g, (int)i, par, c, q);
+        const PathHop h = ptc_hop(a.g, i, par, c, q);
         cpx<float> chi[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) chi[k] = {0.f, 0.f};
         for (int b = 0; b < a.cin; ++b) {
             cpx<float> v[12];
-            SpinorIO<WL_F32>::load(a.in + (2 * (size_t)b + h.npar) * a.half, h.j, v);
+            SpinorIO<WL_F32>::load(a.in + (2 * (size_t)b + h.npar) * a.half, (long)h.j * a.nrhs + rhs, v);
             const float2 *m = &wl[(q * a.cin + b) * 16];
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -146,13 +147,13 @@ __global__ void __launch_bounds__(256) k_ptc_layer(const PtcArgs a) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = acc[k] + t[k];
     }
-    SpinorIO<WL_F32>::store(a.out + (2 * (size_t)o + par) * a.half, i, acc);
+    SpinorIO<WL_F32>::store(a.out + (2 * (size_t)o + par) * a.half, pt, acc);
 }
 
 // One input channel fanned out to cout > 1 output channels: a block takes 64
-// sites; first its 256 threads compute the 8 one-hop transports of each site
-// once (into LDS), then every (site, output channel) pair mixes the nine
-// transported spinors with its own weights.  The per-channel kernel above
+// points (site, rhs); first its 256 threads compute the 8 one-hop transports of
+// each point once (into LDS), then every (point, output channel) pair mixes the
+// nine transported spinors with its own weights.  The per-channel kernel above
 // would repeat every transport for each output channel.
 constexpr int PTC_FAN_SITES = 64;
 
@@ -177,16 +178,17 @@ __global__ void __launch_bounds__(256) k_ptc_layer_fan(const PtcArgs a) {
     const long base = (long)blockIdx.x * PTC_FAN_SITES;
     for (int task = threadIdx.x; task < 8 * PTC_FAN_SITES; task += blockDim.x) {
         const int sl = task % PTC_FAN_SITES, q = task / PTC_FAN_SITES + 1;
-        const long i = base + sl;
+        const long pt = base + sl;
         cpx<float> t[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) t[k] = {0.f, 0.f};
-        if (i < a.vh) {
+        if (pt < a.vh * a.nrhs) {
+            const int i = (int)(pt / a.nrhs), rhs = (int)(pt - (long)i * a.nrhs);
             int c[4];
-            eo_coords(a.g, (int)i, par, c);
-            const PathHop h = ptc_hop(a.g, (int)i, par, c, q);
+            eo_coords(a.g, i, par, c);
+            const PathHop h = ptc_hop(a.g, i, par, c, q);
             cpx<float> v[12];
-            SpinorIO<WL_F32>::load(a.in + (size_t)h.npar * a.half, h.j, v);
+            SpinorIO<WL_F32>::load(a.in + (size_t)h.npar * a.half, (long)h.j * a.nrhs + rhs, v);
             ptc_transport(a.g, a.gauge, a.slab_bytes, h, v, t);
         }
 #pragma unroll
@@ -195,12 +197,12 @@ __global__ void __launch_bounds__(256) k_ptc_layer_fan(const PtcArgs a) {
     __syncthreads();
     for (int task = threadIdx.x; task < a.cout * PTC_FAN_SITES; task += blockDim.x) {
         const int sl = task % PTC_FAN_SITES, o = task / PTC_FAN_SITES;
-        const long i = base + sl;
-        if (i >= a.vh) continue;
+        const long pt = base + sl;
+        if (pt >= a.vh * a.nrhs) continue;
         cpx<float> acc[12], v[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
-        SpinorIO<WL_F32>::load(a.in + (size_t)par * a.half, i, v);  // identity path
+        SpinorIO<WL_F32>::load(a.in + (size_t)par * a.half, pt, v);  // identity path
         for (int q = 0; q < PTC_NPATH; ++q) {
             if (q > 0) {
 #pragma unroll
@@ -220,19 +222,20 @@ __global__ void __launch_bounds__(256) k_ptc_layer_fan(const PtcArgs a) {
                     for (int cc = 0; cc < 3; ++cc) acc[3 * s_ + cc] = cfma(ms, v[3 * t_ + cc], acc[3 * s_ + cc]);
                 }
         }
-        SpinorIO<WL_F32>::store(a.out + (2 * (size_t)o + par) * a.half, i, acc);
+        SpinorIO<WL_F32>::store(a.out + (2 * (size_t)o + par) * a.half, pt, acc);
     }
 }
 
 hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16, hipStream_t s) {
-    if (a.cout < 1 || a.cin < 1 || a.cout * a.cin > PTC_MAXC) return hipErrorInvalidValue;
+    if (a.cout < 1 || a.cin < 1 || a.cout * a.cin > PTC_MAXC || a.nrhs < 1) return hipErrorInvalidValue;
+    const long npts = a.vh * a.nrhs;
     if (a.cin == 1 && a.cout > 1) {
-        dim3 grid((unsigned)((a.vh + PTC_FAN_SITES - 1) / PTC_FAN_SITES), 2);
+        dim3 grid((unsigned)((npts + PTC_FAN_SITES - 1) / PTC_FAN_SITES), 2);
         if (bf16) hipLaunchKernelGGL(k_ptc_layer_fan<true>, grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL(k_ptc_layer_fan<false>, grid, dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    dim3 grid((unsigned)((a.vh + 255) / 256), 2, (unsigned)a.cout);
+    dim3 grid((unsigned)((npts + 255) / 256), 2, (unsigned)a.cout);
     if (bf16) hipLaunchKernelGGL(k_ptc_layer<true>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_ptc_layer<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
@@ -357,15 +360,18 @@ hipError_t launch_ptc_loss(const void *out, const void *e, void *g, long n, cons
 }
 
 // ---------------------------------------------------------------- Adam
+// omb1 = 1 - b1 and omb2 = 1 - b2 are formed in FP64 by the host: 1 - b2 computed in FP32 from the
+// rounded b2 = 0.999f would be 1.3e-5 off (1 - 0.99900001f)
 __global__ void __launch_bounds__(256) k_adam(float *w, uint16_t *wb, double *grad_c, float *m, float *v, long n,
-                                              float lr, float b1, float b2, float eps, float c1, float c2) {
+                                              float lr, float b1, float b2, float omb1, float omb2, float eps,
+                                              float c1, float c2) {
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     // grad_c holds (re, im) pairs of dL/dW*; the real-parameter gradient is twice that
     const float g = (float)(2.0 * grad_c[k]);
     grad_c[k] = 0.0;
-    const float mk = b1 * m[k] + (1.f - b1) * g;
-    const float vk = b2 * v[k] + (1.f - b2) * g * g;
+    const float mk = b1 * m[k] + omb1 * g;
+    const float vk = b2 * v[k] + omb2 * g * g;
     m[k] = mk;
     v[k] = vk;
     const float wk = w[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
@@ -377,7 +383,7 @@ hipError_t launch_adam(float *w, uint16_t *wb, double *grad_c, float *m, float *
                        double b2, double eps, int t, hipStream_t s) {
     const float c1 = (float)(1.0 - std::pow(b1, (double)t)), c2 = (float)(1.0 - std::pow(b2, (double)t));
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, wb, grad_c, m, v, n, (float)lr,
-                       (float)b1, (float)b2, (float)eps, c1, c2);
+                       (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), (float)eps, c1, c2);
     return hipGetLastError();
 }
 

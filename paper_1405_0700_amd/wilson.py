@@ -118,7 +118,7 @@ _SIGS = {
                                    ctypes.POINTER(SolverParams), ctypes.POINTER(SolverInfo), _vp]),
     "wl_ctx_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_void_p]),
     "wl_ctx_get_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_void_p]),
-    "wl_cgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(SolverParams),
+    "wl_cgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(SolverParams),
                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_params_default": (None, [ctypes.POINTER(FgcrParams)]),
     "wl_pcgnr_params_default": (None, [ctypes.POINTER(PcgnrParams)]),
@@ -151,15 +151,16 @@ _SIGS = {
     "wl_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip,
                                          _ip, _dp, _ip]),
     "wl_batch_timing_read": (ctypes.c_int, [_vp, _ip, _dp]),
-    "wl_pcgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(PcgnrParams),
-                                      ctypes.POINTER(SolverInfo), _vp]),
+    "wl_pcgnr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int,
+                                      ctypes.POINTER(PcgnrParams), ctypes.POINTER(SolverInfo), _vp]),
     "wl_fgcr_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(FgcrParams),
                                      ctypes.POINTER(SolverInfo), _vp]),
     "wl_ptc_create": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.POINTER(_vp)]),
     "wl_ptc_destroy": (ctypes.c_int, [_vp]),
     "wl_ptc_get_weights": (ctypes.c_int, [_vp, _dp, _dp]),
     "wl_ptc_get_grads": (ctypes.c_int, [_vp, _dp, _dp]),
-    "wl_ptc_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "wl_ptc_get_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "wl_ptc_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_ptc_layer": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_ptc_weight_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_ptc_accumulate": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, _vp]),
@@ -327,19 +328,21 @@ def wl_cg_solve(ctx, x, b, op, kappa, nrhs=1, params: SolverParams | None = None
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("swizzle", ctypes.c_int), ("tps", ctypes.c_int), ("tchunk", ctypes.c_int),
-                ("nt", ctypes.c_int), ("rpt", ctypes.c_int)]
+                ("nt", ctypes.c_int), ("rpt", ctypes.c_int), ("occ", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.block, self.swizzle, self.tps, self.tchunk, self.nt, self.rpt)
+        return (self.block, self.swizzle, self.tps, self.tchunk, self.nt, self.rpt, self.occ)
 
 
-def wl_cgnr_solve(ctx, x, eta, kappa, params: SolverParams | None = None, stream=None):
-    """Plain FP64 CG for D x = eta stopped on ||eta - D x|| <= tol ||eta||. Returns (status, info dict)."""
+def wl_cgnr_solve(ctx, x, eta, kappa, params: SolverParams | None = None, stream=None, nrhs=1):
+    """Plain FP64 CG for D x = eta stopped on ||eta - D x|| <= tol ||eta||.
+    Returns (status, info dict), or (status, [info dict per rhs]) for nrhs > 1."""
     p = params if params is not None else wl_solver_params_default()
-    info = SolverInfo()
-    st = _check(lib().wl_cgnr_solve(ctx, _ptr(x), _ptr(eta), float(kappa), ctypes.byref(p), ctypes.byref(info),
+    info = (SolverInfo * nrhs)()
+    st = _check(lib().wl_cgnr_solve(ctx, _ptr(x), _ptr(eta), float(kappa), int(nrhs), ctypes.byref(p), info,
                                     _stream(stream)))
-    return st, info.as_dict()
+    out = [info[i].as_dict() for i in range(nrhs)]
+    return st, (out[0] if nrhs == 1 else out)
 
 
 def wl_fgcr_params_default() -> FgcrParams:
@@ -498,13 +501,15 @@ def wl_pcgnr_params_default() -> PcgnrParams:
     return p
 
 
-def wl_pcgnr_solve(ctx, x, b, kappa, net=None, params: PcgnrParams | None = None, stream=None):
-    """CG on the normal equations of D M y = b, x = M y, M the PTC network `net` (None: M = 1)."""
+def wl_pcgnr_solve(ctx, x, b, kappa, net=None, params: PcgnrParams | None = None, stream=None, nrhs=1):
+    """CG on the normal equations of D M y = b, x = M y, M the PTC network `net` (None: M = 1), for nrhs
+    right-hand sides.  Returns (status, info dict), or (status, [info dict per rhs]) for nrhs > 1."""
     p = params if params is not None else wl_pcgnr_params_default()
-    info = SolverInfo()
-    st = _check(lib().wl_pcgnr_solve(ctx, _ptr(x), _ptr(b), float(kappa), net, ctypes.byref(p), ctypes.byref(info),
+    info = (SolverInfo * nrhs)()
+    st = _check(lib().wl_pcgnr_solve(ctx, _ptr(x), _ptr(b), float(kappa), net, int(nrhs), ctypes.byref(p), info,
                                      _stream(stream)))
-    return st, info.as_dict()
+    out = [info[i].as_dict() for i in range(nrhs)]
+    return st, (out[0] if nrhs == 1 else out)
 
 
 def _cplx_flat(w):
@@ -541,8 +546,17 @@ def wl_ptc_get_grads(net, channels):
     return _ptc_pair(lib().wl_ptc_get_grads, net, channels)
 
 
-def wl_ptc_apply(ctx, net, out, inp, stream=None):
-    return _check(lib().wl_ptc_apply(ctx, net, _ptr(out), _ptr(inp), _stream(stream)))
+def wl_ptc_get_moments(net, channels):
+    """-> (m1, m2, v1, v2): Adam's moments of (Re W, Im W), shapes w.shape + (2,) (float64)."""
+    m1 = np.zeros((9, channels, 1, 4, 4, 2))
+    m2 = np.zeros((9, 1, channels, 4, 4, 2))
+    v1, v2 = np.zeros_like(m1), np.zeros_like(m2)
+    _check(lib().wl_ptc_get_moments(net, *(a.ctypes.data_as(_dp) for a in (m1, m2, v1, v2))))
+    return m1, m2, v1, v2
+
+
+def wl_ptc_apply(ctx, net, out, inp, stream=None, nrhs=1, adjoint=False):
+    return _check(lib().wl_ptc_apply(ctx, net, _ptr(out), _ptr(inp), int(nrhs), int(bool(adjoint)), _stream(stream)))
 
 
 def wl_ptc_layer(ctx, out, inp, weights, cout, cin, adjoint=False, stream=None):
@@ -570,13 +584,13 @@ def wl_ptc_step(net, lr, stream=None) -> float:
     return loss.value
 
 
-def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=WL_TCHUNK_AUTO, nt=-1, rpt=1):
-    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt), int(rpt))
+def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=WL_TCHUNK_AUTO, nt=-1, rpt=1, occ=0):
+    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt), int(rpt), int(occ))
     return _check(lib().wl_ctx_set_launch(ctx, prec, ctypes.addressof(cfg)))
 
 
 def wl_ctx_get_launch(ctx, prec):
-    """-> (block, swizzle, tps, tchunk, nt, rpt)"""
+    """-> (block, swizzle, tps, tchunk, nt, rpt, occ)"""
     cfg = Launch()
     _check(lib().wl_ctx_get_launch(ctx, prec, ctypes.addressof(cfg)))
     return cfg.as_tuple()

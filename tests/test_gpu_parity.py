@@ -143,6 +143,92 @@ def test_dslash_low_precision(prec, recon, dagger):
     assert err < TOL[prec]
 
 
+def _quantize(x, prec):
+    """The value a real FP64 number takes in the library's 16-bit storage (entries already divided by the
+    per-point norm for spinors; links are stored as they are): FP64 -> FP32 -> 16 bits, round to nearest
+    even (FP16, BF16), or round(32767 v) / 32767 (int16, decoded in FP32)."""
+    x32 = np.asarray(x, dtype=np.float32)
+    if prec == W.WL_F16N:
+        return x32.astype(np.float16).astype(np.float64)
+    if prec == W.WL_BF16N:
+        b = np.ascontiguousarray(x32).view(np.uint32).astype(np.uint64)
+        b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+        return b.astype(np.uint32).view(np.float32).astype(np.float64)
+    q = np.clip(np.rint(x32 * np.float32(32767.0)), -32767, 32767).astype(np.float32)
+    return (q * np.float32(1.0 / 32767.0)).astype(np.float64)
+
+
+def _links_as_stored(u, prec):
+    """12-real 16-bit links as the kernels see them: rows 0 and 1 quantized, row 2 = conj(row0 x row1)."""
+    q = _quantize(u.real, prec) + 1j * _quantize(u.imag, prec)
+    r0, r1 = q[..., 0, :], q[..., 1, :]
+    r2 = np.conj(np.cross(r0, r1))
+    return np.stack([r0, r1, r2], axis=-2)
+
+
+@pytest.mark.parametrize("prec", [W.WL_F16N, W.WL_BF16N, W.WL_I16N])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dslash_16bit_per_site(prec, dagger):
+    """Per-site check of the 16-bit formats (a normwise tolerance would let an error confined to a few
+    sites pass): the oracle is fed the inputs exactly as stored (spinors unpacked from the 16-bit field,
+    links quantized the same way with the third row rebuilt), so what remains at every site is the
+    rounding of the output to its own per-point norm s_out (at most half a step of the format, relative
+    to s_out) plus FP32 arithmetic (~1e-6 of the largest input norm among the site's neighbours)."""
+    dims = (6, 10, 4, 14)
+    ph = random_phases(23)
+    u, lat = setup(dims, seed=24, phases=ph)
+    phi = synth.gaussian_spinor(dims, seed=25)
+    # at some sites the input is scaled by 1e3 or 1e-3: the per-point norm must follow each site
+    rng = np.random.default_rng(26)
+    scale = rng.choice([1e-3, 1.0, 1e3], size=phi.shape[:4], p=[0.1, 0.8, 0.1])
+    phi = phi * scale[..., None, None]
+    inp = lat.pack(phi, W.WL_FULL, prec)
+    phi_q = lat.unpack(inp, W.WL_FULL, prec).reshape(phi.shape)
+    out = lat.new(W.WL_FULL, prec)
+    (W.wl_dslash_dagger_apply if dagger else W.wl_dslash_apply)(lat.ctx, out, inp, W.WL_FULL, prec, 12)
+    got = lat.unpack(out, W.WL_FULL, prec).reshape(phi.shape)
+    want = orc.hop(phi_q, _links_as_stored(u, prec), ph, dagger=dagger)
+    half_step = {W.WL_F16N: 2.0 ** -11, W.WL_BF16N: 2.0 ** -8, W.WL_I16N: 0.5 / 32767}[prec]
+    comp = lambda a: np.maximum(np.abs(a.real), np.abs(a.imag)).max(axis=(-1, -2))
+    err = comp(got - want)
+    s_out = comp(want)
+    s_in = comp(phi_q)
+    s_nb = np.zeros_like(s_in)
+    for axis in range(4):
+        for sh in (1, -1):
+            s_nb = np.maximum(s_nb, np.roll(s_in, sh, axis=axis))
+    bound = 1.02 * half_step * s_out + 1e-5 * s_nb
+    worst = float((err / bound).max())
+    print("prec", prec, "dagger", dagger, "worst per-site error / bound", worst)
+    assert worst <= 1.0
+    # and the normwise figure against the unquantized oracle stays within the format's tolerance
+    assert rel(got, orc.hop(phi, u, ph, dagger=dagger)) < TOL[prec]
+
+
+def test_dslash_f64_headline_size_default_launch():
+    """FP64 half-dslash and full hopping term at 24^3x48 (the headline lattice, links exp(0.2 i H) seed 201)
+    with the default launch, which at this size uses the z-chunked order and the non-temporal hints."""
+    dims = (24, 24, 24, 48)
+    u = synth.su3_links(dims, 0.2, 201)
+    lat = W.Lattice.create(u, AP)
+    try:
+        phi = synth.gaussian_spinor(dims, seed=202)
+        want = orc.hop(phi, u, AP)
+        we, wo = orc.eo_split(want, dims)
+        pe, po = orc.eo_split(phi, dims)
+        oe = lat.new(W.WL_EVEN)
+        W.wl_dslash_apply(lat.ctx, oe, lat.pack(po, W.WL_ODD), W.WL_EVEN)
+        assert rel(lat.unpack(oe, W.WL_EVEN), we) < TOL[W.WL_F64]
+        od = lat.new(W.WL_ODD)
+        W.wl_dslash_dagger_apply(lat.ctx, od, lat.pack(pe, W.WL_EVEN), W.WL_ODD)
+        assert rel(lat.unpack(od, W.WL_ODD), orc.eo_split(orc.hop(phi, u, AP, dagger=True), dims)[1]) < TOL[W.WL_F64]
+        out = lat.new(W.WL_FULL)
+        W.wl_dslash_apply(lat.ctx, out, lat.pack(phi), W.WL_FULL)
+        assert rel(lat.unpack(out).reshape(want.shape), want) < TOL[W.WL_F64]
+    finally:
+        lat.close()
+
+
 def test_dslash_multi_rhs_equals_single():
     dims = (6, 4, 4, 8)
     u, lat = setup(dims)
@@ -335,6 +421,57 @@ def test_cg_zero_rhs_and_maxiter_and_breakdown():
     assert st == W.WL_BREAKDOWN
 
 
+def test_cg_singular_operator_stops_cleanly():
+    """U = 1, all directions periodic, kappa = 1/8: D has a zero mode (every constant spinor), so D^+ D x = b
+    has no solution for a Gaussian b.  CG must stop by itself (maxiter, or breakdown if <p, A p> vanishes)
+    and return; the oracle confirms that the residual of what it returns is at least b's component in the
+    null space."""
+    dims = (4, 4, 4, 4)
+    u = synth.unit_links(dims)
+    lat = W.Lattice.create(u, (1, 1, 1, 1))
+    try:
+        b = synth.gaussian_spinor(dims, seed=67)
+        p = W.wl_solver_params_default()
+        p.maxiter = 300
+        x = lat.new(W.WL_FULL)
+        st, info = W.wl_cg_solve(lat.ctx, x, lat.pack(b), W.WL_OP_D, 0.125, params=p)
+        assert st in (W.WL_NOT_CONVERGED, W.WL_BREAKDOWN), st
+        assert info[0]["iters"] <= p.maxiter
+        null = b.mean(axis=(0, 1, 2, 3))  # projection onto the constant spinors
+        floor = float(np.linalg.norm(np.broadcast_to(null, b.shape)) / np.linalg.norm(b))
+        xs = lat.unpack(x).reshape(b.shape)
+        if np.all(np.isfinite(xs)):
+            r = orc.dirac(orc.dirac(xs, u, 0.125, (1, 1, 1, 1)), u, 0.125, (1, 1, 1, 1), dagger=True) - b
+            assert np.linalg.norm(r) / np.linalg.norm(b) >= 0.99 * floor
+        print("status", st, "iters", info[0]["iters"], "null-space floor", floor)
+    finally:
+        lat.close()
+
+
+def test_occupancy_cap_keeps_results_bitwise():
+    """The occupancy cap only reserves LDS: results are bit for bit those of the uncapped launch."""
+    dims = (6, 10, 4, 14)
+    ph = random_phases(71)
+    u, lat = setup(dims, seed=72, phases=ph)
+    stack = np.stack([synth.gaussian_spinor(dims, seed=73 + r).reshape(-1, 4, 3) for r in range(3)])
+    for prec in (W.WL_F64, W.WL_F32, W.WL_F16N):
+        recon = 12 if prec == W.WL_F16N else 18
+        saved = W.wl_ctx_get_launch(lat.ctx, prec)
+        try:
+            outs = []
+            for occ in (0, 1, 3, 8):
+                W.wl_ctx_set_launch(lat.ctx, prec, 256, 1, saved[2], saved[3], saved[4], 1, occ)
+                o = lat.new(W.WL_FULL, prec, 3)
+                W.wl_dirac_apply(lat.ctx, o, lat.pack(stack, W.WL_FULL, prec, 3), W.WL_OP_D, True, 0.13, prec, recon,
+                                 3)
+                torch.cuda.synchronize()
+                outs.append(o.cpu())
+            for o in outs[1:]:
+                assert torch.equal(o, outs[0])
+        finally:
+            W.wl_ctx_set_launch(lat.ctx, prec, *saved)
+
+
 def test_cg_free_field_plane_wave_one_iteration():
     dims = (4, 4, 4, 8)
     kappa = 0.12
@@ -371,7 +508,7 @@ def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
     saved = W.wl_ctx_get_launch(lat.ctx, prec)
     W.wl_ctx_set_launch(lat.ctx, prec, block, swizzle, tps, tchunk, nt)
     try:
-        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk, nt, 1)
+        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk, nt, 1, 0)
         phi = synth.gaussian_spinor(dims, seed=79)
         for dagger in (False, True):
             want = orc.hop(phi, u, ph, dagger=dagger)

@@ -293,3 +293,107 @@ def test_preconditioned_cgnr_zero_source_and_bad_parameters():
     with pytest.raises(W.WilsonError):
         W.wl_pcgnr_solve(lat.ctx, lat.new(W.WL_FULL), lat.pack(synth.gaussian_spinor((4, 4, 4, 8), seed=60)), 0.12,
                          None, p)
+
+
+def test_adam_steps_match_oracle():
+    """Six Adam steps: the GPU's FP32 master weights and both moments follow repeated calls of the
+    oracle's adam_step fed the gradients the GPU accumulated at each step (so the moments' carry-over
+    and the bias corrections at t = 1 .. 6 are pinned, not only the first step's sign rule); each
+    step's gradient is also checked against the oracle's gradient at the GPU's current BF16 weights."""
+    ph = random_phases(61)
+    u, lat = lattice(DIMS, 62, ph)
+    w1, w2 = synth.ptc_weights(4, seed=63)
+    w1 = w1 + random_weights(4, 1, 64, 0.05)
+    w2 = w2 + random_weights(1, 4, 65, 0.05)
+    net = W.wl_ptc_create(w1, w2)
+    pairs = [(synth.gaussian_spinor(DIMS, seed=70 + i), synth.gaussian_spinor(DIMS, seed=80 + i)) for i in range(2)]
+    ins = [(channels(lat, [r]), channels(lat, [e])) for r, e in pairs]
+    ow1, ow2 = W.wl_ptc_get_weights(net, 4)  # the FP32 master weights the steps start from
+    om1 = np.zeros(ow1.shape + (2,))
+    om2 = np.zeros(ow2.shape + (2,))
+    ov1, ov2 = np.zeros_like(om1), np.zeros_like(om2)
+    lr = 2e-3
+    for t in range(1, 7):
+        for r, e in ins:
+            W.wl_ptc_accumulate(lat.ctx, net, r, e, 1.0 / len(ins))
+        g1, g2 = W.wl_ptc_get_grads(net, 4)
+        cw1, cw2 = W.wl_ptc_get_weights(net, 4)
+        _, g1o, g2o = ptc.loss_and_grads([(f32(r), f32(e)) for r, e in pairs], bf16_round(cw1), bf16_round(cw2), u,
+                                         ph)
+        assert rel(g1, g1o) < 1e-4 and rel(g2, g2o) < 1e-4, t
+        W.wl_ptc_step(net, lr)
+        ow1, om1, ov1 = ptc.adam_step(ow1, g1, om1, ov1, t, lr=lr)
+        ow2, om2, ov2 = ptc.adam_step(ow2, g2, om2, ov2, t, lr=lr)
+        n1, n2 = W.wl_ptc_get_weights(net, 4)
+        m1, m2, v1, v2 = W.wl_ptc_get_moments(net, 4)
+        # FP32 state against the FP64 restatement: moments to a few FP32 roundings; the weights move by
+        # at most lr per step, so their difference is judged against lr
+        assert rel(m1, om1) < 1e-5 and rel(m2, om2) < 1e-5, t
+        assert rel(v1, ov1) < 1e-5 and rel(v2, ov2) < 1e-5, t
+        assert np.abs(n1 - ow1).max() < 1e-3 * lr and np.abs(n2 - ow2).max() < 1e-3 * lr, t
+    W.wl_ptc_destroy(net)
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_network_on_several_rhs(adjoint):
+    """M (and M^+) on a FULL field of 3 right-hand sides equals the one-rhs application of each, bit for bit
+    (the same arithmetic per point), and the oracle's network (its adjoint: the two layer adjoints in reverse
+    order) within the FP32 tolerance."""
+    ph = random_phases(91)
+    u, lat = lattice(DIMS, 92, ph)
+    w1, w2 = synth.ptc_weights(4, seed=93)
+    w1 = w1 + random_weights(4, 1, 94, 0.05)
+    w2 = w2 + random_weights(1, 4, 95, 0.05)
+    net = W.wl_ptc_create(w1, w2)
+    fields = [f32(synth.gaussian_spinor(DIMS, seed=96 + r)) for r in range(3)]
+    stack = np.stack([f.reshape(-1, 4, 3) for f in fields])
+    out = lat.new(W.WL_FULL, W.WL_F32, 3)
+    W.wl_ptc_apply(lat.ctx, net, out, lat.pack(stack, W.WL_FULL, W.WL_F32, 3), nrhs=3, adjoint=adjoint)
+    multi = lat.unpack(out, W.WL_FULL, W.WL_F32, 3)
+    w1b, w2b = bf16_round(w1), bf16_round(w2)
+    for r, f in enumerate(fields):
+        o1 = lat.new(W.WL_FULL, W.WL_F32)
+        W.wl_ptc_apply(lat.ctx, net, o1, lat.pack(f, W.WL_FULL, W.WL_F32), adjoint=adjoint)
+        assert np.array_equal(multi[r], lat.unpack(o1, W.WL_FULL, W.WL_F32))
+        if adjoint:
+            hidden = ptc.layer_adjoint([f], w2b, u, ph)
+            want = ptc.layer_adjoint(hidden, w1b, u, ph)[0]
+        else:
+            want, _ = ptc.net_apply(f, w1b, w2b, u, ph)
+        assert rel(multi[r].reshape(want.shape), want) < TOL32
+    W.wl_ptc_destroy(net)
+
+
+def test_cgnr_and_preconditioned_cgnr_on_several_rhs():
+    """Four right-hand sides in one solve (kappa 0.137, eps 0.2 links on 8^4, where D's spectrum surrounds
+    the origin): plain FP64 CGNR and CG on the normal equations of D M (network and M = 1) bring every rhs
+    to an oracle-restated system residual <= 1e-10; the multi-rhs iteration counts stay within a few of the
+    one-rhs solves of the same sources (the same arithmetic per point; only the reductions' order differs)."""
+    dims, kappa = (8, 8, 8, 8), 0.137
+    u, lat = lattice(dims, 97, AP, 0.2)
+    srcs = [synth.gaussian_spinor(dims, seed=98 + r) for r in range(4)]
+    stack = np.stack([s.reshape(-1, 4, 3) for s in srcs])
+    B = lat.pack(stack, W.WL_FULL, W.WL_F64, 4)
+    w1, w2 = synth.ptc_weights(8, seed=530)
+    net = W.wl_ptc_create(w1, w2)
+    x = lat.new(W.WL_FULL, W.WL_F64, 4)
+    st, infos = W.wl_cgnr_solve(lat.ctx, x, B, kappa, nrhs=4)
+    xs = lat.unpack(x, W.WL_FULL, W.WL_F64, 4)
+    assert st == W.WL_OK
+    for r in range(4):
+        assert system_resid(u, kappa, xs[r].reshape(srcs[r].shape), srcs[r]) <= 1.05e-10
+    for m in (None, net):
+        x = lat.new(W.WL_FULL, W.WL_F64, 4)
+        p = W.wl_pcgnr_params_default()
+        p.fallback = 0
+        st, infos = W.wl_pcgnr_solve(lat.ctx, x, B, kappa, m, p, nrhs=4)
+        xs = lat.unpack(x, W.WL_FULL, W.WL_F64, 4)
+        assert st == W.WL_OK
+        for r in range(4):
+            res = system_resid(u, kappa, xs[r].reshape(srcs[r].shape), srcs[r])
+            x1 = lat.new(W.WL_FULL)
+            st1, one = W.wl_pcgnr_solve(lat.ctx, x1, lat.pack(srcs[r]), kappa, m, p)
+            print("net", m is not None, "rhs", r, infos[r], "oracle", res, "one-rhs iters", one["iters"])
+            assert res <= 1.05e-10 and infos[r]["true_rel_resid"] <= 1e-10 and infos[r]["fallback"] == 0
+            assert abs(infos[r]["iters"] - one["iters"]) <= max(3, one["iters"] // 20)
+    W.wl_ptc_destroy(net)

@@ -139,7 +139,19 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *           reserves unused LDS per block so that fewer blocks fit on a compute
  *           unit; fewer points in flight keep the re-read neighbour spinors
  *           within the XCD's L2).  Default 4 for the 16-bit formats, 0 else.
- * Results do not depend on block, swizzle, tchunk, nt or occ; tps changes the
+ *   sweep   0: off; k > 0: time sweep (with tps = 1 and rpt = 1): a thread owns
+ *           one point of a time slice and walks k consecutive slices of its
+ *           column, keeping the column's input spinors at t - 1, t and t + 1
+ *           in registers, so both time hops and the hop inside the x pair
+ *           read no memory; blocks tile a slice's points, consecutive blocks
+ *           take neighbouring tiles of the same time range.  For many
+ *           right-hand sides, whose neighbour spinors otherwise fall out of
+ *           L2 before their second use.  FP64 and FP32 storage only (ignored
+ *           for the 16-bit formats).  Results are those of tps = 1 bit for
+ *           bit.  Measured slower than the default launch on the 12-rhs FP32
+ *           half-dslash (354 against 310 us at 24^3x48): an option, off by
+ *           default.
+ * Results do not depend on block, swizzle, tchunk, nt, occ or sweep; tps changes the
  * summation order of the 8 hops and rpt the compiler's contraction of
  * multiply-adds (rounding only).  Defaults are chosen per
  * precision by measurement (see wl_ctx_get_launch). */
@@ -152,6 +164,7 @@ typedef struct {
     int nt;
     int rpt;
     int occ;
+    int sweep;
 } wl_launch;
 wl_status wl_ctx_set_launch(wl_ctx *ctx, wl_prec prec, const wl_launch *cfg);
 wl_status wl_ctx_get_launch(const wl_ctx *ctx, wl_prec prec, wl_launch *cfg);
@@ -296,12 +309,19 @@ typedef struct {
  * FP64 x at each refresh and before the solve returns. */
 void wl_solver_params_default(wl_solver_params *p);
 
-/* Conjugate gradient on the normal equations M^+ M x = b, M = D or D_hat.
+/* Conjugate gradient on the normal equations M^+ M x = b, M = D or D_hat
+ * (the paper's solvers around the hopping term of Eq. (1); D = 1 - kappa H and
+ * the even/odd Schur complement D_hat = 1 - kappa^2 H_eo H_oe by readings C-4
+ * and C-6).  Stops on the iterated residual ||b - A x|| <= tol ||b||, then
+ * recomputes it in FP64 and continues from the true residual if it misses tol
+ * (reading C-7).  Mixed precision: FP64 reliable updates (reading R-21).
  *   x : in: initial guess, out: solution (internal FP64 field of the op's subset)
  *   b : right-hand side (internal FP64 field), not modified
  *   nrhs right-hand sides are solved as independent systems sharing every
- *   operator application; each stops on its own residual.
- * Synchronous: returns when done.  info may be NULL (else nrhs entries). */
+ *   operator application; each stops on its own residual (reading C-13).
+ * Synchronous: returns when done.  info may be NULL (else nrhs entries).
+ * Returns WL_OK, WL_NOT_CONVERGED (maxiter reached; x and info filled) or
+ * WL_BREAKDOWN (a non-finite value or <p, A p> <= 0), or a negative error. */
 wl_status wl_cg_solve(wl_ctx *ctx, void *x, const void *b, wl_op op, double kappa, int nrhs,
                       const wl_solver_params *params, wl_solver_info *info, void *stream);
 
@@ -315,7 +335,8 @@ wl_status wl_cg_solve(wl_ctx *ctx, void *x, const void *b, wl_op op, double kapp
 wl_status wl_cgnr_solve(wl_ctx *ctx, void *x, const void *eta, double kappa, int nrhs,
                         const wl_solver_params *params, wl_solver_info *info, void *stream);
 
-/* Flexible GCR with restarts, right-preconditioned by the PTC network.
+/* Flexible GCR with restarts, right-preconditioned by the PTC network
+ * (reading C-16: FGCR(m) on D; the network by reading C-14).
  * One cycle keeps up to `restart` search directions: z = M(r), w = D z,
  * w and z modified-Gram-Schmidt orthogonalised against the kept pairs,
  * alpha = <w, r> / <w, w>, x += alpha z, r -= alpha w (FP32 fields and FP32
@@ -475,7 +496,8 @@ wl_status wl_batch_dirac_apply(wl_batch *batch, void *const *out, const void *co
                                const double *kappa, wl_prec prec, int recon, int nrhs, void *stream);
 
 /* CG on the normal equations M_k^+ M_k x[k] = b[k] of every system together
- * (the independent solves of each system's nrhs right-hand sides run in
+ * (readings C-7 and C-13 as for wl_cg_solve, per system and rhs;
+ * the independent solves of each system's nrhs right-hand sides run in
  * lockstep: one persistent launch per hopping stage of an iteration, the
  * scalar and vector steps per system).  Parameters as for wl_cg_solve (inner
  * precision, FP64 reliable updates, use_graph: the lockstep iteration is

@@ -717,6 +717,7 @@ extern "C" wl_status wl_autotune(wl_ctx *c, wl_prec prec, int recon, int nrhs, c
         chosen->nt = best.nt;
         chosen->rpt = best.rpt;
         chosen->occ = best.occ;
+        chosen->sweep = best.sweep;
     }
     if (best_us) *best_us = best_t;
     if (from_cache) *from_cache = cached;

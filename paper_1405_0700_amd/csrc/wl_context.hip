@@ -227,9 +227,9 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
     // 16-bit storage: few registers per thread, so without a cap so many waves are in flight
     // that their neighbour spinors crowd each other out of L2; about 4 waves per SIMD measured
     // best (FP16 half-dslash at 32^3x64: 82 -> 67 us)
-    c->cfg[WL_F16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1, 1, 4};
-    c->cfg[WL_BF16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1, 1, 4};
-    c->cfg[WL_I16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1, 1, 4};
+    c->cfg[WL_F16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1, 1, 0, 4};
+    c->cfg[WL_BF16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1, 1, 0, 4};
+    c->cfg[WL_I16N] = {256, 1, 1, WL_TCHUNK_AUTO, -1, 1, 0, 4};
     c->slab[WL_F64][0] = slab;
     *out = c;
     return WL_OK;
@@ -366,9 +366,10 @@ extern "C" wl_status wl_convert_spinor(const wl_ctx *c, void *dst, wl_prec dprec
     return WL_OK;
 }
 
-const char *wli::launch_problem(int block, int tps, int nt, int rpt, int occ) {
+const char *wli::launch_problem(int block, int tps, int nt, int rpt, int occ, int sweep) {
     if (block < 64 || block > 256 || block % 64) return "block not in {64, 128, 192, 256}";
     if (occ < 0 || occ > 8) return "occ not in 0..8";
+    if (sweep < 0 || sweep > 65536) return "sweep not in 0..65536";
     if (tps != 1 && tps != 2) return "tps not in {1, 2}";
     if (nt < -1 || nt > 1) return "nt not in {-1, 0, 1}";
     if (rpt < 1 || rpt > 4) return "rpt not in 1..4";
@@ -417,9 +418,9 @@ extern "C" wl_status wl_ctx_set_launch(wl_ctx *c, wl_prec prec, const wl_launch 
     g_err.clear();
     if (!c || !l) return fail(WL_ERR_ARG, "null argument");
     if (!prec_ok(prec)) return fail(WL_ERR_ARG, "bad precision %d", (int)prec);
-    if (const char *why = launch_problem(l->block, l->tps, l->nt, l->rpt, l->occ))
-        return fail(WL_ERR_ARG, "launch (block %d, tps %d, nt %d, rpt %d, occ %d): %s", l->block, l->tps, l->nt,
-                    l->rpt, l->occ, why);
+    if (const char *why = launch_problem(l->block, l->tps, l->nt, l->rpt, l->occ, l->sweep))
+        return fail(WL_ERR_ARG, "launch (block %d, tps %d, nt %d, rpt %d, occ %d, sweep %d): %s", l->block, l->tps,
+                    l->nt, l->rpt, l->occ, l->sweep, why);
     LaunchCfg &g = c->cfg[prec];
     g.block = l->block;
     g.swizzle = l->swizzle ? 1 : 0;
@@ -428,6 +429,7 @@ extern "C" wl_status wl_ctx_set_launch(wl_ctx *c, wl_prec prec, const wl_launch 
     g.nt = l->nt;
     g.rpt = l->rpt;
     g.occ = l->occ;
+    g.sweep = l->sweep;
     return WL_OK;
 }
 
@@ -443,5 +445,6 @@ extern "C" wl_status wl_ctx_get_launch(const wl_ctx *c, wl_prec prec, wl_launch 
     l->nt = g.nt;
     l->rpt = g.rpt;
     l->occ = g.occ;
+    l->sweep = g.sweep;
     return WL_OK;
 }

@@ -33,6 +33,7 @@ struct HopArgs {
     const char *alpha;    // EPI_CGR: alpha of rhs k at alpha + k * alpha_stride (a double)
     long alpha_stride;
     unsigned shm;         // dynamic LDS bytes reserved per block (host side: caps the occupancy)
+    int sweep;            // time sweep: slices per block (0: one point per thread, no sweep)
 };
 
 struct LaunchCfg {
@@ -48,6 +49,9 @@ struct LaunchCfg {
                        // -1 on when the launch's working set exceeds 200 MB
     int rpt = 1;       // right-hand sides per thread (each link load reused for all
                        // of them); used when nrhs % rpt == 0 and tps == 1
+    int sweep = 0;     // k > 0: time sweep, each thread walks k slices of one point's column
+                       // (its time neighbours kept in registers); used when tps == 1 and
+                       // rpt == 1; 0: off
     int occ = 0;       // 0: no cap; k in 1..8: about k waves per SIMD at most (unused LDS is
                        // reserved per block, so that fewer blocks fit on a CU; fewer
                        // points in flight keep the re-read neighbours of multi-rhs
@@ -97,9 +101,21 @@ inline int effective_rpt(const LaunchCfg &cfg, int nrhs, int tps) {
     return cfg.rpt > 1 && tps == 1 && nrhs % cfg.rpt == 0 ? cfg.rpt : 1;
 }
 
-// blocks per parity of a hopping launch (npts points of nrhs right-hand sides)
-inline long hop_launch_blocks(int tps, const LaunchCfg &cfg, long npts, int nrhs) {
+// slices per block of a time-sweep launch (0: no sweep), for a lattice of lt time slices
+inline int effective_sweep(const LaunchCfg &cfg, int nrhs, int tps, int lt, int prec = 0) {
+    // 16-bit storage: the decode's multiply would contract differently with a spinor held
+    // in registers than straight after its load, so the sweep is offered for FP64 / FP32 only
+    if (cfg.sweep <= 0 || tps != 1 || effective_rpt(cfg, nrhs, tps) != 1 || prec > 1) return 0;
+    return cfg.sweep < lt ? cfg.sweep : lt;
+}
+
+// blocks per parity of a hopping launch (npts points of nrhs right-hand sides; lt time
+// slices, sites_per_slice sites of one parity per slice)
+inline long hop_launch_blocks(int tps, const LaunchCfg &cfg, long npts, int nrhs, int lt = 0,
+                              long sites_per_slice = 0, int prec = 0) {
     const int r = effective_rpt(cfg, nrhs, tps);
+    if (const int sw = lt > 0 ? effective_sweep(cfg, nrhs, tps, lt, prec) : 0)
+        return hop_blocks(sites_per_slice * nrhs, cfg.block, 1) * ((lt + sw - 1) / sw);
     return r > 1 ? hop_blocks(npts / r, cfg.block, 1) : hop_blocks(npts, cfg.block, tps);
 }
 

@@ -23,6 +23,10 @@ namespace wl {
 
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 static void launch_one(int tps, dim3 grid, dim3 block, hipStream_t s, const HopArgs &a) {
+    if (a.sweep > 0) {
+        hipLaunchKernelGGL((hop_sweep_kernel<SP, GP, RECON, DAG, EPI, NT>), grid, block, a.shm, s, a);
+        return;
+    }
     if (tps == 2) {
         hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>), grid, block, a.shm, s, a);
         return;
@@ -168,7 +172,8 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
     set_processing_order(a, cfg.tchunk);
     const int rpt = effective_rpt(cfg, a.nrhs, tps);
     if (rpt > 1 && (a.nrhs > 256 || block < 64 || (epi & EPI_CGR))) return hipErrorInvalidValue;
-    dim3 grid((unsigned)hop_launch_blocks(tps, cfg, a.npts, a.nrhs), (unsigned)nparity);
+    a.sweep = effective_sweep(cfg, a.nrhs, tps, a.g.L[3], prec);
+    dim3 grid((unsigned)hop_launch_blocks(tps, cfg, a.npts, a.nrhs, a.g.L[3], a.g.st, prec), (unsigned)nparity);
     dim3 blk(block);
     const bool nt = use_nontemporal(prec, cfg, a, nparity, epi);
     // the block sums of the norm epilogue use up to 4 KB of static LDS (8 KB with rpt 4)

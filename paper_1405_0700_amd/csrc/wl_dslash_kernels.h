@@ -99,13 +99,10 @@ __device__ __forceinline__ void su3_mul2(const cpx<T> u[9], const cpx<T> h[6], c
         }
 }
 
-template <int SP, int GP, int RECON, bool DAG, bool NT, int MU, bool FWD>
-__device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs,
-                                    cpx<typename SpinorIO<SP>::real> acc[12]) {
-    using T = typename SpinorIO<SP>::real;
-    const Geom &g = a.g;
-    int j;
-    bool wrap;
+// Neighbour of even/odd site i (coordinates c, xh = c[0] / 2) one hop along +-MU:
+// its index j (in the other parity's field) and whether the hop wraps.
+template <int MU, bool FWD>
+__device__ __forceinline__ void hop_neighbour(const Geom &g, int i, int xh, const int c[4], int &j, bool &wrap) {
     if constexpr (MU == 0) {
         int x = c[0] + (FWD ? 1 : -1);
         wrap = FWD ? (x == g.L[0]) : (x < 0);
@@ -117,10 +114,19 @@ __device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, co
         j = FWD ? i + stride : i - stride;
         if (wrap) j += FWD ? -g.L[MU] * stride : g.L[MU] * stride;
     }
+}
+
+// One hop with the neighbour's spinor f given: project, multiply by the link
+// (loaded here), boundary phase, accumulate.
+template <int SP, int GP, int RECON, bool DAG, bool NT, int MU, bool FWD>
+__device__ __forceinline__ void hop_apply(const HopArgs &a, int par, int i, int j, bool wrap,
+                                          const cpx<typename SpinorIO<SP>::real> f[12],
+                                          cpx<typename SpinorIO<SP>::real> acc[12]) {
+    using T = typename SpinorIO<SP>::real;
+    const Geom &g = a.g;
     // Forward hop (H): (1 - gamma) -> S = -1; backward: (1 + gamma) -> S = +1; H^+ swaps them.
     constexpr int S = (FWD != DAG) ? -1 : 1;
-    cpx<T> f[12], h[6], u[9], v[6];
-    SpinorIO<SP>::load(a.in[1 - par], (long)j * a.nrhs + rhs, f);
+    cpx<T> h[6], u[9], v[6];
     const int lpar = FWD ? par : 1 - par;
     const char *slab = (const char *)a.gauge + (size_t)(lpar * 4 + MU) * a.slab_bytes;
     LinkIO<GP, RECON>::template load<NT>(slab, FWD ? i : j, u);
@@ -132,6 +138,18 @@ __device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, co
         for (int k = 0; k < 6; ++k) v[k] = cmul(z, v[k]);
     }
     accumulate<T, MU, S>(acc, v);
+}
+
+template <int SP, int GP, int RECON, bool DAG, bool NT, int MU, bool FWD>
+__device__ __forceinline__ void hop(const HopArgs &a, int par, int i, int xh, const int c[4], int rhs,
+                                    cpx<typename SpinorIO<SP>::real> acc[12]) {
+    using T = typename SpinorIO<SP>::real;
+    int j;
+    bool wrap;
+    hop_neighbour<MU, FWD>(a.g, i, xh, c, j, wrap);
+    cpx<T> f[12];
+    SpinorIO<SP>::load(a.in[1 - par], (long)j * a.nrhs + rhs, f);
+    hop_apply<SP, GP, RECON, DAG, NT, MU, FWD>(a, par, i, j, wrap, f, acc);
 }
 
 // The same hop for R consecutive right-hand sides of one site: the link is
@@ -305,32 +323,14 @@ __device__ __forceinline__ long logical_block(int swizzle) {
     return xcd * q + (xcd < r ? xcd : r) + bid / 8;
 }
 
-// The work of one thread of the one-thread-per-point kernels: output point at
-// position gid of the processing order of parity par.  Returns the point's
-// contribution to ||out||^2 (EPI_NORM), else 0.
-template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
-__device__ __forceinline__ double hop_point(const HopArgs &a, int par, long gid) {
+// The epilogue of one output point pt (rhs rhs) of parity par: out = a x + b acc
+// (twists, in-place CG residual update and norm as selected); returns the point's
+// contribution to the norm (EPI_NORM), else 0.
+template <int SP, int EPI, bool NT>
+__device__ __forceinline__ double hop_epilogue(const HopArgs &a, int par, long pt, int rhs,
+                                               cpx<typename SpinorIO<SP>::real> acc[12]) {
     using T = typename SpinorIO<SP>::real;
     double nrm = 0.0;
-    if (gid >= a.npts) return nrm;
-    const long ps = gid / a.nrhs;
-    const int rhs = (int)(gid - ps * a.nrhs);
-    const int i = site_of(a, ps);
-    const long pt = (long)i * a.nrhs + rhs;
-    int c[4];
-    eo_coords(a.g, i, par, c);
-    const int xh = c[0] >> 1;
-    cpx<T> acc[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
-    hop<SP, GP, RECON, DAG, NT, 0, true>(a, par, i, xh, c, rhs, acc);
-    hop<SP, GP, RECON, DAG, NT, 0, false>(a, par, i, xh, c, rhs, acc);
-    hop<SP, GP, RECON, DAG, NT, 1, true>(a, par, i, xh, c, rhs, acc);
-    hop<SP, GP, RECON, DAG, NT, 1, false>(a, par, i, xh, c, rhs, acc);
-    hop<SP, GP, RECON, DAG, NT, 2, true>(a, par, i, xh, c, rhs, acc);
-    hop<SP, GP, RECON, DAG, NT, 2, false>(a, par, i, xh, c, rhs, acc);
-    hop<SP, GP, RECON, DAG, NT, 3, true>(a, par, i, xh, c, rhs, acc);
-    hop<SP, GP, RECON, DAG, NT, 3, false>(a, par, i, xh, c, rhs, acc);
     const T b = (T)a.b;
     if (a.tm_h != 0.0) twist<T, 12>(acc, 0, (T)a.tm_h);
     if constexpr (EPI & EPI_XPAY) {
@@ -376,6 +376,35 @@ __device__ __forceinline__ double hop_point(const HopArgs &a, int par, long gid)
     return nrm;
 }
 
+// The work of one thread of the one-thread-per-point kernels: output point at
+// position gid of the processing order of parity par.  Returns the point's
+// contribution to ||out||^2 (EPI_NORM), else 0.
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__device__ __forceinline__ double hop_point(const HopArgs &a, int par, long gid) {
+    using T = typename SpinorIO<SP>::real;
+    double nrm = 0.0;
+    if (gid >= a.npts) return nrm;
+    const long ps = gid / a.nrhs;
+    const int rhs = (int)(gid - ps * a.nrhs);
+    const int i = site_of(a, ps);
+    const long pt = (long)i * a.nrhs + rhs;
+    int c[4];
+    eo_coords(a.g, i, par, c);
+    const int xh = c[0] >> 1;
+    cpx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    hop<SP, GP, RECON, DAG, NT, 0, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 0, false>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 1, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 1, false>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 2, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 2, false>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 3, true>(a, par, i, xh, c, rhs, acc);
+    hop<SP, GP, RECON, DAG, NT, 3, false>(a, par, i, xh, c, rhs, acc);
+    return hop_epilogue<SP, EPI, NT>(a, par, pt, rhs, acc);
+}
+
 // One thread per output point.
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
@@ -388,6 +417,93 @@ __global__ void __launch_bounds__(256) hop_kernel(const HopArgs a) {
         __shared__ double lds[256];
         const long blk = (long)blockIdx.y * gridDim.x + lb;
         block_sum_rhs(nrm, gid, a.nrhs, lds, a.partials + blk, a.part_stride);
+    }
+}
+
+// Time sweep: a thread owns one point (q, rhs) of a time slice (q the site's
+// index within its slice) and walks `sweep` consecutive slices t0 .. t0+sweep-1.
+// The input spinors of its own column at t-1, t and t+1 stay in registers, so
+// each is read from memory once per sweep and serves both time hops (and the
+// x hop inside the site pair) without a cache; the y, z and other x neighbours
+// are the loads of neighbouring threads and blocks at the same t.  Blocks tile
+// the points of a slice (rhs fastest); consecutive blocks take consecutive tiles
+// of the same time range, so with the XCD swizzle each XCD sweeps a contiguous
+// range of positions and finds its z neighbours in its own L2.  The arithmetic
+// of each output point is that of the one-thread-per-point kernel, bit for bit.
+template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
+__global__ void __launch_bounds__(256) hop_sweep_kernel(const HopArgs a) {
+    using T = typename SpinorIO<SP>::real;
+    if (a.flag && *a.flag == 0) return;
+    const int par = a.out_par0 + blockIdx.y;
+    const Geom &g = a.g;
+    const long S = g.st;                       // sites per time slice of one parity
+    const long spts = S * a.nrhs;              // points per slice
+    const long ntile = (spts + blockDim.x - 1) / blockDim.x;
+    const long lb = logical_block(a.swizzle);  // gridDim.x = ntile * time ranges
+    const long tile = lb % ntile, range = lb / ntile;
+    const int t0 = (int)range * a.sweep, t1 = min(g.L[3], t0 + a.sweep);
+    const long sp = tile * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (sp < spts && t0 < t1) {
+        const long q = sp / a.nrhs;
+        const int rhs = (int)(sp - q * a.nrhs);
+        const void *in = a.in[1 - par];
+        const int lt = g.L[3];
+        cpx<T> fm[12], f0[12], fp[12];  // input of this column at t - 1, t, t + 1
+        SpinorIO<SP>::load(in, (q + (long)((t0 - 1 + lt) % lt) * S) * a.nrhs + rhs, fm);
+        SpinorIO<SP>::load(in, (q + (long)t0 * S) * a.nrhs + rhs, f0);
+        SpinorIO<SP>::load(in, (q + (long)((t0 + 1) % lt) * S) * a.nrhs + rhs, fp);
+        for (int t = t0; t < t1; ++t) {
+            const int i = (int)(q + (long)t * S);
+            int c[4];
+            eo_coords(g, i, par, c);
+            const int xh = c[0] >> 1;
+            cpx<T> acc[12], f[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+            int j;
+            bool wrap;
+            // x: one of the two neighbours is the other site of the pair (index i, f0)
+            hop_neighbour<0, true>(g, i, xh, c, j, wrap);
+            if (j == i) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) f[k] = f0[k];
+            } else {
+                SpinorIO<SP>::load(in, (long)j * a.nrhs + rhs, f);
+            }
+            hop_apply<SP, GP, RECON, DAG, NT, 0, true>(a, par, i, j, wrap, f, acc);
+            hop_neighbour<0, false>(g, i, xh, c, j, wrap);
+            if (j == i) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) f[k] = f0[k];
+            } else {
+                SpinorIO<SP>::load(in, (long)j * a.nrhs + rhs, f);
+            }
+            hop_apply<SP, GP, RECON, DAG, NT, 0, false>(a, par, i, j, wrap, f, acc);
+            hop<SP, GP, RECON, DAG, NT, 1, true>(a, par, i, xh, c, rhs, acc);
+            hop<SP, GP, RECON, DAG, NT, 1, false>(a, par, i, xh, c, rhs, acc);
+            hop<SP, GP, RECON, DAG, NT, 2, true>(a, par, i, xh, c, rhs, acc);
+            hop<SP, GP, RECON, DAG, NT, 2, false>(a, par, i, xh, c, rhs, acc);
+            // t: the column's own inputs at t + 1 and t - 1
+            hop_neighbour<3, true>(g, i, xh, c, j, wrap);
+            hop_apply<SP, GP, RECON, DAG, NT, 3, true>(a, par, i, j, wrap, fp, acc);
+            hop_neighbour<3, false>(g, i, xh, c, j, wrap);
+            hop_apply<SP, GP, RECON, DAG, NT, 3, false>(a, par, i, j, wrap, fm, acc);
+            nrm += hop_epilogue<SP, EPI, NT>(a, par, (long)i * a.nrhs + rhs, rhs, acc);
+            if (t + 1 < t1) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    fm[k] = f0[k];
+                    f0[k] = fp[k];
+                }
+                SpinorIO<SP>::load(in, (q + (long)((t + 2) % lt) * S) * a.nrhs + rhs, fp);
+            }
+        }
+    }
+    if constexpr (EPI & EPI_NORM) {
+        __shared__ double lds[256];
+        const long blk = (long)blockIdx.y * gridDim.x + lb;
+        block_sum_rhs(nrm, sp, a.nrhs, lds, a.partials + blk, a.part_stride);
     }
 }
 

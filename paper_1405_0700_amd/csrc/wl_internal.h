@@ -156,7 +156,7 @@ wl_status ensure_pinned(wl_ctx *c, size_t bytes);
 wl_status get_links(wl_ctx *c, int prec, int recon, const void **ptr, size_t *slab);
 VecArgs vec_args(const wl_ctx *c, int prec, int nrhs);
 void set_vec(VecArgs &a, int k, const void *base, size_t hb);
-const char *launch_problem(int block, int tps, int nt, int rpt, int occ = 0);
+const char *launch_problem(int block, int tps, int nt, int rpt, int occ = 0, int sweep = 0);
 wl_status fill_hop_args(wl_ctx *c, int prec, int recon, void *out, const void *in, const void *x,
                                int out_subset, int nrhs, double a, double b, double *partials, long part_stride,
                                const int *flag, HopArgs &h, int *np_out, double tm_x = 0.0, double tm_h = 0.0);

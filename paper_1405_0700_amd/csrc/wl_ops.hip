@@ -94,7 +94,8 @@ wl_status wli::hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, void 
     const LaunchCfg &cfg = c->cfg[prec];
     HIP_TRY(launch_hop(prec, recon, dag, epi, h, np, cfg, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    if (nblk_out) *nblk_out = hop_launch_blocks(effective_tps(prec, cfg), cfg, h.npts, nrhs) * np;
+    if (nblk_out)
+        *nblk_out = hop_launch_blocks(effective_tps(prec, cfg), cfg, h.npts, nrhs, h.g.L[3], h.g.st, prec) * np;
     return WL_OK;
 }
 
@@ -306,8 +307,9 @@ extern "C" wl_status wl_eo_reconstruct_tm(const wl_ctx *cc, void *x_o, const voi
 long wli::part_stride_for(const wl_ctx *c, int nrhs) {
     const long n = c->Vh * (long)nrhs;
     const long hb = hop_blocks(n, 64, 2) * 2;  // the most blocks any hopping launch may use
+    const long sb = hop_blocks((long)c->g.st * nrhs, 64, 1) * c->g.L[3] * 2;  // time sweep, one slice per block
     const long bb = blas_blocks(n) * 2;
-    return std::max(hb, bb);
+    return std::max(std::max(hb, sb), bb);
 }
 
 extern "C" wl_status wl_blas_axpy(const wl_ctx *c, double a, const void *x, void *y, wl_subset subset, wl_prec prec,

@@ -328,10 +328,10 @@ def wl_cg_solve(ctx, x, b, op, kappa, nrhs=1, params: SolverParams | None = None
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("swizzle", ctypes.c_int), ("tps", ctypes.c_int), ("tchunk", ctypes.c_int),
-                ("nt", ctypes.c_int), ("rpt", ctypes.c_int), ("occ", ctypes.c_int)]
+                ("nt", ctypes.c_int), ("rpt", ctypes.c_int), ("occ", ctypes.c_int), ("sweep", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.block, self.swizzle, self.tps, self.tchunk, self.nt, self.rpt, self.occ)
+        return (self.block, self.swizzle, self.tps, self.tchunk, self.nt, self.rpt, self.occ, self.sweep)
 
 
 def wl_cgnr_solve(ctx, x, eta, kappa, params: SolverParams | None = None, stream=None, nrhs=1):
@@ -584,13 +584,13 @@ def wl_ptc_step(net, lr, stream=None) -> float:
     return loss.value
 
 
-def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=WL_TCHUNK_AUTO, nt=-1, rpt=1, occ=0):
-    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt), int(rpt), int(occ))
+def wl_ctx_set_launch(ctx, prec, block, swizzle, tps, tchunk=WL_TCHUNK_AUTO, nt=-1, rpt=1, occ=0, sweep=0):
+    cfg = Launch(int(block), int(swizzle), int(tps), int(tchunk), int(nt), int(rpt), int(occ), int(sweep))
     return _check(lib().wl_ctx_set_launch(ctx, prec, ctypes.addressof(cfg)))
 
 
 def wl_ctx_get_launch(ctx, prec):
-    """-> (block, swizzle, tps, tchunk, nt, rpt, occ)"""
+    """-> (block, swizzle, tps, tchunk, nt, rpt, occ, sweep)"""
     cfg = Launch()
     _check(lib().wl_ctx_get_launch(ctx, prec, ctypes.addressof(cfg)))
     return cfg.as_tuple()

@@ -253,9 +253,9 @@ def test_autotune_picks_a_valid_launch_and_caches_it(tmp_path):
     cache = tmp_path / "tune.txt"
     cfg, us, cached = W.wl_autotune(lat.ctx, W.WL_F32, 18, 1, cache)
     assert not cached and us > 0
-    block, swizzle, tps, tchunk, nt, rpt, occ = cfg
+    block, swizzle, tps, tchunk, nt, rpt, occ, sweep = cfg
     assert block in (64, 128, 256) and tps in (1, 2) and swizzle in (0, 1) and tchunk in (0, 4, W.WL_TCHUNK_AUTO) \
-        and nt in (0, 1) and occ == 0
+        and nt in (0, 1) and occ == 0 and sweep == 0
     assert rpt == 1  # one right-hand side: nothing to share
     assert W.wl_ctx_get_launch(lat.ctx, W.WL_F32) == cfg
     # the tuned launch still computes D (FP32 storage tolerance against the oracle)
@@ -274,7 +274,7 @@ def test_autotune_picks_a_valid_launch_and_caches_it(tmp_path):
         f.write("garbage line without separator\n")
         f.write("%s | 64 0 1 0 0 3 12.5\n" % key)
     cfg3, us3, cached3 = W.wl_autotune(lat.ctx, W.WL_F32, 18, 3, cache)
-    assert cached3 and cfg3 == (64, 0, 1, 0, 0, 3, 0) and us3 == 12.5
+    assert cached3 and cfg3 == (64, 0, 1, 0, 0, 3, 0, 0) and us3 == 12.5
     # an entry that is not a valid launch shape (block 1000) is ignored and the shape tuned again
     with open(cache, "a") as f:
         f.write("%s | 1000 0 1 0 0 1 1.0\n" % key.replace("nrhs 3", "nrhs 2"))

@@ -472,6 +472,66 @@ def test_occupancy_cap_keeps_results_bitwise():
             W.wl_ctx_set_launch(lat.ctx, prec, *saved)
 
 
+@pytest.mark.parametrize("prec,recon", [(W.WL_F64, 18), (W.WL_F32, 18), (W.WL_F16N, 12)])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_time_sweep_matches_one_point_per_thread(prec, recon, nrhs):
+    """The time-sweep kernel (each thread walks `sweep` slices of one column, time neighbours in registers)
+    computes every output point with the one-thread-per-point arithmetic: bit for bit equal for sweeps of 1,
+    3 and more than Lt slices, on a lattice whose slice does not fill whole blocks, for the hopping term, its
+    adjoint and both Dirac operators (epilogues with the x field).  16-bit storage does not use the sweep
+    (the setting is ignored), so its results are trivially equal."""
+    dims = (6, 10, 4, 14)
+    ph = random_phases(87)
+    u, lat = setup(dims, seed=88, phases=ph)
+    stack = np.stack([synth.gaussian_spinor(dims, seed=89 + r).reshape(-1, 4, 3) for r in range(nrhs)])
+    saved = W.wl_ctx_get_launch(lat.ctx, prec)
+    outs = {}
+    try:
+        for sweep in (0, 1, 3, 100):
+            W.wl_ctx_set_launch(lat.ctx, prec, 128, 1, 1, 0, -1, 1, 0, sweep)
+            inp = lat.pack(stack, W.WL_FULL, prec, nrhs)
+            res = []
+            for fn in (lambda o: W.wl_dslash_apply(lat.ctx, o, inp, W.WL_FULL, prec, recon, nrhs),
+                       lambda o: W.wl_dslash_dagger_apply(lat.ctx, o, inp, W.WL_FULL, prec, recon, nrhs),
+                       lambda o: W.wl_dirac_apply(lat.ctx, o, inp, W.WL_OP_D, True, 0.13, prec, recon, nrhs)):
+                o = lat.new(W.WL_FULL, prec, nrhs)
+                fn(o)
+                res.append(o)
+            e = lat.new(W.WL_EVEN, prec, nrhs)
+            W.wl_dirac_apply(lat.ctx, e, inp[: inp.numel() // 2], W.WL_OP_DHAT, False, 0.13, prec, recon, nrhs)
+            res.append(e)
+            torch.cuda.synchronize()
+            outs[sweep] = [r.cpu() for r in res]
+        for sweep in (1, 3, 100):
+            for a, b in zip(outs[sweep], outs[0]):
+                assert torch.equal(a, b), sweep
+    finally:
+        W.wl_ctx_set_launch(lat.ctx, prec, *saved)
+
+
+def test_cg_with_time_sweep():
+    """CG whose hopping launches all use the time sweep (norm and residual-update epilogues included):
+    every rhs reaches the oracle-restated normal-equation residual."""
+    dims, kappa = (6, 10, 4, 14), 0.13
+    ph = random_phases(91)
+    u, lat = setup(dims, seed=92, phases=ph)
+    b = [synth.gaussian_spinor(dims, seed=93 + r) for r in range(2)]
+    saved = W.wl_ctx_get_launch(lat.ctx, W.WL_F64)
+    try:
+        W.wl_ctx_set_launch(lat.ctx, W.WL_F64, 256, 1, 1, W.WL_TCHUNK_AUTO, -1, 1, 0, 4)
+        x = lat.new(W.WL_FULL, W.WL_F64, 2)
+        st, info = W.wl_cg_solve(lat.ctx, x, lat.pack(np.stack([v.reshape(-1, 4, 3) for v in b]), W.WL_FULL,
+                                                      W.WL_F64, 2), W.WL_OP_D, kappa, nrhs=2)
+        assert st == W.WL_OK
+        xs = lat.unpack(x, W.WL_FULL, W.WL_F64, 2)
+        for r in range(2):
+            xr = xs[r].reshape(b[r].shape)
+            res = orc.dirac(orc.dirac(xr, u, kappa, ph), u, kappa, ph, dagger=True) - b[r]
+            assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1.05e-10
+    finally:
+        W.wl_ctx_set_launch(lat.ctx, W.WL_F64, *saved)
+
+
 def test_cg_free_field_plane_wave_one_iteration():
     dims = (4, 4, 4, 8)
     kappa = 0.12
@@ -508,7 +568,7 @@ def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
     saved = W.wl_ctx_get_launch(lat.ctx, prec)
     W.wl_ctx_set_launch(lat.ctx, prec, block, swizzle, tps, tchunk, nt)
     try:
-        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk, nt, 1, 0)
+        assert W.wl_ctx_get_launch(lat.ctx, prec) == (block, swizzle, tps, tchunk, nt, 1, 0, 0)
         phi = synth.gaussian_spinor(dims, seed=79)
         for dagger in (False, True):
             want = orc.hop(phi, u, ph, dagger=dagger)

@@ -268,6 +268,27 @@ wl_status wl_blas_dot(const wl_ctx *ctx, const void *x, const void *y, wl_subset
 wl_status wl_blas_norm2(const wl_ctx *ctx, const void *x, wl_subset subset, wl_prec prec,
                         int nrhs, double *result, void *stream);
 
+/* Allocation-free variant of wl_blas_dot, for callers that cannot allocate
+ * device memory or synchronise: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  It computes exactly what
+ * wl_blas_dot returns (the same kernels and summation order, bit for bit) and
+ * writes it to DEVICE memory: result_dev[0] = Re <x, y>, result_dev[1] =
+ * Im <x, y>, summed over the nrhs right-hand sides (result_dev: 2 doubles,
+ * 8-byte aligned, caller-owned).  Asynchronous on `stream`; no allocation, no
+ * host synchronisation.
+ * Limit: its partial sums live in a static device array of 2^20 doubles
+ * (8 MiB, one per device, held until the process ends), which must hold
+ * 2 nrhs (blocks + 1) values, blocks = ceil(Vh nrhs / 256) per parity of the
+ * subset; larger inputs return WL_ERR_ARG without launching anything.  Every
+ * call on one device shares that device's array: calls that overlap on one
+ * device (on different streams, or from different threads) race and must be
+ * ordered by the caller.  Nothing in the array needs clearing: every call
+ * writes each partial sum before reading it.
+ * Errors: as wl_blas_dot (WL_ERR_ARG for bad arguments, WL_ERR_HIP for a
+ * launch failure). */
+wl_status wl_blas_dot_noalloc(const wl_ctx *ctx, const void *x, const void *y, wl_subset subset,
+                              wl_prec prec, int nrhs, double *result_dev, void *stream);
+
 /* ---------------------------------------------------------------- solvers */
 
 typedef struct {

@@ -165,6 +165,8 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
     }
     int device = 0;
     HIP_TRY(hipGetDevice(&device));
+    // the allocation-free entry points' scratch address on this device (once per device)
+    if (wl_status sst = scratch_setup(device)) return sst;
     wl_ctx *c = new wl_ctx();
     std::memcpy(c->dims, dims, sizeof c->dims);
     std::memcpy(c->phases, phases, sizeof c->phases);

@@ -175,6 +175,8 @@ wl_status apply_mdag_update_r(wl_ctx *c, int op, double kappa, int prec, int rec
                                      hipStream_t s, long *nblk, double mu, const CGScalars *sc);
 long part_stride_for(const wl_ctx *c, int nrhs);
 wl_status reduce_to_host(wl_ctx *c, int nvals, long stride, long nblk, double *out, hipStream_t s);
+// looks up the current device's address of the allocation-free entry points' static scratch array
+wl_status scratch_setup(int device);
 wl_status true_residual(CGRun &R);
 wl_status load_residual(CGRun &R);
 wl_status cg_finish_iteration(CGRun &R, bool reliable);

@@ -160,6 +160,7 @@ _SIGS = {
     "wl_ptc_get_weights": (ctypes.c_int, [_vp, _dp, _dp]),
     "wl_ptc_get_grads": (ctypes.c_int, [_vp, _dp, _dp]),
     "wl_ptc_get_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "wl_blas_dot_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "wl_ptc_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_ptc_layer": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "wl_ptc_weight_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
@@ -303,6 +304,12 @@ def wl_blas_dot(ctx, x, y, subset, prec=WL_F64, nrhs=1, stream=None) -> complex:
     out = (ctypes.c_double * 2)()
     _check(lib().wl_blas_dot(ctx, _ptr(x), _ptr(y), subset, prec, nrhs, out, _stream(stream)))
     return complex(out[0], out[1])
+
+
+def wl_blas_dot_noalloc(ctx, x, y, subset, prec=WL_F64, nrhs=1, result=None, stream=None):
+    """<x, y> summed over rhs into the device tensor `result` (2 float64: re, im); asynchronous, no allocation
+    inside the library (the static-scratch variant of wl_blas_dot)."""
+    return _check(lib().wl_blas_dot_noalloc(ctx, _ptr(x), _ptr(y), subset, prec, nrhs, _ptr(result), _stream(stream)))
 
 
 def wl_blas_norm2(ctx, x, subset, prec=WL_F64, nrhs=1, stream=None) -> float:

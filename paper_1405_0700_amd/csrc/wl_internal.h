@@ -51,6 +51,7 @@ enum Slot {
     S_PCG,                                                             // preconditioned CGNR workspace
     S_FACE,                                                            // t-face send / receive buffers
     S_PCG_SC,                                                          // preconditioned CGNR device scalars
+    S_PTC_PATHS,                                                       // PTC two-pass layer: 9 path fields
     S_NSLOTS
 };
 

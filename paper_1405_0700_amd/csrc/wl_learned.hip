@@ -132,14 +132,23 @@ static PtcArgs ptc_args(wl_ctx *c, void *out, const void *in, int cout, int cin,
 // returned in `hidden` (channels C)
 static wl_status ptc_adjoint_apply(wl_ctx *c, const wl_ptc *n, void *out, const void *in, void *hidden,
                                    hipStream_t s, int nrhs);
+// the nine path fields of a one-output-channel layer's two-pass form (nrhs right-hand sides)
+static wl_status ptc_paths(wl_ctx *c, int nrhs, char **paths) {
+    wl_status st = ensure_buf(c, S_PTC_PATHS, (size_t)PTC_NPATH * 2 * half_bytes(c, WL_F32, nrhs));
+    *paths = st ? nullptr : (char *)c->buf[S_PTC_PATHS];
+    return st;
+}
 // out = M in for nrhs right-hand sides (FULL FP32 fields of nrhs; hidden: channels times that)
 static wl_status ptc_forward(wl_ctx *c, const wl_ptc *n, void *out, const void *in, void *hidden, hipStream_t s,
                              int nrhs = 1) {
     wl_status st;
+    char *paths = nullptr;
+    if ((st = ptc_paths(c, nrhs, &paths))) return st;
     PtcArgs a1 = ptc_args(c, hidden, in, n->channels, 1, n->wb, 0, &st, nrhs);
     if (st) return st;
     HIP_TRY(launch_ptc_layer(a1, true, s));
     PtcArgs a2 = ptc_args(c, out, hidden, 1, n->channels, n->wb + 2 * n->n1, 0, &st, nrhs);
+    a2.paths = paths;
     if (st) return st;
     HIP_TRY(launch_ptc_layer(a2, true, s));
     return WL_OK;
@@ -475,7 +484,10 @@ static wl_status ptc_adjoint_apply(wl_ctx *c, const wl_ptc *n, void *out, const 
     PtcArgs a2 = ptc_args(c, hidden, in, n->channels, 1, n->wb + 2 * n->n1, 1, &st, nrhs);
     if (st) return st;
     HIP_TRY(launch_ptc_layer(a2, true, s));
+    char *paths = nullptr;
+    if ((st = ptc_paths(c, nrhs, &paths))) return st;
     PtcArgs a1 = ptc_args(c, out, hidden, 1, n->channels, n->wb, 1, &st, nrhs);
+    a1.paths = paths;
     if (st) return st;
     HIP_TRY(launch_ptc_layer(a1, true, s));
     return WL_OK;

@@ -30,6 +30,9 @@ struct PtcArgs {
     int adjoint;
     long vh;
     int nrhs;           // right-hand sides per channel (1 for the training kernels)
+    char *paths;        // optional workspace of 9 FULL fields of nrhs (2 * 9 * half bytes): with it a
+                        // layer with one output channel (cin > 1) runs in two passes, the channel
+                        // mixing of every path at the source point first, then the transports
 };
 
 hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16_weights, hipStream_t s);

@@ -226,6 +226,88 @@ __global__ void __launch_bounds__(256) k_ptc_layer_fan(const PtcArgs a) {
     }
 }
 
+// Two-pass form of a layer with one output channel and cin > 1 input channels
+// (the 8 -> 1 layer and the adjoint of the 1 -> 8 layer).  The spin matrices act
+// before the transports, so the mixing of path q, v_q(y) = sum_b M_q^b in_b(y),
+// can be done at the source point y, once, for all the output points that reach
+// y along q; then out(x) = sum_q T_q v_q(x + q) gathers nine single spinors.  The
+// one-pass kernel above instead mixes the 8 input channels again at each of the
+// nine neighbours (72 spinor loads per output point).  Pass 1: a thread per
+// (point, group of 3 paths) reads the point's input channels once and keeps three
+// mixtures; the per-point arithmetic is that of the one-pass kernel.
+constexpr int PTC_MIX_GROUP = 3;
+static_assert(PTC_NPATH % PTC_MIX_GROUP == 0, "paths split into whole groups");
+
+template <bool BF16W>
+__global__ void __launch_bounds__(256) k_ptc_mix(const PtcArgs a) {
+    __shared__ float2 wl[PTC_MIX_GROUP * PTC_MAXC * 16];  // spin matrices [path in group][input][4x4]
+    const int par = blockIdx.y, q0 = blockIdx.z * PTC_MIX_GROUP;
+    const int nw = PTC_MIX_GROUP * a.cin * 16;
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) {
+        const int g = k / (a.cin * 16), rem = k - g * a.cin * 16, b = rem >> 4, st = rem & 15;
+        const int q = q0 + g;
+        float2 e;
+        if (a.adjoint) {
+            const int s_ = st >> 2, t_ = st & 3;
+            e = ptc_weight<BF16W>(a.w, ((long)(ptc_reverse(q) * a.cin + b) * a.cout + 0) * 16 + 4 * t_ + s_);
+            e.y = -e.y;
+        } else {
+            e = ptc_weight<BF16W>(a.w, ((long)(q * a.cout + 0) * a.cin + b) * 16 + st);
+        }
+        wl[k] = e;
+    }
+    __syncthreads();
+    const long pt = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pt >= a.vh * a.nrhs) return;
+    cpx<float> chi[PTC_MIX_GROUP][12];
+#pragma unroll
+    for (int g = 0; g < PTC_MIX_GROUP; ++g)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) chi[g][k] = {0.f, 0.f};
+    for (int b = 0; b < a.cin; ++b) {
+        cpx<float> v[12];
+        SpinorIO<WL_F32>::load(a.in + (2 * (size_t)b + par) * a.half, pt, v);
+#pragma unroll
+        for (int g = 0; g < PTC_MIX_GROUP; ++g) {
+            const float2 *m = &wl[(g * a.cin + b) * 16];
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                for (int t_ = 0; t_ < 4; ++t_) {
+                    const float2 e = m[4 * s_ + t_];
+                    const cpx<float> ms = {e.x, e.y};
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) chi[g][3 * s_ + cc] = cfma(ms, v[3 * t_ + cc], chi[g][3 * s_ + cc]);
+                }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < PTC_MIX_GROUP; ++g)
+        SpinorIO<WL_F32>::store(a.paths + (2 * (size_t)(q0 + g) + par) * a.half, pt, chi[g]);
+}
+
+// Pass 2: out(x) = sum_q T_q v_q(x + q), the nine mixtures of the neighbours
+__global__ void __launch_bounds__(256) k_ptc_gather(const PtcArgs a) {
+    const int par = blockIdx.y;
+    const long pt = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pt >= a.vh * a.nrhs) return;
+    const int i = (int)(pt / a.nrhs), rhs = (int)(pt - (long)i * a.nrhs);
+    int c[4];
+    eo_coords(a.g, i, par, c);
+    cpx<float> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+    for (int q = 0; q < PTC_NPATH; ++q) {
+        const PathHop h = ptc_hop(a.g, i, par, c, q);
+        cpx<float> chi[12], t[12];
+        SpinorIO<WL_F32>::load(a.paths + (2 * (size_t)q + h.npar) * a.half, (long)h.j * a.nrhs + rhs, chi);
+        ptc_transport(a.g, a.gauge, a.slab_bytes, h, chi, t);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = acc[k] + t[k];
+    }
+    SpinorIO<WL_F32>::store(a.out + (size_t)par * a.half, pt, acc);
+}
+
 hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16, hipStream_t s) {
     if (a.cout < 1 || a.cin < 1 || a.cout * a.cin > PTC_MAXC || a.nrhs < 1) return hipErrorInvalidValue;
     const long npts = a.vh * a.nrhs;
@@ -233,6 +315,13 @@ hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16, hipStream_t s) {
         dim3 grid((unsigned)((npts + PTC_FAN_SITES - 1) / PTC_FAN_SITES), 2);
         if (bf16) hipLaunchKernelGGL(k_ptc_layer_fan<true>, grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL(k_ptc_layer_fan<false>, grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    if (a.cout == 1 && a.cin > 1 && a.paths) {
+        dim3 g1((unsigned)((npts + 255) / 256), 2, PTC_NPATH / PTC_MIX_GROUP);
+        if (bf16) hipLaunchKernelGGL(k_ptc_mix<true>, g1, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(k_ptc_mix<false>, g1, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_ptc_gather, dim3((unsigned)((npts + 255) / 256), 2), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     dim3 grid((unsigned)((npts + 255) / 256), 2, (unsigned)a.cout);

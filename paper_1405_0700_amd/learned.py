@@ -13,11 +13,18 @@ master weights:
   error norm     L = (1/N) sum ||M(r) - e||^2 / ||e||^2
   residual norm  L = (1/N) sum ||D (M(r) - e)||^2 / ||D e||^2
                    = (1/N) sum ||D M(r) - r||^2 / ||r||^2      (r = D e)
-The error norm weights each eigenmode of the error by 1/|lambda|^2 relative
-to the residual, so a local network fitted to it mostly tries to amplify the
-smooth low modes it cannot represent; the residual norm measures the pair's
-error by the residual a step x += M(r) leaves, which is what the flexible
-GCR step with this preconditioner reduces.  The residual norm is the default.
+Which iterations the pairs come from decides what the network learns.  Late
+iterations leave residuals and errors made of the smooth low modes of D, which
+a network of one-hop transports cannot invert; fitted to them, the error norm
+amplifies those modes and the residual norm shrinks them, and either way the
+conditioning of D M, which is what CG on its normal equations needs, gets
+worse (measured: a net trained on iterations 5..160 takes 578 CG iterations
+where no net takes 265, 16^3x32 at kappa 0.137).  The first iterations' residuals
+(the source itself at k = 0, then k = 1, 2, 3) still hold every mode; fitted
+to them, the residual norm approximates D^-1 where a local operator can, and
+leaves D M close to the identity elsewhere (measured: about 100 iterations
+against about 305 without a net and 470 with the untrained one, 32^3x64).  The defaults are those iterations and the
+residual norm.
 """
 
 from __future__ import annotations
@@ -26,7 +33,7 @@ import time
 
 from . import wilson as W
 
-SNAPSHOTS = (5, 10, 20, 40, 80, 160)
+SNAPSHOTS = (0, 1, 2, 3)
 
 
 def harvest(lat, sources, kappa, snapshots=SNAPSHOTS, tol=1e-12):

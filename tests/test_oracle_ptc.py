@@ -177,3 +177,23 @@ def test_init_weights_shapes_and_pass_through():
     assert np.array_equal(w1[0, 0, 0], np.eye(4)) and np.array_equal(w2[0, 0, 0], np.eye(4))
     sd = np.std(np.concatenate([w1[1:].ravel(), w1[0, 1:].ravel()]))
     assert abs(sd - 0.1 / 3.0) < 0.01
+
+
+def test_adam_with_a_constant_gradient_steps_lr_against_its_sign_every_step():
+    """Adam's bias corrections make the moments of a constant gradient exact at every step t:
+    m_t / (1 - b1^t) = g and v_t / (1 - b2^t) = g^2, so (eps = 0) every step moves each real parameter by
+    exactly lr against the sign of its gradient, and after T steps w_T = w_0 - T lr sign(g).  A dropped or
+    wrong bias correction, or moments that restart every step, breaks this after the first step."""
+    rng = np.random.default_rng(5)
+    w0 = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    g = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))  # dL/dW*: real gradient (2 Re, 2 Im)
+    w, m, v = w0.copy(), np.zeros((3, 4, 2)), np.zeros((3, 4, 2))
+    lr, T = 1e-2, 7
+    for t in range(1, T + 1):
+        w, m, v = ptc.adam_step(w, g, m, v, t, lr=lr, eps=0.0)
+        want = w0 - t * lr * (np.sign(g.real) + 1j * np.sign(g.imag))
+        assert np.allclose(w, want, rtol=0, atol=1e-13), t
+        # the raw moments carry over: m_t = (1 - b1^t) 2 Re/Im g, v_t = (1 - b2^t) (2 Re/Im g)^2
+        gr = np.stack([2 * g.real, 2 * g.imag], axis=-1)
+        assert np.allclose(m, (1 - 0.9 ** t) * gr, rtol=1e-13, atol=0)
+        assert np.allclose(v, (1 - 0.999 ** t) * gr * gr, rtol=1e-12, atol=0)

@@ -789,6 +789,23 @@ def run_learned(args):
                      "fallback": [i["fallback"] for i in infos]}
         sols[name] = list(lat.unpack(x, W.WL_FULL, W.WL_F64, nsrc).reshape(nsrc, -1, 4, 3))
         log("%s %s" % (name, res[name]))
+    # FGCR with the network as right preconditioner (one application per iteration), one source at a time
+    for name, m in (("fgcr_none", None), ("fgcr_trained", net)):
+        xs, its, sts, fbs, total = [], [], [], [], 0.0
+        for k in range(nsrc):
+            x = lat.new(W.WL_FULL)
+            pf = W.wl_fgcr_params_default()
+            pf.maxiter = 3000
+            (st, info), ms = timed(lambda: W.wl_fgcr_solve(lat.ctx, x, eta_1[k], kappa, m, pf))
+            total += ms
+            xs.append(lat.unpack(x, W.WL_FULL))
+            its.append(info["iters"])
+            sts.append(st)
+            fbs.append(info["fallback"])
+        res[name] = {"status": sts, "time_ms": round(total, 2), "time_per_source_ms": round(total / nsrc, 2),
+                     "iters": its, "fallback": fbs}
+        sols[name] = xs
+        log("%s %s" % (name, res[name]))
     # cost of one network application at this size (nsrc right-hand sides, forward)
     a = lat.new(W.WL_FULL, W.WL_F32, nsrc)
     b = lat.new(W.WL_FULL, W.WL_F32, nsrc)

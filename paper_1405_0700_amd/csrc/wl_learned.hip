@@ -13,6 +13,8 @@ struct wl_ptc {
     float *m = nullptr, *v = nullptr;  // Adam moments per real parameter
     double *loss = nullptr;  // accumulated loss (device)
     int t = 0;               // Adam steps taken
+    uint16_t *tab = nullptr;  // matrix-core operand tables (forward, then adjoint) of the BF16 weights
+    mutable bool tab_ok = false;  // false until built, and again after every weight update
 };
 
 extern "C" wl_status wl_ptc_create(int channels, const double *w1, const double *w2, wl_ptc **out) {
@@ -31,7 +33,9 @@ extern "C" wl_status wl_ptc_create(int channels, const double *w1, const double 
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&n->w, nr * sizeof(float))) != hipSuccess || (e = hipMalloc(&n->wb, nr * sizeof(uint16_t))) != hipSuccess ||
         (e = hipMalloc(&n->grad, nr * sizeof(double))) != hipSuccess || (e = hipMalloc(&n->m, nr * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&n->v, nr * sizeof(float))) != hipSuccess || (e = hipMalloc(&n->loss, sizeof(double))) != hipSuccess) {
+        (e = hipMalloc(&n->v, nr * sizeof(float))) != hipSuccess || (e = hipMalloc(&n->loss, sizeof(double))) != hipSuccess ||
+        (ptc_net_supported(channels) &&
+         (e = hipMalloc(&n->tab, 2 * ptc_net_table_elems(channels) * sizeof(uint16_t))) != hipSuccess)) {
         (void)hipGetLastError();
         wl_ptc_destroy(n);
         return fail(WL_ERR_NOMEM, "hipMalloc of PTC weights failed: %s", hipGetErrorString(e));
@@ -58,6 +62,7 @@ extern "C" wl_status wl_ptc_destroy(wl_ptc *n) {
     if (n->m) (void)hipFree(n->m);
     if (n->v) (void)hipFree(n->v);
     if (n->loss) (void)hipFree(n->loss);
+    if (n->tab) (void)hipFree(n->tab);
     delete n;
     return WL_OK;
 }
@@ -154,6 +159,30 @@ static wl_status ptc_forward(wl_ctx *c, const wl_ptc *n, void *out, const void *
     return WL_OK;
 }
 
+// out = M in (adjoint: M^+ in) for nrhs right-hand sides, without the hidden field: the
+// matrix-core network for 4 or 8 channels, else the layer kernels with the hidden field in S_PTC_H
+static wl_status ptc_net_apply(wl_ctx *c, const wl_ptc *n, void *out, const void *in, bool adjoint, hipStream_t s,
+                               int nrhs) {
+    wl_status st;
+    if (!n->tab) {
+        if ((st = ensure_buf(c, S_PTC_H, ptc_field_bytes(c, n->channels, nrhs)))) return st;
+        return adjoint ? ptc_adjoint_apply(c, n, out, in, c->buf[S_PTC_H], s, nrhs)
+                       : ptc_forward(c, n, out, in, c->buf[S_PTC_H], s, nrhs);
+    }
+    const long te = ptc_net_table_elems(n->channels);
+    if (!n->tab_ok) {
+        HIP_TRY(launch_ptc_net_tables(n->wb, n->n1, n->channels, n->tab, n->tab + te, s));
+        n->tab_ok = true;
+    }
+    char *paths = nullptr;
+    if ((st = ptc_paths(c, nrhs, &paths))) return st;
+    PtcArgs a = ptc_args(c, out, in, 1, 1, nullptr, adjoint ? 1 : 0, &st, nrhs);
+    if (st) return st;
+    a.paths = paths;
+    HIP_TRY(launch_ptc_net(a, n->channels, n->tab + (adjoint ? te : 0), s));
+    return WL_OK;
+}
+
 extern "C" wl_status wl_ptc_apply(wl_ctx *c, const wl_ptc *n, void *out, const void *in, int nrhs, int adjoint,
                                   void *stream) {
     g_err.clear();
@@ -161,10 +190,7 @@ extern "C" wl_status wl_ptc_apply(wl_ctx *c, const wl_ptc *n, void *out, const v
     if (nrhs < 1 || nrhs > 64) return fail(WL_ERR_ARG, "nrhs %d outside [1, 64]", nrhs);
     const size_t hb = half_bytes(c, WL_F32, nrhs);
     if (overlap(out, 2 * hb, in, 2 * hb)) return fail(WL_ERR_ARG, "out and in overlap");
-    wl_status st = ensure_buf(c, S_PTC_H, ptc_field_bytes(c, n->channels, nrhs));
-    if (st) return st;
-    return adjoint ? ptc_adjoint_apply(c, n, out, in, c->buf[S_PTC_H], (hipStream_t)stream, nrhs)
-                   : ptc_forward(c, n, out, in, c->buf[S_PTC_H], (hipStream_t)stream, nrhs);
+    return ptc_net_apply(c, n, out, in, adjoint != 0, (hipStream_t)stream, nrhs);
 }
 
 extern "C" wl_status wl_ptc_layer(wl_ctx *c, void *out, const void *in, const float *weights, int cout, int cin,
@@ -295,6 +321,7 @@ extern "C" wl_status wl_ptc_step(wl_ptc *n, double lr, double *loss, void *strea
     if (!(lr > 0.0) || !std::isfinite(lr)) return fail(WL_ERR_ARG, "bad learning rate");
     hipStream_t s = (hipStream_t)stream;
     n->t += 1;
+    n->tab_ok = false;
     HIP_TRY(launch_adam(n->w, n->wb, n->grad, n->m, n->v, 2 * (n->n1 + n->n2), lr, 0.9, 0.999, 1e-8, n->t, s));
     double l = 0.0;
     HIP_TRY(hipMemcpyAsync(&l, n->loss, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -532,11 +559,10 @@ extern "C" wl_status wl_pcgnr_solve(wl_ctx *c, void *x, const void *b, double ka
         (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * nrhs * F.stride)) ||
         (st = ensure_buf(c, S_PCG_SC, sc_bytes)))
         return st;
-    if (net && (st = ensure_buf(c, S_PTC_H, ptc_field_bytes(c, net->channels, nrhs)))) return st;
     char *base = (char *)c->buf[S_PCG];
     void *y = base, *p = base + full_lo, *rho = base + 2 * full_lo, *sv = base + 3 * full_lo,
          *q = base + 4 * full_lo, *t = base + 5 * full_lo;
-    void *rhi = c->buf[S_GCR_R], *thi = c->buf[S_GCR_TMP], *hid = net ? c->buf[S_PTC_H] : nullptr;
+    void *rhi = c->buf[S_GCR_R], *thi = c->buf[S_GCR_TMP];
     PcgScalars *sc = (PcgScalars *)c->buf[S_PCG_SC];
     int *count = (int *)((char *)sc + sizeof(PcgScalars) * nrhs);
     double *d_start = (double *)((char *)count + 64), *d_stop = d_start + nrhs;
@@ -552,8 +578,7 @@ extern "C" wl_status wl_pcgnr_solve(wl_ctx *c, void *x, const void *b, double ka
     // out = M in (a copy without a network), for all rhs
     auto apply_net = [&](void *out, const void *in, bool adjoint) -> wl_status {
         if (!net) return convert(WL_F32, out, hb_lo, WL_F32, in, hb_lo, false);
-        return adjoint ? ptc_adjoint_apply(c, net, out, in, hid, F.s, nrhs)
-                       : ptc_forward(c, net, out, in, hid, F.s, nrhs);
+        return ptc_net_apply(c, net, out, in, adjoint, F.s, nrhs);
     };
     // sv = M^+ D^+ rho and the partials of ||sv||^2 per rhs
     long nblk_blas = blas_blocks(c->Vh * (long)nrhs) * 2;
@@ -729,7 +754,6 @@ extern "C" wl_status wl_fgcr_solve(wl_ctx *c, void *x, const void *b, double kap
         (st = ensure_buf(c, S_GCR_W, (size_t)m * full_lo)) ||
         (st = ensure_buf(c, S_PARTIALS, sizeof(double) * 2 * F.stride)))
         return st;
-    if (net && (st = ensure_buf(c, S_PTC_H, ptc_field_bytes(c, net->channels)))) return st;
     char *rlo = (char *)c->buf[S_GCR_X], *xc = rlo + full_lo;
     char *Z = (char *)c->buf[S_GCR_Z], *Wv = (char *)c->buf[S_GCR_W];
     void *rhi = c->buf[S_GCR_R], *thi = c->buf[S_GCR_TMP];
@@ -770,7 +794,7 @@ extern "C" wl_status wl_fgcr_solve(wl_ctx *c, void *x, const void *b, double kap
         for (int k = 0; k < m && total < P.maxiter; ++k) {
             void *zk = Z + (size_t)k * full_lo, *wk = Wv + (size_t)k * full_lo;
             if (net) {
-                if ((st = ptc_forward(c, net, zk, rlo, c->buf[S_PTC_H], F.s))) return st;
+                if ((st = ptc_net_apply(c, net, zk, rlo, false, F.s, 1))) return st;
             } else {
                 VecArgs v = vec_args(c, WL_F32, 1);
                 const size_t hb = half_bytes(c, WL_F32, 1);

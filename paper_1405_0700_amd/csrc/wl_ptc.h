@@ -37,6 +37,20 @@ struct PtcArgs {
 
 hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16_weights, hipStream_t s);
 
+// The whole two-layer network 1 -> C -> 1 (C = 4 or 8) on matrix cores, in two
+// passes: at every point y the nine transports of in, the first layer's channel
+// mixing and the second layer's mixing of each path (both real matrix products
+// on MFMA with BF16 operands, the FP32 activations split exactly into three BF16
+// parts, FP32 accumulation), stored as the nine path fields a.paths; then the
+// gather k_ptc_gather into a.out.  Forward (M) or adjoint (M^+) by the table.
+// `tab` holds the MFMA operand tables of both layers for one direction, built by
+// launch_ptc_net_tables; a.w is not used.  a.cout = a.cin = 1, a.nrhs as usual.
+bool ptc_net_supported(int channels);
+long ptc_net_table_elems(int channels);  // BF16 elements of one direction's table
+hipError_t launch_ptc_net_tables(const uint16_t *wb, long n1, int channels, uint16_t *tab_fwd, uint16_t *tab_adj,
+                                 hipStream_t s);
+hipError_t launch_ptc_net(const PtcArgs &a, int channels, const uint16_t *tab, hipStream_t s);
+
 // Weight gradient dL/d conj(W_p^{ab}) = sum_x sum_colour g[a](x) (T_p in[b])(x)^+
 // for all (p, a, b): per-chunk FP32 partials, then an FP64 sum over chunks that
 // is stored to (or added to) grad[p][a][b][4][4] (complex double).  Channel-major

@@ -330,6 +330,279 @@ hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- network on matrix cores
+// The network out = L2(L1(in)) is linear, and the spin matrices of a layer act
+// before its transports, so the second layer's mixing of each path can be done
+// at the source point (as in the two-pass form above): at every point y
+//   t_q(y) = (T_q in)(y)                              nine transports
+//   h_o(y) = sum_q W1_q^o t_q(y)                      first layer, C channels
+//   v_p(y) = sum_o W2_p^o h_o(y)                      second layer, per path p
+// and out(x) = sum_p T_p v_p(x + p) (k_ptc_gather).  The C-channel hidden field
+// never leaves the registers.  Both mixings are real matrix products, each
+// complex 4x4 spin matrix w = a + ib becoming the 8x8 real block with entries
+// [re <- re] = a, [re <- im] = -b, [im <- re] = b, [im <- im] = a:
+//   H (8C x 16) = A1 (8C x 96) T (96 x 16),  V (80 x 16) = A2 (80 x 8C) H,
+// per colour, with 16 points (site, rhs) as the columns.  A wave takes 16 points
+// and runs v_mfma_f32_16x16x32_bf16: the weights are BF16 already (exact); each
+// FP32 activation is split exactly into three BF16 parts (hi = its top 16 bits,
+// mid = the top 16 bits of the remainder, lo = the rest, at most 8 significant
+// bits), so every product is exact and the sums are FP32 accumulations.
+// MFMA lane layout (lane l, g = l / 16, n = l % 16): A row l % 16, columns
+// 8 g .. 8 g + 7; B rows 8 g .. 8 g + 7, column n; D rows 4 g .. 4 g + 3,
+// column n.  The K order inside a 32-column block is free (the same for A and
+// B), so each lane feeds B with what it holds:
+//   layer 1, K blocks 0 and 1: lane group g computes path 1 + 4 kb + g for point
+//     n and supplies its 8 reals (spin, re / im) of one colour;
+//   layer 1, K block 2: the identity path, its hi / mid / lo parts in lane groups
+//     0 / 1 / 2 (A repeats the path-0 weights for each), group 3 zero;
+//   layer 2, K block kb2: the lane's accumulators of layer-1 M tiles 2 kb2 and
+//     2 kb2 + 1 (rows 4 g + i of each), three MFMAs for hi / mid / lo.
+// Row orders: H row 8 o + 2 s + c (channel o, spin s, c = re / im); V row
+// 8 p + 2 s + c, rows 72..79 zero.  A lane of a layer-2 output tile then holds
+// spins 2 (g & 1), 2 (g & 1) + 1 of path 2 mt + g / 2 for one colour: with the
+// three colours, three whole float4 units of the FP32 spinor layout.
+typedef __bf16 ptc_bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t ptc_u32x4 __attribute__((ext_vector_type(4)));
+typedef float ptc_f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int PTC_NET_NM2 = 5;  // layer-2 M tiles (72 rows padded to 80)
+__host__ __device__ constexpr int ptc_net_blocks(int C) { return 3 * (C / 2) + PTC_NET_NM2 * (C / 4); }
+
+bool ptc_net_supported(int channels) { return channels == 4 || channels == 8; }
+long ptc_net_table_elems(int channels) { return (long)ptc_net_blocks(channels) * 64 * 8; }
+
+__device__ __forceinline__ ptc_f32x4 ptc_mfma(ptc_u32x4 a, ptc_u32x4 b, ptc_f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(ptc_bf16x8, a), __builtin_bit_cast(ptc_bf16x8, b),
+                                                    c, 0, 0, 0);
+}
+
+// exact three-way BF16 split of two floats x0 (low half) and x1 (high half);
+// v_perm_b32 with selector 0x07060302 packs the top 16 bits of two words
+__device__ __forceinline__ uint32_t ptc_pack_hi(uint32_t lo_word, uint32_t hi_word) {
+    return __builtin_amdgcn_perm(hi_word, lo_word, 0x07060302u);
+}
+__device__ __forceinline__ void ptc_split2(float x0, float x1, uint32_t &hi, uint32_t &mid, uint32_t &lo) {
+    const uint32_t b0 = __float_as_uint(x0), b1 = __float_as_uint(x1);
+    const float r0 = x0 - __uint_as_float(b0 & 0xffff0000u), r1 = x1 - __uint_as_float(b1 & 0xffff0000u);
+    const uint32_t c0 = __float_as_uint(r0), c1 = __float_as_uint(r1);
+    const float s0 = r0 - __uint_as_float(c0 & 0xffff0000u), s1 = r1 - __uint_as_float(c1 & 0xffff0000u);
+    hi = ptc_pack_hi(b0, b1);
+    mid = ptc_pack_hi(c0, c1);
+    lo = ptc_pack_hi(__float_as_uint(s0), __float_as_uint(s1));
+}
+
+// the 8 reals (spin s = 0..3, re / im) of colour j, split into hi / mid / lo
+__device__ __forceinline__ void ptc_split_colour(const cpx<float> v[12], int j, ptc_u32x4 out[3]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        uint32_t h, m, l;
+        ptc_split2(v[3 * s + j].re, v[3 * s + j].im, h, m, l);
+        out[0][s] = h;
+        out[1][s] = m;
+        out[2][s] = l;
+    }
+}
+
+// one part (0 hi, 1 mid, 2 lo) of the split of x, as a word whose top 16 bits are that part
+__device__ __forceinline__ uint32_t ptc_part(float x, int part) {
+    const uint32_t b = __float_as_uint(x);
+    const float r = x - __uint_as_float(b & 0xffff0000u);
+    const uint32_t c = __float_as_uint(r);
+    const float t = r - __uint_as_float(c & 0xffff0000u);
+    return part == 0 ? b : (part == 1 ? c : __float_as_uint(t));
+}
+
+// Operand tables: block b < 3 C / 2 is layer-1 (M tile b / 3, K block b % 3),
+// then layer-2 (M tile, K block) = ((b - 3 C / 2) / (C / 4), (b - 3 C / 2) % (C / 4));
+// each block is [lane][8] BF16, lane l holding its A fragment.  Forward: layer 1
+// W1_q^{o}, layer 2 W2_p^{o}.  Adjoint: layer 1 (W2_{rev q}^{o})^+, layer 2
+// (W1_{rev p}^{o})^+ (the transports of M^+ run along the reversed paths).
+template <int C>
+__global__ void __launch_bounds__(256) k_ptc_net_table(const uint16_t *wb, long n1, uint16_t *tab, int adjoint) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)ptc_net_blocks(C) * 512) return;
+    const int i = (int)(idx & 7), l = (int)((idx >> 3) & 63), blk = (int)(idx >> 9);
+    const int g = l >> 4;
+    const uint16_t *w1 = wb, *w2 = wb + 2 * n1;
+    int row_o, row_s, row_c, q, t, col_c;  // output (channel or path, spin, re/im), input (path or channel, spin, re/im)
+    bool zero = false, layer1 = blk < 3 * (C / 2);
+    if (layer1) {
+        const int mt = blk / 3, kb = blk % 3, m = 16 * mt + (l & 15);
+        row_o = m >> 3; row_s = (m & 7) >> 1; row_c = m & 1;
+        q = kb < 2 ? 1 + 4 * kb + g : 0;
+        zero = kb == 2 && g == 3;
+        t = i >> 1; col_c = i & 1;
+    } else {
+        const int b2 = blk - 3 * (C / 2), mt2 = b2 / (C / 4), kb2 = b2 % (C / 4), r = 16 * mt2 + (l & 15);
+        zero = r >= 8 * PTC_NPATH;
+        row_o = r >> 3; row_s = (r & 7) >> 1; row_c = r & 1;
+        const int h = 32 * kb2 + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
+        q = h >> 3; t = (h & 7) >> 1; col_c = h & 1;  // q: hidden channel here
+    }
+    uint16_t v = 0;
+    if (!zero) {
+        // complex weight (re, im) as BF16 bits
+        long cidx;
+        const uint16_t *base;
+        bool conj = false;
+        if (layer1) {
+            // row_o: channel o, q: path
+            if (!adjoint) { base = w1; cidx = ((long)q * C + row_o) * 16 + 4 * row_s + t; }
+            else { base = w2; cidx = ((long)ptc_reverse(q) * C + row_o) * 16 + 4 * t + row_s; conj = true; }
+        } else {
+            // row_o: path p, q: channel o
+            if (!adjoint) { base = w2; cidx = ((long)row_o * C + q) * 16 + 4 * row_s + t; }
+            else { base = w1; cidx = ((long)ptc_reverse(row_o) * C + q) * 16 + 4 * t + row_s; conj = true; }
+        }
+        const uint16_t re = base[2 * cidx];
+        const uint16_t im = conj ? (uint16_t)(base[2 * cidx + 1] ^ 0x8000u) : base[2 * cidx + 1];
+        // [re <- re] = a, [re <- im] = -b, [im <- re] = b, [im <- im] = a
+        v = row_c == 0 ? (col_c == 0 ? re : (uint16_t)(im ^ 0x8000u)) : (col_c == 0 ? im : re);
+    }
+    tab[idx] = v;
+}
+
+hipError_t launch_ptc_net_tables(const uint16_t *wb, long n1, int channels, uint16_t *tab_fwd, uint16_t *tab_adj,
+                                 hipStream_t s) {
+    if (!ptc_net_supported(channels)) return hipErrorInvalidValue;
+    const long n = ptc_net_table_elems(channels);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    for (int adj = 0; adj < 2; ++adj) {
+        uint16_t *tab = adj ? tab_adj : tab_fwd;
+        if (channels == 8) hipLaunchKernelGGL(k_ptc_net_table<8>, dim3(blocks), dim3(256), 0, s, wb, n1, tab, adj);
+        else hipLaunchKernelGGL(k_ptc_net_table<4>, dim3(blocks), dim3(256), 0, s, wb, n1, tab, adj);
+    }
+    return hipGetLastError();
+}
+
+// Pass A; a wave per tile of 16 points of one parity, tiles of both parities in
+// one range (parity = tile / tiles_per_parity), waves loop over tiles.
+template <int C>
+__global__ void __launch_bounds__(256, 2) k_ptc_net_mix(const PtcArgs a, const uint16_t *tab, long tiles_par) {
+    constexpr int NM1 = C / 2, NK2 = C / 4, NB = ptc_net_blocks(C);
+    __shared__ ptc_u32x4 ta[NB * 64];
+    for (int k = threadIdx.x; k < NB * 64; k += blockDim.x) ta[k] = ((const ptc_u32x4 *)tab)[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+    const long npts = a.vh * a.nrhs;
+    const long ntile = 2 * tiles_par;
+    for (long tile = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntile;
+         tile += (long)gridDim.x * (blockDim.x >> 6)) {
+        const int par = tile >= tiles_par ? 1 : 0;
+        const long pt = (tile - par * tiles_par) * 16 + n;
+        const bool valid = pt < npts;
+        int i = 0, rhs = 0;
+        int c[4] = {0, 0, 0, 0};
+        if (valid) {
+            // npts < 2^31 (checked at launch)
+            i = (int)pt / a.nrhs;
+            rhs = (int)pt - i * a.nrhs;
+            eo_coords(a.g, i, par, c);
+        }
+        ptc_f32x4 acc1[NM1][3];
+#pragma unroll
+        for (int mt = 0; mt < NM1; ++mt)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc1[mt][j] = ptc_f32x4{0.f, 0.f, 0.f, 0.f};
+        // layer 1, hop paths: K blocks 0 and 1
+#pragma unroll 1
+        for (int kb = 0; kb < 2; ++kb) {
+            cpx<float> t[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) t[k] = {0.f, 0.f};
+            if (valid) {
+                const PathHop h = ptc_hop(a.g, i, par, c, 1 + 4 * kb + g);
+                cpx<float> v[12];
+                SpinorIO<WL_F32>::load(a.in + (size_t)h.npar * a.half, (long)h.j * a.nrhs + rhs, v);
+                ptc_transport(a.g, a.gauge, a.slab_bytes, h, v, t);
+            }
+            ptc_u32x4 b[3][3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) ptc_split_colour(t, j, b[j]);
+#pragma unroll
+            for (int mt = 0; mt < NM1; ++mt) {
+                const ptc_u32x4 w = ta[(mt * 3 + kb) * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int part = 2; part >= 0; --part) acc1[mt][j] = ptc_mfma(w, b[j][part], acc1[mt][j]);
+            }
+        }
+        // layer 1, identity path: K block 2 (hi / mid / lo in lane groups 0 / 1 / 2)
+        {
+            cpx<float> v[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) v[k] = {0.f, 0.f};
+            if (valid && g < 3) SpinorIO<WL_F32>::load(a.in + (size_t)par * a.half, pt, v);
+            ptc_u32x4 b[3];  // group 3 holds zeros (v = 0 there)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int s_ = 0; s_ < 4; ++s_)
+                    b[j][s_] = ptc_pack_hi(ptc_part(v[3 * s_ + j].re, g), ptc_part(v[3 * s_ + j].im, g));
+#pragma unroll
+            for (int mt = 0; mt < NM1; ++mt) {
+                const ptc_u32x4 w = ta[(mt * 3 + 2) * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) acc1[mt][j] = ptc_mfma(w, b[j], acc1[mt][j]);
+            }
+        }
+        // layer 2
+        ptc_u32x4 b2[NK2][3][3];
+#pragma unroll
+        for (int kb2 = 0; kb2 < NK2; ++kb2)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const ptc_f32x4 lo4 = acc1[2 * kb2][j], hi4 = acc1[2 * kb2 + 1][j];
+                uint32_t h, m, l;
+                ptc_split2(lo4[0], lo4[1], h, m, l);
+                b2[kb2][j][0][0] = h; b2[kb2][j][1][0] = m; b2[kb2][j][2][0] = l;
+                ptc_split2(lo4[2], lo4[3], h, m, l);
+                b2[kb2][j][0][1] = h; b2[kb2][j][1][1] = m; b2[kb2][j][2][1] = l;
+                ptc_split2(hi4[0], hi4[1], h, m, l);
+                b2[kb2][j][0][2] = h; b2[kb2][j][1][2] = m; b2[kb2][j][2][2] = l;
+                ptc_split2(hi4[2], hi4[3], h, m, l);
+                b2[kb2][j][0][3] = h; b2[kb2][j][1][3] = m; b2[kb2][j][2][3] = l;
+            }
+#pragma unroll
+        for (int mt2 = 0; mt2 < PTC_NET_NM2; ++mt2) {
+            ptc_f32x4 acc[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc[j] = ptc_f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb2 = 0; kb2 < NK2; ++kb2) {
+                const ptc_u32x4 w = ta[(3 * NM1 + mt2 * NK2 + kb2) * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int part = 2; part >= 0; --part) acc[j] = ptc_mfma(w, b2[kb2][j][part], acc[j]);
+            }
+            const int p = 2 * mt2 + (g >> 1);
+            if (valid && p < PTC_NPATH) {
+                // spins s0 = 2 (g & 1) and s0 + 1, colours 0..2: complex components 3 s0 .. 3 s0 + 5,
+                // float4 units 3 (g & 1) .. 3 (g & 1) + 2
+                float4 *dst = (float4 *)(a.paths + (2 * (size_t)p + par) * a.half) + blk_unit(pt, 6, 3 * (g & 1));
+                dst[0] = make_float4(acc[0][0], acc[0][1], acc[1][0], acc[1][1]);
+                dst[BLK] = make_float4(acc[2][0], acc[2][1], acc[0][2], acc[0][3]);
+                dst[2 * BLK] = make_float4(acc[1][2], acc[1][3], acc[2][2], acc[2][3]);
+            }
+        }
+    }
+}
+
+hipError_t launch_ptc_net(const PtcArgs &a, int channels, const uint16_t *tab, hipStream_t s) {
+    if (!ptc_net_supported(channels) || !a.paths || a.nrhs < 1 || !tab) return hipErrorInvalidValue;
+    const long npts = a.vh * a.nrhs;
+    if (npts + 16 > INT_MAX) return hipErrorInvalidValue;
+    const long tiles_par = (npts + 15) / 16;
+    const long waves = 2 * tiles_par;
+    const unsigned blocks = (unsigned)std::min<long>((waves + 3) / 4, 2048);
+    if (channels == 8) hipLaunchKernelGGL(k_ptc_net_mix<8>, dim3(blocks), dim3(256), 0, s, a, tab, tiles_par);
+    else hipLaunchKernelGGL(k_ptc_net_mix<4>, dim3(blocks), dim3(256), 0, s, a, tab, tiles_par);
+    hipLaunchKernelGGL(k_ptc_gather, dim3((unsigned)((npts + 255) / 256), 2), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- weight gradient
 __global__ void __launch_bounds__(256) k_ptc_wgrad(const PtcGradArgs a) {
     const int combo = blockIdx.y;

@@ -1,8 +1,9 @@
-"""The learned preconditioner end to end on small lattices: training pairs
-harvested from plain CG satisfy r = D e, training with the library's own
-forward/backward/Adam kernels (residual-norm loss) lowers the loss, and FGCR
-with the trained network needs fewer iterations than FGCR without a
-preconditioner and than with the untrained network, on a gauge field and
+"""The learned preconditioner end to end on small lattices, with the default
+training recipe (pairs from the first iterations of plain CG, residual-norm
+loss): harvested pairs satisfy r = D e, training with the library's own
+forward/backward/Adam kernels lowers the loss, and FGCR and CG on the normal
+equations of D M with the trained network need fewer iterations than without
+a preconditioner and than with the untrained network, on a gauge field and
 source it was not trained on."""
 
 import numpy as np
@@ -16,7 +17,10 @@ from paper_1405_0700_amd import wilson as W
 pytestmark = pytest.mark.gpu
 AP = (1, 1, 1, -1)
 DIMS = (8, 8, 8, 8)
-KAPPA = 0.13
+KAPPA = 0.137
+# restarted FGCR with the untrained network stalls at kappa 0.137 on this field (with either network kernel):
+# its comparison runs at 0.13
+KAPPA_FGCR = 0.13
 
 
 @pytest.fixture(autouse=True)
@@ -32,11 +36,11 @@ def trained():
         u = synth.su3_links(DIMS, 0.2, 600 + k)
         lat = W.Lattice.create(u, AP)
         srcs = [synth.gaussian_spinor(DIMS, seed=610 + 2 * k + j) for j in range(2)]
-        sets.append((lat, learned.harvest(lat, srcs, KAPPA, snapshots=(5, 10, 20, 40))))
+        sets.append((lat, learned.harvest(lat, srcs, KAPPA)))
         gauges.append(u)
     w1, w2 = synth.ptc_weights(8, seed=530)
     net = W.wl_ptc_create(w1, w2)
-    losses = learned.train(sets, net, epochs=40, lr=2e-3, loss="residual", kappa=KAPPA)
+    losses = learned.train(sets, net, epochs=60, lr=1e-3, loss="residual", kappa=KAPPA)
     yield sets, gauges, net, losses
     W.wl_ptc_destroy(net)
 
@@ -69,9 +73,9 @@ def test_fgcr_with_the_trained_network(trained):
         x = lat.new(W.WL_FULL)
         p = W.wl_fgcr_params_default()
         p.fallback = 0
-        st, info = W.wl_fgcr_solve(lat.ctx, x, lat.pack(b), KAPPA, m, p)
+        st, info = W.wl_fgcr_solve(lat.ctx, x, lat.pack(b), KAPPA_FGCR, m, p)
         xs = lat.unpack(x).reshape(b.shape)
-        r = np.linalg.norm(orc.dirac(xs, u, KAPPA, AP) - b) / np.linalg.norm(b)
+        r = np.linalg.norm(orc.dirac(xs, u, KAPPA_FGCR, AP) - b) / np.linalg.norm(b)
         assert st == W.WL_OK and r <= 1.05e-10, (name, st, r)
         res[name] = info["iters"]
     print("FGCR iterations by preconditioner:", res)
@@ -86,7 +90,8 @@ def test_preconditioned_cgnr_with_the_trained_network(trained):
     lat = W.Lattice.create(u, AP)
     b = synth.gaussian_spinor(DIMS, seed=621)
     res = {}
-    for name, m in (("none", None), ("trained", net)):
+    fresh = W.wl_ptc_create(*synth.ptc_weights(8, seed=530))
+    for name, m in (("none", None), ("initial", fresh), ("trained", net)):
         x = lat.new(W.WL_FULL)
         p = W.wl_pcgnr_params_default()
         p.fallback = 0
@@ -96,5 +101,6 @@ def test_preconditioned_cgnr_with_the_trained_network(trained):
         assert st == W.WL_OK and r <= 1.05e-10, (name, st, r)
         res[name] = info["iters"]
     print("preconditioned CGNR iterations:", res)
-    assert res["trained"] < res["none"]
+    assert res["trained"] < res["none"] and res["trained"] < res["initial"]
+    W.wl_ptc_destroy(fresh)
     lat.close()

@@ -397,3 +397,55 @@ def test_cgnr_and_preconditioned_cgnr_on_several_rhs():
             assert res <= 1.05e-10 and infos[r]["true_rel_resid"] <= 1e-10 and infos[r]["fallback"] == 0
             assert abs(infos[r]["iters"] - one["iters"]) <= max(3, one["iters"] // 20)
     W.wl_ptc_destroy(net)
+
+
+@pytest.mark.parametrize("channels,nrhs,adjoint", [(8, 1, False), (8, 3, True), (4, 3, False), (4, 1, True),
+                                                   (8, 5, False), (6, 2, False), (6, 2, True)])
+def test_network_on_matrix_cores(channels, nrhs, adjoint):
+    """M (M^+) through the matrix-core network kernel (4 or 8 channels; 6 takes the layer kernels) against the
+    oracle's two layers (their adjoints in reverse order) with the same BF16 weights.  6x6x2x2 has V/2 = 72
+    points per parity, so every nrhs leaves a partial last tile of 16 points."""
+    dims = (6, 6, 2, 2)
+    ph = random_phases(600 + channels)
+    u, lat = lattice(dims, 601, ph)
+    w1, w2 = synth.ptc_weights(channels, seed=602)
+    w1 = w1 + random_weights(channels, 1, 603, 0.05)
+    w2 = w2 + random_weights(1, channels, 604, 0.05)
+    net = W.wl_ptc_create(w1, w2)
+    fields = [f32(synth.gaussian_spinor(dims, seed=610 + r)) for r in range(nrhs)]
+    stack = np.stack([f.reshape(-1, 4, 3) for f in fields])
+    out = lat.new(W.WL_FULL, W.WL_F32, nrhs)
+    W.wl_ptc_apply(lat.ctx, net, out, lat.pack(stack, W.WL_FULL, W.WL_F32, nrhs), nrhs=nrhs, adjoint=adjoint)
+    got = lat.unpack(out, W.WL_FULL, W.WL_F32, nrhs)
+    w1b, w2b = bf16_round(w1), bf16_round(w2)
+    for r, f in enumerate(fields):
+        if adjoint:
+            want = ptc.layer_adjoint(ptc.layer_adjoint([f], w2b, u, ph), w1b, u, ph)[0]
+        else:
+            want, _ = ptc.net_apply(f, w1b, w2b, u, ph)
+        g = (got[r] if nrhs > 1 else got).reshape(want.shape)
+        assert rel(g, want) < TOL32, (r, rel(g, want))
+        assert np.abs(g - want).max() < TOL32 * np.abs(want).max()
+    W.wl_ptc_destroy(net)
+
+
+def test_network_tables_follow_the_weights():
+    """After an Adam step the matrix-core network uses the new BF16 weights (its operand tables are rebuilt)."""
+    dims = (4, 6, 4, 8)
+    ph = random_phases(620)
+    u, lat = lattice(dims, 621, ph)
+    w1, w2 = synth.ptc_weights(8, seed=622)
+    w1 = w1 + random_weights(8, 1, 623, 0.05)
+    net = W.wl_ptc_create(w1, w2)
+    r = f32(synth.gaussian_spinor(dims, seed=624))
+    e = f32(synth.gaussian_spinor(dims, seed=625))
+    out = lat.new(W.WL_FULL, W.WL_F32)
+    rin = lat.pack(r, W.WL_FULL, W.WL_F32)
+    W.wl_ptc_apply(lat.ctx, net, out, rin)
+    W.wl_ptc_accumulate(lat.ctx, net, rin, lat.pack(e, W.WL_FULL, W.WL_F32), 1.0)
+    W.wl_ptc_step(net, 1e-2)
+    n1, n2 = W.wl_ptc_get_weights(net, 8)
+    W.wl_ptc_apply(lat.ctx, net, out, rin)
+    want, _ = ptc.net_apply(r, bf16_round(n1), bf16_round(n2), u, ph)
+    assert rel(lat.unpack(out, W.WL_FULL, W.WL_F32).reshape(want.shape), want) < TOL32
+    W.wl_ptc_destroy(net)

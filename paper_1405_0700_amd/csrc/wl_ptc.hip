@@ -286,7 +286,10 @@ __global__ void __launch_bounds__(256) k_ptc_mix(const PtcArgs a) {
         SpinorIO<WL_F32>::store(a.paths + (2 * (size_t)(q0 + g) + par) * a.half, pt, chi[g]);
 }
 
-// Pass 2: out(x) = sum_q T_q v_q(x + q), the nine mixtures of the neighbours
+// Pass 2: out(x) = sum_q T_q v_q(x + q), the nine mixtures of the neighbours.
+// NT: the path fields are read with non-temporal loads (every value is read
+// once; keeps them from evicting the links and the output from the caches).
+template <bool NT>
 __global__ void __launch_bounds__(256) k_ptc_gather(const PtcArgs a) {
     const int par = blockIdx.y;
     const long pt = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -300,7 +303,18 @@ __global__ void __launch_bounds__(256) k_ptc_gather(const PtcArgs a) {
     for (int q = 0; q < PTC_NPATH; ++q) {
         const PathHop h = ptc_hop(a.g, i, par, c, q);
         cpx<float> chi[12], t[12];
-        SpinorIO<WL_F32>::load(a.paths + (2 * (size_t)q + h.npar) * a.half, (long)h.j * a.nrhs + rhs, chi);
+        const char *base = a.paths + (2 * (size_t)q + h.npar) * a.half;
+        if constexpr (NT) {
+            const v4f *p = (const v4f *)base + blk_unit((long)h.j * a.nrhs + rhs, 6, 0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const v4f d = __builtin_nontemporal_load(p + k * BLK);
+                chi[2 * k] = {d[0], d[1]};
+                chi[2 * k + 1] = {d[2], d[3]};
+            }
+        } else {
+            SpinorIO<WL_F32>::load(base, (long)h.j * a.nrhs + rhs, chi);
+        }
         ptc_transport(a.g, a.gauge, a.slab_bytes, h, chi, t);
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = acc[k] + t[k];
@@ -321,7 +335,7 @@ hipError_t launch_ptc_layer(const PtcArgs &a, bool bf16, hipStream_t s) {
         dim3 g1((unsigned)((npts + 255) / 256), 2, PTC_NPATH / PTC_MIX_GROUP);
         if (bf16) hipLaunchKernelGGL(k_ptc_mix<true>, g1, dim3(256), 0, s, a);
         else hipLaunchKernelGGL(k_ptc_mix<false>, g1, dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_ptc_gather, dim3((unsigned)((npts + 255) / 256), 2), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_ptc_gather<false>, dim3((unsigned)((npts + 255) / 256), 2), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     dim3 grid((unsigned)((npts + 255) / 256), 2, (unsigned)a.cout);
@@ -581,10 +595,11 @@ __global__ void __launch_bounds__(256, 2) k_ptc_net_mix(const PtcArgs a, const u
             if (valid && p < PTC_NPATH) {
                 // spins s0 = 2 (g & 1) and s0 + 1, colours 0..2: complex components 3 s0 .. 3 s0 + 5,
                 // float4 units 3 (g & 1) .. 3 (g & 1) + 2
-                float4 *dst = (float4 *)(a.paths + (2 * (size_t)p + par) * a.half) + blk_unit(pt, 6, 3 * (g & 1));
-                dst[0] = make_float4(acc[0][0], acc[0][1], acc[1][0], acc[1][1]);
-                dst[BLK] = make_float4(acc[2][0], acc[2][1], acc[0][2], acc[0][3]);
-                dst[2 * BLK] = make_float4(acc[1][2], acc[1][3], acc[2][2], acc[2][3]);
+                // non-temporal: each path value is read once, by the gather
+                v4f *dst = (v4f *)(a.paths + (2 * (size_t)p + par) * a.half) + blk_unit(pt, 6, 3 * (g & 1));
+                st_out<true, v4f>(dst, v4f{acc[0][0], acc[0][1], acc[1][0], acc[1][1]});
+                st_out<true, v4f>(dst + BLK, v4f{acc[2][0], acc[2][1], acc[0][2], acc[0][3]});
+                st_out<true, v4f>(dst + 2 * BLK, v4f{acc[1][2], acc[1][3], acc[2][2], acc[2][3]});
             }
         }
     }
@@ -599,7 +614,7 @@ hipError_t launch_ptc_net(const PtcArgs &a, int channels, const uint16_t *tab, h
     const unsigned blocks = (unsigned)std::min<long>((waves + 3) / 4, 2048);
     if (channels == 8) hipLaunchKernelGGL(k_ptc_net_mix<8>, dim3(blocks), dim3(256), 0, s, a, tab, tiles_par);
     else hipLaunchKernelGGL(k_ptc_net_mix<4>, dim3(blocks), dim3(256), 0, s, a, tab, tiles_par);
-    hipLaunchKernelGGL(k_ptc_gather, dim3((unsigned)((npts + 255) / 256), 2), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ptc_gather<true>, dim3((unsigned)((npts + 255) / 256), 2), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -417,13 +417,13 @@ __device__ __forceinline__ void ptc_split_colour(const cpx<float> v[12], int j, 
     }
 }
 
-// one part (0 hi, 1 mid, 2 lo) of the split of x, as a word whose top 16 bits are that part
-__device__ __forceinline__ uint32_t ptc_part(float x, int part) {
-    const uint32_t b = __float_as_uint(x);
-    const float r = x - __uint_as_float(b & 0xffff0000u);
-    const uint32_t c = __float_as_uint(r);
-    const float t = r - __uint_as_float(c & 0xffff0000u);
-    return part == 0 ? b : (part == 1 ? c : __float_as_uint(t));
+// one part of the split of x, as a word whose top 16 bits are that part: with
+// d1 = 1, d2 = 0 the mid part, with d1 = d2 = 1 the lo part, with both 0 the hi
+// part (x itself); fma(-1, h, x) = x - h exactly, fma(-0, h, x) = x
+__device__ __forceinline__ uint32_t ptc_part(float x, float d1, float d2) {
+    const float r = fmaf(-d1, __uint_as_float(__float_as_uint(x) & 0xffff0000u), x);
+    const float t = fmaf(-d2, __uint_as_float(__float_as_uint(r) & 0xffff0000u), r);
+    return __float_as_uint(t);
 }
 
 // Operand tables: block b < 3 C / 2 is layer-1 (M tile b / 3, K block b % 3),
@@ -489,6 +489,41 @@ hipError_t launch_ptc_net_tables(const uint16_t *wb, long n1, int channels, uint
     return hipGetLastError();
 }
 
+// t = U chi (forward hop) or U^+ chi (backward hop) for the 4 spins, times the
+// boundary phase on a wrapped hop, without branching on the direction: the
+// lanes of a wave take different paths, so the backward link is transposed and
+// conjugated by selects and one multiply sequence serves both; the phase
+// multiply is skipped when no lane of the wave wraps.  Hop paths only (q >= 1).
+__device__ __forceinline__ void ptc_transport_sel(const Geom &g, const void *gauge, size_t slab, const PathHop &h,
+                                                  bool active, const cpx<float> chi[12], cpx<float> t[12]) {
+    cpx<float> u[9];
+    LinkIO<WL_F32, 18>::load((const char *)gauge + (size_t)(h.lpar * 4 + h.mu) * slab, h.lsite, u);
+    cpx<float> m[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const cpx<float> a = u[3 * r + k], b = u[3 * k + r];
+            m[3 * r + k] = h.fwd ? a : cpx<float>{b.re, -b.im};
+        }
+    const bool wraps = active && h.wrap && ((g.phase_mask >> h.mu) & 1);
+    if (__builtin_amdgcn_ballot_w64(wraps)) {
+        const cpx<float> z = wraps ? cpx<float>{(float)g.zr[h.mu], h.fwd ? (float)g.zi[h.mu] : -(float)g.zi[h.mu]}
+                                   : cpx<float>{1.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 9; ++k) m[k] = cmul(z, m[k]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            cpx<float> acc = {0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc = cfma(m[3 * r + k], chi[3 * s + k], acc);
+            t[3 * s + r] = acc;
+        }
+}
+
 // Pass A; a wave per tile of 16 points of one parity, tiles of both parities in
 // one range (parity = tile / tiles_per_parity), waves loop over tiles.
 template <int C>
@@ -521,15 +556,17 @@ __global__ void __launch_bounds__(256, 2) k_ptc_net_mix(const PtcArgs a, const u
         // layer 1, hop paths: K blocks 0 and 1
 #pragma unroll 1
         for (int kb = 0; kb < 2; ++kb) {
-            cpx<float> t[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) t[k] = {0.f, 0.f};
+            // invalid points (the last tile's tail) take site 0 with zero input and store nothing
+            const PathHop h = ptc_hop(a.g, i, par, c, 1 + 4 * kb + g);
+            cpx<float> v[12];
             if (valid) {
-                const PathHop h = ptc_hop(a.g, i, par, c, 1 + 4 * kb + g);
-                cpx<float> v[12];
                 SpinorIO<WL_F32>::load(a.in + (size_t)h.npar * a.half, (long)h.j * a.nrhs + rhs, v);
-                ptc_transport(a.g, a.gauge, a.slab_bytes, h, v, t);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) v[k] = {0.f, 0.f};
             }
+            cpx<float> t[12];
+            ptc_transport_sel(a.g, a.gauge, a.slab_bytes, h, valid, v, t);
             ptc_u32x4 b[3][3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) ptc_split_colour(t, j, b[j]);
@@ -549,11 +586,12 @@ __global__ void __launch_bounds__(256, 2) k_ptc_net_mix(const PtcArgs a, const u
             for (int k = 0; k < 12; ++k) v[k] = {0.f, 0.f};
             if (valid && g < 3) SpinorIO<WL_F32>::load(a.in + (size_t)par * a.half, pt, v);
             ptc_u32x4 b[3];  // group 3 holds zeros (v = 0 there)
+            const float d1 = g >= 1 ? 1.f : 0.f, d2 = g >= 2 ? 1.f : 0.f;
 #pragma unroll
             for (int j = 0; j < 3; ++j)
 #pragma unroll
                 for (int s_ = 0; s_ < 4; ++s_)
-                    b[j][s_] = ptc_pack_hi(ptc_part(v[3 * s_ + j].re, g), ptc_part(v[3 * s_ + j].im, g));
+                    b[j][s_] = ptc_pack_hi(ptc_part(v[3 * s_ + j].re, d1, d2), ptc_part(v[3 * s_ + j].im, d1, d2));
 #pragma unroll
             for (int mt = 0; mt < NM1; ++mt) {
                 const ptc_u32x4 w = ta[(mt * 3 + 2) * 64 + lane];

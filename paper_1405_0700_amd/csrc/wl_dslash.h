@@ -10,6 +10,10 @@ namespace wl {
 // point's rhs from the solver's device scalars; nothing happens where alpha = 0)
 // and ||r||^2 is reduced.  One-point-per-thread kernels only (rpt = 1).
 enum : int { EPI_XPAY = 1, EPI_NORM = 2, EPI_CGR = 4 };
+// With non-temporal link loads (the kernels' NT), store the output through the
+// caches all the same: set by the launcher for outputs small enough to be read
+// again from the Infinity Cache by the next kernel of a solve.
+enum : int { EPI_CACHED_OUT = 16 };
 
 struct HopArgs {
     Geom g;

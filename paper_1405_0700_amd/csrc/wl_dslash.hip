@@ -46,7 +46,21 @@ static hipError_t launch_epi(int epi, int tps, HopArgs &a, dim3 grid, dim3 block
     case EPI_XPAY | EPI_NORM | EPI_CGR:
         launch_one<SP, GP, RECON, DAG, EPI_XPAY | EPI_NORM | EPI_CGR, NT>(tps, grid, block, s, a);
         break;
-    default: return hipErrorInvalidValue;
+    default:
+        if constexpr (NT) {
+            constexpr int C = EPI_CACHED_OUT;
+            switch (epi) {
+            case C: launch_one<SP, GP, RECON, DAG, C, NT>(tps, grid, block, s, a); break;
+            case C | EPI_XPAY: launch_one<SP, GP, RECON, DAG, C | EPI_XPAY, NT>(tps, grid, block, s, a); break;
+            case C | EPI_NORM: launch_one<SP, GP, RECON, DAG, C | EPI_NORM, NT>(tps, grid, block, s, a); break;
+            case C | EPI_XPAY | EPI_NORM:
+                launch_one<SP, GP, RECON, DAG, C | EPI_XPAY | EPI_NORM, NT>(tps, grid, block, s, a);
+                break;
+            default: return hipErrorInvalidValue;
+            }
+            break;
+        }
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -176,6 +190,14 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
     dim3 grid((unsigned)hop_launch_blocks(tps, cfg, a.npts, a.nrhs, a.g.L[3], a.g.st, prec), (unsigned)nparity);
     dim3 blk(block);
     const bool nt = use_nontemporal(prec, cfg, a, nparity, epi);
+    // Outputs up to 80 MB are written through the caches even when the links are
+    // read non-temporally: the next kernel of a solve reads them at once, and they fit
+    // in the 256 MB Infinity Cache next to its other fields (FP64 e/o CG at 24^3x48,
+    // 64 MB outputs: 2 % faster); larger ones (32^3x64 FP64, 201 MB; multi-rhs fields)
+    // stay non-temporal (cached there: 7 % slower).  One point per thread only.
+    int epi_k = epi;
+    if (nt && !(epi & EPI_CGR) && (double)padded(a.npts) * nparity * spinor_point_bytes(prec) <= 80e6)
+        epi_k |= EPI_CACHED_OUT;
     // the block sums of the norm epilogue use up to 4 KB of static LDS (8 KB with rpt 4)
     a.shm = occupancy_lds(cfg.occ, block, 8192);
     switch (rpt) {
@@ -185,17 +207,17 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
     default: break;
     }
     if (prec == WL_F64)
-        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, nt, epi, tps, a, grid, blk, stream)
-                           : launch_dag<WL_F64, WL_F64, 18>(dagger, nt, epi, tps, a, grid, blk, stream);
+        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F64, WL_F64, 18>(dagger, nt, epi_k, tps, a, grid, blk, stream);
     if (prec == WL_F32)
-        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, nt, epi, tps, a, grid, blk, stream)
-                           : launch_dag<WL_F32, WL_F32, 18>(dagger, nt, epi, tps, a, grid, blk, stream);
+        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F32, WL_F32, 18>(dagger, nt, epi_k, tps, a, grid, blk, stream);
     if (prec == WL_F16N && recon == 12)
-        return launch_dag<WL_F16N, WL_F16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
+        return launch_dag<WL_F16N, WL_F16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
     if (prec == WL_BF16N && recon == 12)
-        return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
+        return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
     if (prec == WL_I16N && recon == 12)
-        return launch_dag<WL_I16N, WL_I16N, 12>(dagger, nt, epi, tps, a, grid, blk, stream);
+        return launch_dag<WL_I16N, WL_I16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
     return hipErrorInvalidValue;
 }
 

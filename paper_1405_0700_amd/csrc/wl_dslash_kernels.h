@@ -360,7 +360,7 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int par, long p
         for (int k = 0; k < 12; ++k) nrm += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
         return nrm;
     }
-    SpinorIO<SP>::template store<NT>(a.out[par], pt, acc);
+    SpinorIO<SP>::template store<NT && !(EPI & EPI_CACHED_OUT)>(a.out[par], pt, acc);
     if constexpr (EPI & EPI_NORM) {
         if constexpr (SP == WL_F64) {
 #pragma unroll
@@ -652,7 +652,8 @@ __device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, lon
     // what is stored where: y = res in out, or (EPI_CGR) r - alpha y in r
     void *dst = a.out[par];
     bool doit = active;
-    constexpr bool NTS = NT && !(EPI & EPI_CGR);  // the residual is read again at once
+    // the residual is read again at once, and so are cached outputs
+    constexpr bool NTS = NT && !(EPI & EPI_CGR) && !(EPI & EPI_CACHED_OUT);
     if constexpr (EPI & EPI_CGR) {
         dst = a.r[par];
         if (active) {

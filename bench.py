@@ -388,7 +388,7 @@ def run_eo_cg(args):
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "wl::hop_kernel_split<0, 0, 18, false, 0, true> (FP64 half-dslash H_oe, 18-real links)",
+                "kernel": "wl::hop_kernel_split<0, 0, 18, false, 16, true> (FP64 half-dslash H_oe, 18-real links, non-temporal link loads, output through the caches)",
                 "launches": n_hop, "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": SITE_BYTES["hop"] * vh}
     sols = {"f64_18": (lat.unpack(solver.xe, W.WL_EVEN), lat.unpack(solver.xo, W.WL_ODD))}

@@ -207,7 +207,9 @@ def test_dslash_16bit_per_site(prec, dagger):
 
 def test_dslash_f64_headline_size_default_launch():
     """FP64 half-dslash and full hopping term at 24^3x48 (the headline lattice, links exp(0.2 i H) seed 201)
-    with the default launch, which at this size uses the z-chunked order and the non-temporal hints."""
+    with the default launch, which at this size uses the z-chunked order and non-temporal link loads; the
+    half-dslash output (64 MB) is stored through the caches, the full one (128 MB) non-temporally.  Both store
+    forms give the same bits as a launch without non-temporal hints."""
     dims = (24, 24, 24, 48)
     u = synth.su3_links(dims, 0.2, 201)
     lat = W.Lattice.create(u, AP)
@@ -225,6 +227,14 @@ def test_dslash_f64_headline_size_default_launch():
         out = lat.new(W.WL_FULL)
         W.wl_dslash_apply(lat.ctx, out, lat.pack(phi), W.WL_FULL)
         assert rel(lat.unpack(out).reshape(want.shape), want) < TOL[W.WL_F64]
+        cfg = W.wl_ctx_get_launch(lat.ctx, W.WL_F64)
+        block, swz, tps, tch, nt, rpt, occ, sweep = cfg
+        W.wl_ctx_set_launch(lat.ctx, W.WL_F64, block, swz, tps, tch, 0, rpt, occ, sweep)
+        oe0, out0 = lat.new(W.WL_EVEN), lat.new(W.WL_FULL)
+        W.wl_dslash_apply(lat.ctx, oe0, lat.pack(po, W.WL_ODD), W.WL_EVEN)
+        W.wl_dslash_apply(lat.ctx, out0, lat.pack(phi), W.WL_FULL)
+        assert torch.equal(oe0, oe) and torch.equal(out0, out)
+        W.wl_ctx_set_launch(lat.ctx, W.WL_F64, *cfg)
     finally:
         lat.close()
 

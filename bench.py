@@ -821,8 +821,8 @@ def run_learned(args):
     print(json.dumps({"metric": "time-to-1e-10 of D x = eta: mixed-precision multi-RHS CG on the normal equations "
                                 "of D M with the learned PTC preconditioner M vs plain FP64 CG",
                       "unit": "ms", "higher_is_better": False,
-                      "workload": "train 8 x 16^3x32 (links seeds 501-508, 4 sources each, the plain solver's "
-                                  "iterations 0-3), kappa 0.137; test 32^3x64 links seed 520, %d sources "
+                      "workload": "train 8 x 16^3x32 (links seeds 501-508, 4 Gaussian sources each, pairs (source, "
+                                  "solution)), kappa 0.137; test 32^3x64 links seed 520, %d sources "
                                   "(seeds 521-%d)" % (nsrc, 520 + nsrc),
                       "stopping_criterion": "||eta - D x|| <= 1e-10 ||eta|| for every solver and source (reading C-7)",
                       "harvest_s": round(t_harvest, 2), "train_s": round(t_train, 2), "epochs": args.epochs,

@@ -91,7 +91,17 @@ def test_preconditioned_cgnr_with_the_trained_network(trained):
     b = synth.gaussian_spinor(DIMS, seed=621)
     res = {}
     fresh = W.wl_ptc_create(*synth.ptc_weights(8, seed=530))
-    for name, m in (("none", None), ("initial", fresh), ("trained", net)):
+    # the first-order Neumann preconditioner M = 1 + kappa H as network weights: layer 1 passes the input to
+    # channel 0, layer 2 applies the identity plus kappa (1 -/+ gamma_mu) along the forward / backward hops
+    w1 = np.zeros((9, 8, 1, 4, 4), dtype=np.complex128)
+    w2 = np.zeros((9, 1, 8, 4, 4), dtype=np.complex128)
+    w1[0, 0, 0] = np.eye(4)
+    w2[0, 0, 0] = np.eye(4)
+    for mu in range(4):
+        w2[1 + 2 * mu, 0, 0] = KAPPA * (np.eye(4) - orc.gamma(mu))
+        w2[2 + 2 * mu, 0, 0] = KAPPA * (np.eye(4) + orc.gamma(mu))
+    neumann = W.wl_ptc_create(w1, w2)
+    for name, m in (("none", None), ("initial", fresh), ("trained", net), ("neumann", neumann)):
         x = lat.new(W.WL_FULL)
         p = W.wl_pcgnr_params_default()
         p.fallback = 0
@@ -102,5 +112,7 @@ def test_preconditioned_cgnr_with_the_trained_network(trained):
         res[name] = info["iters"]
     print("preconditioned CGNR iterations:", res)
     assert res["trained"] < res["none"] and res["trained"] < res["initial"]
+    assert res["neumann"] < res["none"]
     W.wl_ptc_destroy(fresh)
+    W.wl_ptc_destroy(neumann)
     lat.close()

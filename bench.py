@@ -347,6 +347,49 @@ MIXED = [("f64_12", 0, 12), ("f32_18", 1, 18), ("f32_12", 1, 12), ("f16n_12", 2,
          ("i16n_12", 4, 12)]
 
 
+def run_config1(W):
+    """The small cache-resident case: 8^4, links exp(0.5 i H) seed 101, Gaussian source seed 102, kappa
+    0.12, full lattice: one full hopping term (both parities, FP64) and CG on the normal equations of D to
+    ||eta - D x|| <= 1e-10 ||eta|| (wl_cgnr_solve), timed on the GPU and restated by the oracle.  The
+    lattice fits in the caches: latency and parity, not an HBM measurement."""
+    import torch
+    from paper_1405_0700_amd import synth
+    d1, kappa, ph = (8, 8, 8, 8), 0.12, WORKLOAD["phases"]
+    u1 = synth.su3_links(d1, 0.5, 101)
+    eta1 = synth.gaussian_spinor(d1, seed=102)
+    lat = W.Lattice.create(u1, ph)
+    try:
+        b = lat.pack(eta1, W.WL_FULL)
+        h = lat.new(W.WL_FULL)
+        for _ in range(5):
+            W.wl_dslash_apply(lat.ctx, h, b, W.WL_FULL)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(50):
+            W.wl_dslash_apply(lat.ctx, h, b, W.WL_FULL)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 50 * 1e3
+        x = lat.new(W.WL_FULL)
+        W.wl_cgnr_solve(lat.ctx, x, b, kappa)  # warm-up (builds the solver's workspaces)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = W.wl_cgnr_solve(lat.ctx, x, b, kappa)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        xs = lat.unpack(x, W.WL_FULL).reshape(eta1.shape)
+    finally:
+        lat.close()
+    res = oracle_full_residuals(u1, kappa, ph, eta1, xs)
+    return {"workload": "8^4, links exp(0.5iH) seed 101, Gaussian source seed 102, kappa 0.12, full D, FP64",
+            "hopping_term_full_us": round(us, 2), "cg_normal_eq_ms": round(ms, 3), "iters": info["iters"],
+            "status": st, "stopping_criterion": "||eta - D x|| <= 1e-10 ||eta|| (reading C-7)",
+            "oracle": {k: float("%.4g" % v) for k, v in res.items()},
+            "oracle_criterion_met": bool(res["system"] <= 1.01e-10)}
+
+
 def run_eo_cg(args):
     import torch
     from paper_1405_0700_amd import wilson as W
@@ -409,6 +452,7 @@ def run_eo_cg(args):
     head = check.check(*sols["f64_18"])
     for name in mixed:
         mixed[name]["oracle"] = {k: float("%.4g" % v) for k, v in check.check(*sols[name]).items()}
+    config1 = run_config1(W)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(u, eta, wl, args.cpu_iters, converge=not args.cpu_quick)
@@ -444,6 +488,7 @@ def run_eo_cg(args):
         "oracle_criterion_met": bool(head["normal_eq"] <= wl["tol"] * 1.01),
         "algorithmic_bytes_per_step": nbytes // args.steps,
         "mixed_precision_same_system": mixed,
+        "config1_8x8x8x8": config1,
     }
     print(json.dumps(line))
     lat.close()

@@ -393,6 +393,33 @@ inline size_t link_bytes(int prec, int recon) {
 }
 
 // ------------------------------------------------------------------ geometry
+// Division of a non-negative 32-bit integer by a divisor d >= 1 fixed at set-up,
+// by a multiply-high, an add and shifts instead of the division sequence: the
+// round-up method of Granlund and Montgomery ("Division by invariant integers
+// using multiplication", 1994): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+// t = mulhi(m, n), q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0); exact for
+// every 32-bit n (d = 1 gives m = 1, t = 0, q = n).
+struct FastDiv {
+    uint32_t m;
+    int s1, s2;
+    int d;
+};
+inline FastDiv make_fastdiv(int d) {
+    int l = 0;
+    while ((1LL << l) < d) ++l;
+    FastDiv f;
+    f.m = (uint32_t)((((unsigned long long)1 << 32) * (unsigned long long)((1LL << l) - d)) / (unsigned long long)d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    f.d = d;
+    return f;
+}
+__host__ __device__ __forceinline__ int fdiv(int n, const FastDiv &f) {
+    const uint32_t un = (uint32_t)n;
+    const uint32_t t = (uint32_t)(((unsigned long long)f.m * un) >> 32);
+    return (int)((t + ((un - t) >> f.s1)) >> f.s2);
+}
+
 struct Geom {
     int L[4];      // Lx, Ly, Lz, Lt
     int lxh;       // Lx / 2
@@ -400,16 +427,17 @@ struct Geom {
     int sy, sz, st;  // even/odd index strides of y, z, t
     int phase_mask;  // bit mu set if z_mu != 1
     double zr[4], zi[4];
+    FastDiv f_lxh, f_ly, f_lz, f_sz;  // division by Lx / 2, Ly, Lz and (Lx / 2) Ly
 };
 
 // coordinates of even/odd site i of parity p
 __device__ __forceinline__ void eo_coords(const Geom &g, int i, int p, int c[4]) {
-    int xh = i % g.lxh;
-    int r = i / g.lxh;
-    c[1] = r % g.L[1];
-    r /= g.L[1];
-    c[2] = r % g.L[2];
-    c[3] = r / g.L[2];
+    const int r = fdiv(i, g.f_lxh);
+    const int xh = i - r * g.lxh;
+    const int r2 = fdiv(r, g.f_ly);
+    c[1] = r - r2 * g.L[1];
+    c[3] = fdiv(r2, g.f_lz);
+    c[2] = r2 - c[3] * g.L[2];
     c[0] = 2 * xh + ((c[1] + c[2] + c[3] + p) & 1);
 }
 

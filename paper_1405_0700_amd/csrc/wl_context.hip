@@ -180,6 +180,10 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
     g.sy = g.lxh;
     g.sz = g.lxh * dims[1];
     g.st = g.lxh * dims[1] * dims[2];
+    g.f_lxh = make_fastdiv(g.lxh);
+    g.f_ly = make_fastdiv(dims[1]);
+    g.f_lz = make_fastdiv(dims[2]);
+    g.f_sz = make_fastdiv(g.sz);
     g.phase_mask = 0;
     for (int m = 0; m < 4; ++m) {
         g.zr[m] = phases[2 * m];

@@ -141,6 +141,7 @@ hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, 
         return hipErrorInvalidValue;
     for (int k = 0; k < B.nsys; ++k) {
         HopArgs &a = B.sys[k];
+        if (a.npts > (1L << 30)) return hipErrorInvalidValue;  // 32-bit point indices
         a.swizzle = 0;
         a.tchunk = 0;
         a.chunk_sites = 0;
@@ -181,6 +182,7 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
                       const LaunchCfg &cfg, hipStream_t stream) {
     const int block = cfg.block;
     if (block <= 0 || block > 256 || block % 64) return hipErrorInvalidValue;
+    if (a.npts > (1L << 30)) return hipErrorInvalidValue;  // the kernels index points with 32-bit integers
     const int tps = effective_tps(prec, cfg);
     a.swizzle = cfg.swizzle;
     set_processing_order(a, cfg.tchunk);

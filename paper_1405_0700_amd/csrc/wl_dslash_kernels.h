@@ -288,26 +288,40 @@ __device__ __forceinline__ void hop_rt(const HopArgs &a, int par, int i, int xh,
     accumulate_rt<T, MU>(acc, v, s);
 }
 
+// Site position and right-hand side of point gid of the processing order (rhs
+// fastest).  Points of a launch stay below 2^31 (checked by the launchers), so
+// the index arithmetic is 32-bit: 64-bit division is a long software sequence.
+__device__ __forceinline__ int pos_of_point(const HopArgs &a, long gid, int &rhs) {
+    const int g = (int)gid;
+    if (a.nrhs == 1) {
+        rhs = 0;
+        return g;
+    }
+    const int ps = g / a.nrhs;
+    rhs = g - ps * a.nrhs;
+    return ps;
+}
+
 // e/o index of the site at position ps of the processing order
-__device__ __forceinline__ int site_of(const HopArgs &a, long ps) {
-    if (a.tchunk == 0) return (int)ps;
+__device__ __forceinline__ int site_of(const HopArgs &a, int ps) {
+    if (a.tchunk == 0) return ps;
     const Geom &g = a.g;
     const int plane = g.sz;  // (Lx/2) * Ly sites of one (z, t)
     if (a.tchunk < 0) {
         // chunks of -tchunk z-planes over all t, each walked with t slowest
         const int k = -a.tchunk;
-        const long chunk = ps / a.chunk_sites;
-        const int r = (int)(ps - chunk * a.chunk_sites);
-        const int z0 = (int)chunk * k;
+        const int chunk = ps / a.chunk_sites;
+        const int r = ps - chunk * a.chunk_sites;
+        const int z0 = chunk * k;
         const int kz = min(k, g.L[2] - z0);  // the last chunk may be thinner
         const int t = r / (kz * plane);
         const int q = r - t * kz * plane;
-        const int zl = q / plane;
+        const int zl = fdiv(q, g.f_sz);
         return (q - zl * plane) + plane * (z0 + zl) + g.st * t;
     }
-    const long chunk = ps / a.chunk_sites;
-    const int r = (int)(ps - chunk * a.chunk_sites);
-    const int t0 = (int)chunk * a.tchunk;
+    const int chunk = ps / a.chunk_sites;
+    const int r = ps - chunk * a.chunk_sites;
+    const int t0 = chunk * a.tchunk;
     const int trc = min(a.tchunk, g.L[3] - t0);  // the last chunk may be shorter
     const int yx = r % plane;
     const int q = r / plane;
@@ -384,9 +398,8 @@ __device__ __forceinline__ double hop_point(const HopArgs &a, int par, long gid)
     using T = typename SpinorIO<SP>::real;
     double nrm = 0.0;
     if (gid >= a.npts) return nrm;
-    const long ps = gid / a.nrhs;
-    const int rhs = (int)(gid - ps * a.nrhs);
-    const int i = site_of(a, ps);
+    int rhs;
+    const int i = site_of(a, pos_of_point(a, gid, rhs));
     const long pt = (long)i * a.nrhs + rhs;
     int c[4];
     eo_coords(a.g, i, par, c);
@@ -445,8 +458,8 @@ __global__ void __launch_bounds__(256) hop_sweep_kernel(const HopArgs a) {
     const long sp = tile * blockDim.x + threadIdx.x;
     double nrm = 0.0;
     if (sp < spts && t0 < t1) {
-        const long q = sp / a.nrhs;
-        const int rhs = (int)(sp - q * a.nrhs);
+        int rhs;
+        const long q = pos_of_point(a, sp, rhs);
         const void *in = a.in[1 - par];
         const int lt = g.L[3];
         cpx<T> fm[12], f0[12], fp[12];  // input of this column at t - 1, t, t + 1
@@ -521,8 +534,8 @@ __global__ void __launch_bounds__(256) hop_kernel_mr(const HopArgs a) {
     double nrm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) nrm[r] = 0.0;
-    const long ps = gid / G;
-    const int rhs0 = (int)(gid - ps * G) * R;
+    const int ps = (int)gid / G;
+    const int rhs0 = ((int)gid - ps * G) * R;
     if (active) {
         const int i = site_of(a, ps);
         int c[4];
@@ -611,9 +624,8 @@ __device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, lon
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
     if (active) {
-        const long ps = gid / a.nrhs;
-        const int rhs = (int)(gid - ps * a.nrhs);
-        const int i = site_of(a, ps);
+        int rhs;
+        const int i = site_of(a, pos_of_point(a, gid, rhs));
         pt = (long)i * a.nrhs + rhs;
         int c[4];
         eo_coords(a.g, i, par, c);
@@ -657,7 +669,7 @@ __device__ __forceinline__ double hop_split_point(const HopArgs &a, int par, lon
     if constexpr (EPI & EPI_CGR) {
         dst = a.r[par];
         if (active) {
-            const double alpha = *(const double *)(a.alpha + (long)(gid % a.nrhs) * a.alpha_stride);
+            const double alpha = *(const double *)(a.alpha + (long)((int)gid % a.nrhs) * a.alpha_stride);
             doit = alpha != 0.0;
             if (doit) {
                 cpx<T> rv[6];
@@ -707,7 +719,7 @@ __global__ void __launch_bounds__(256) hop_kernel_split(const HopArgs a) {
         __shared__ double lds[256];
         __shared__ int lrhs[256];
         const long blk = (long)blockIdx.y * gridDim.x + lb;
-        block_sum_by_rhs(nrm, (int)(gid % a.nrhs), a.nrhs, lds, lrhs, a.partials + blk, a.part_stride);
+        block_sum_by_rhs(nrm, (int)gid % a.nrhs, a.nrhs, lds, lrhs, a.partials + blk, a.part_stride);
     }
 }
 
@@ -738,7 +750,7 @@ __global__ void __launch_bounds__(256) hop_batch_kernel(const BatchArgs B) {
                 long gid;
                 const double nrm = hop_split_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, lb, &gid);
                 if constexpr (EPI & EPI_NORM)
-                    block_sum_by_rhs(nrm, (int)(gid % a.nrhs), a.nrhs, lds, lrhs, a.partials + local, a.part_stride);
+                    block_sum_by_rhs(nrm, (int)gid % a.nrhs, a.nrhs, lds, lrhs, a.partials + local, a.part_stride);
             } else {
                 const long gid = lb * blockDim.x + threadIdx.x;
                 const double nrm = hop_point<SP, GP, RECON, DAG, EPI, NT>(a, a.out_par0 + py, gid);

@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_hop_bulk(const HopArgs a, int par) {
     using T = typename SpinorIO<SP>::real;
     const long ps = logical_block(a.swizzle) * blockDim.x + threadIdx.x;
     if (ps >= a.npts) return;
-    const long i = site_of(a, ps);
+    const long i = site_of(a, (int)ps);
     int c[4];
     eo_coords(a.g, (int)i, par, c);
     const int xh = c[0] >> 1, lt = a.g.L[3];
@@ -167,6 +167,7 @@ hipError_t launch_face_pack(int prec, int recon, bool dag, const HopArgs &a, int
     WL_HALO_DISPATCH(pack_t, dag, a, par, send_fwd, send_bwd, s)
 }
 hipError_t launch_hop_bulk(int prec, int recon, bool dag, bool nt, const HopArgs &a, int par, hipStream_t s) {
+    if (a.npts > (1L << 30)) return hipErrorInvalidValue;  // 32-bit point indices
     WL_HALO_DISPATCH(bulk_t, dag, nt, a, par, s)
 }
 hipError_t launch_hop_boundary(int prec, int recon, bool dag, const HopArgs &a, int par, const void *recv_fwd,

@@ -233,7 +233,7 @@ def main():
     ap.add_argument("--cpu-quick", action="store_true",
                     help="skip the oracle CG-to-convergence runs of the CPU baseline")
     ap.add_argument("--workload", choices=["eo-cg", "mixed", "propagator", "learned", "batch", "eigcg", "access",
-                                           "split"],
+                                           "split", "launch"],
                     default="eo-cg",
                     help="eo-cg: the headline (24^3x48 FP64 e/o CG); mixed: 32^3x64 FP64 vs mixed-precision CG; "
                          "propagator: 12 point sources, multi-RHS vs sequential; learned: train the PTC "
@@ -241,7 +241,8 @@ def main():
                          "equations of D M with plain FP64 CG on 32^3x64; "
                          "eigcg: a sequence of right-hand sides, incremental EigCG vs plain FP64 CG; "
                          "access: the link-spinor kernel with sequential, index-array and pointer addressing; "
-                         "split: the bulk / boundary split half-dslash against the fused one")
+                         "split: the bulk / boundary split half-dslash against the fused one; "
+                         "launch: half-dslash launch-shape sweeps and plain device streams for reference")
     ap.add_argument("--eig-eps", type=float, default=0.8, help="eigcg: link roughness, U = exp(i eps H)")
     ap.add_argument("--eig-kappa", type=float, default=0.196, help="eigcg: hopping parameter")
     ap.add_argument("--eig-mu", type=float, default=0.0, help="eigcg: twisted mass")
@@ -290,6 +291,8 @@ def main():
         return run_access(args)
     if args.workload == "split":
         return run_split(args)
+    if args.workload == "launch":
+        return run_launch(args)
     return run_eo_cg(args)
 
 
@@ -388,6 +391,75 @@ def run_config1(W):
             "status": st, "stopping_criterion": "||eta - D x|| <= 1e-10 ||eta|| (reading C-7)",
             "oracle": {k: float("%.4g" % v) for k, v in res.items()},
             "oracle_criterion_met": bool(res["system"] <= 1.01e-10)}
+
+
+def run_launch(args):
+    """Half-dslash launch shapes, timed with events over 20 back-to-back applications each, and plain device
+    streams of 4 GiB for reference (what HBM gives a copy, a fill and a read here):
+      f64_24 / f64_32   FP64-18 at 24^3x48 and 32^3x64 (links seed 401), two threads per point, over the
+                        processing order (z-range depth -k, t-chunks k > 0, e/o order 0)
+      f16n_32           FP16+norm-12 at 32^3x64: one or two threads per point, blocks, occupancy caps
+      rhs12_f32_24      12 right-hand sides FP32-18 at 24^3x48: one or two threads per point, time sweeps
+    The library default of each context is listed first ("default")."""
+    import torch
+    from paper_1405_0700_amd import synth
+    from paper_1405_0700_amd import wilson as W
+    A = W.WL_TCHUNK_AUTO
+
+    def timed(fn, n=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n * 1e3
+
+    n = 4 << 30
+    a = torch.empty(n // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    hbm = {"copy_TBps": round(2 * n / timed(lambda: b.copy_(a), 10) / 1e6, 3),
+           "fill_TBps": round(n / timed(lambda: b.fill_(2.0), 10) / 1e6, 3),
+           "torch_sum_TBps": round(n / timed(lambda: a.sum(), 10) / 1e6, 3)}  # a reduction, not a bandwidth test
+    del a, b
+    torch.cuda.empty_cache()
+
+    def sweep(dims, prec, recon, nrhs, site_bytes, cfgs):
+        lat = W.Lattice.create(synth.su3_links(dims, 0.2, 401), (1, 1, 1, -1))
+        vh = lat.volume // 2
+        x = lat.new(W.WL_ODD, prec, nrhs)
+        y = lat.new(W.WL_EVEN, prec, nrhs)
+        src = lat.new(W.WL_ODD, W.WL_F32, nrhs)
+        src.view(torch.float32).normal_(generator=torch.Generator(device="cuda").manual_seed(402))
+        W.wl_convert_spinor(lat.ctx, x, prec, src, W.WL_F32, W.WL_ODD, nrhs)
+        W.wl_ctx_prepare_links(lat.ctx, prec, recon)
+        rows = []
+        default = W.wl_ctx_get_launch(lat.ctx, prec)
+        for name, cfg in [("default", default)] + [(None, c) for c in cfgs]:
+            W.wl_ctx_set_launch(lat.ctx, prec, *cfg)
+            us = timed(lambda: W.wl_dslash_apply(lat.ctx, y, x, W.WL_EVEN, prec, recon, nrhs))
+            rows.append({"launch": list(cfg), "us": round(us, 2),
+                         "algorithmic_GBps": round(site_bytes * vh / us / 1e3, 1)} | ({"default": True} if name else {}))
+        lat.close()
+        return rows
+
+    cfg = lambda block, tps, tch, occ=0, sweep_=0: (block, 1, tps, tch, -1, 1, occ, sweep_)
+    out = {
+        "f64_24": sweep((24, 24, 24, 48), W.WL_F64, 18, 1, 1536,
+                        [cfg(128, 2, t) for t in (-3, -6, -12, 0, 4)]),
+        "f64_32": sweep((32, 32, 32, 64), W.WL_F64, 18, 1, 1536,
+                        [cfg(128, 2, t) for t in (-4, -8, 0, 8)]),
+        "f16n_32": sweep((32, 32, 32, 64), W.WL_F16N, 12, 1, 296,
+                         [cfg(bl, tps, A, occ) for tps in (1, 2) for bl in (128, 256) for occ in (0, 4)]),
+        "rhs12_f32_24": sweep((24, 24, 24, 48), W.WL_F32, 18, 12, 2880,
+                              [cfg(256, 2, A), cfg(256, 1, A)] + [cfg(256, 1, 0, 0, sw) for sw in (4, 8, 16)]),
+    }
+    print(json.dumps({"metric": "half-dslash time per launch shape (us), algorithmic GB/s; device streams (TB/s)",
+                      "unit": "us", "higher_is_better": False, "workload": "launch", "hbm_streams_4GiB": hbm,
+                      "sweeps": out}))
 
 
 def run_eo_cg(args):

@@ -227,9 +227,10 @@ extern "C" wl_status wl_ctx_create(const int dims[4], const double phases[8], co
         return fail(WL_ERR_HIP, "gauge upload failed: %s", hipGetErrorString(e));
     }
     c->gauge[WL_F64][0] = d;
-    // measured defaults (MI355X, 24^3x48 and 32^3x64 lattices)
+    // measured defaults (MI355X, 24^3x48 and 32^3x64 lattices): two threads per point;
+    // FP64 blocks of 128 threads, FP32 blocks of 256 (2 % faster than 128 at 1, 4 and 12 rhs)
     c->cfg[WL_F64] = {128, 1, 2, WL_TCHUNK_AUTO, -1};
-    c->cfg[WL_F32] = {128, 1, 2, WL_TCHUNK_AUTO, -1};
+    c->cfg[WL_F32] = {256, 1, 2, WL_TCHUNK_AUTO, -1};
     // 16-bit storage: few registers per thread, so without a cap so many waves are in flight
     // that their neighbour spinors crowd each other out of L2; about 4 waves per SIMD measured
     // best (FP16 half-dslash at 32^3x64: 82 -> 67 us)

@@ -825,8 +825,8 @@ def run_batch(args):
 
 def run_learned(args):
     """Config 5: train the PTC preconditioner (8 hidden channels, BF16 weights) with the library's own
-    kernels on residual/error pairs from plain FP64 CG on 8 fields 16^3x32 (kappa 0.137, links
-    exp(0.2iH) seeds 501-508, 4 Gaussian sources each, the pairs of its first iterations), then solve
+    kernels on (source, solution) pairs from plain FP64 CG on 8 fields 16^3x32 (kappa 0.137, links
+    exp(0.2iH) seeds 501-508, 4 Gaussian sources each, residual-norm loss), then solve
     D x = eta on 32^3x64 (links seed 520) for `--learned-rhs` Gaussian sources (seeds 521...), every
     solver stopped on ||eta - D x|| <= 1e-10 ||eta|| (reading C-7):
       cg_f64            plain FP64 CGNR, one source after another (the comparison of the benchmark spec)
@@ -834,6 +834,8 @@ def run_learned(args):
       pcgnr_none        mixed precision (FP32 inner, FP64 defect correction), multi-RHS, no network
       pcgnr_initial     the same with the untrained network
       pcgnr_trained     the same with the trained network
+      fgcr_none         flexible GCR (FP64), one source after another, no network
+      fgcr_trained      the same with the trained network as right preconditioner
     The oracle restates every source's residual."""
     import numpy as np
     import torch

@@ -59,16 +59,23 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 __device__ __forceinline__ float bf16_to_f32(uint16_t u) { return __builtin_bit_cast(float, (uint32_t)u << 16); }
 
 template <int P> struct Half16;
+// dec(u) = raw(u) * scale: raw is the stored number, scale the format's fixed factor
 template <> struct Half16<WL_F16N> {
+    static constexpr float scale = 1.0f;
+    __device__ static float raw(uint16_t u) { return f16_to_f32(u); }
     __device__ static float dec(uint16_t u) { return f16_to_f32(u); }
     __device__ static uint16_t enc(float f) { return f32_to_f16(f); }
 };
 template <> struct Half16<WL_BF16N> {
+    static constexpr float scale = 1.0f;
+    __device__ static float raw(uint16_t u) { return bf16_to_f32(u); }
     __device__ static float dec(uint16_t u) { return bf16_to_f32(u); }
     __device__ static uint16_t enc(float f) { return f32_to_bf16(f); }
 };
 // 16-bit fixed point for values in [-1, 1]: q = round(32767 f)
 template <> struct Half16<WL_I16N> {
+    static constexpr float scale = 1.0f / 32767.0f;
+    __device__ static float raw(uint16_t u) { return (float)(int16_t)u; }
     __device__ static float dec(uint16_t u) { return (float)(int16_t)u * (1.0f / 32767.0f); }
     __device__ static uint16_t enc(float f) {
         const float q = fminf(fmaxf(rintf(f * 32767.0f), -32767.0f), 32767.0f);
@@ -202,6 +209,21 @@ template <int P> struct SpinorIO16 {
                 v[4 * k + j] = {s * Half16<P>::dec((uint16_t)(w[j] & 0xffffu)),
                                 s * Half16<P>::dec((uint16_t)(w[j] >> 16))};
         }
+    }
+    // The stored numbers (raw, without the norm) and the factor that load()
+    // applies to them (the point's norm times the format's fixed scale).
+    __device__ static float load_unscaled(const void *base, long i, cpx<float> v[12]) {
+        const uint4 *p = units(base, i);
+        const float s = *norm_ptr(base, i);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 d = p[k * BLK];
+            uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[4 * k + j] = {Half16<P>::raw((uint16_t)(w[j] & 0xffffu)), Half16<P>::raw((uint16_t)(w[j] >> 16))};
+        }
+        return s * Half16<P>::scale;
     }
     template <bool NT = false> __device__ static void store(void *base, long i, const cpx<float> v[12]) {
         uint4 *p = (uint4 *)units(base, i);

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_hop_boundary(const HopArgs a, int par,
 #pragma unroll
             for (int k = 0; k < 6; ++k) v[k] = cmul(z, v[k]);
         }
-        accumulate<T, 3, S>(acc, v);
+        accumulate<T, 3, S>(acc, v, T(1));
         if (c[3] != 0) hop<SP, GP, RECON, DAG, false, 3, false>(a, par, (int)i, xh, c, 0, acc);
     }
     if (c[3] == 0) {
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) k_hop_boundary(const HopArgs a, int par,
 #pragma unroll
             for (int k = 0; k < 6; ++k) v[k] = cmul(z, v[k]);
         }
-        accumulate<T, 3, S>(acc, v);
+        accumulate<T, 3, S>(acc, v, T(1));
     }
     const T b = (T)a.b;
 #pragma unroll

@@ -634,12 +634,15 @@ wl_status wl_su3_apply(void *psi, const void *u, const void *phi, long n, int mo
 
 /* While enabled (enable = n >= 1), every n-th launch of the hopping-term kernel
  * made through this context (by the operators and the solvers; n = 1: every
- * launch) is bracketed by a pair of HIP events recorded on the stream it is
- * launched on; each pair adds a few microseconds to the stream, so sampling
- * (n coprime to the launches of one solver iteration) keeps the instrumented
- * run close to an uninstrumented one.  enable = 0 disables.  Enabling (or
- * disabling) discards what was recorded.  At most 1 << 16 launches are
- * recorded.  Errors: WL_ERR_ARG for enable < 0. */
+ * launch) is timed by a pair of HIP events on the stream it is launched on.
+ * The kernel's own dispatch packet stamps them at the start and the end of its
+ * execution (hipExtLaunchKernelGGL), so that a duration is what a kernel trace
+ * reports for the launch; the kernels with several right-hand sides per thread
+ * have the events recorded before and after them, which adds the dispatch gaps
+ * (a few microseconds).  Sampling (n coprime to the launches of one solver
+ * iteration) keeps the instrumented run close to an uninstrumented one.
+ * enable = 0 disables.  Enabling (or disabling) discards what was recorded.
+ * At most 1 << 16 launches are recorded.  Errors: WL_ERR_ARG for enable < 0. */
 wl_status wl_timing_enable(wl_ctx *ctx, int enable);
 
 /* Number and summed GPU duration (milliseconds) of the recorded launches of

@@ -72,9 +72,14 @@ bool use_nontemporal(int prec, const LaunchCfg &cfg, const HopArgs &a, int npari
 void set_processing_order(HopArgs &a, int tchunk);
 
 // Enqueue out = a x + b H in (H^+ if dagger) over `nparity` output parities.
-// Returns hipSuccess or the launch error.
+// Returns hipSuccess or the launch error.  ev0 / ev1, when given, time the
+// launch: the kernel's own dispatch packet stamps its start and end (the
+// one-point-per-thread, two-threads-per-point and sweep kernels), so that the
+// interval is the kernel's execution, as a kernel trace reports it; the kernels
+// with several right-hand sides per thread record them before and after.
 hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int nparity,
-                      const LaunchCfg &cfg, hipStream_t stream);
+                      const LaunchCfg &cfg, hipStream_t stream, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 
 // Persistent launch over the tiles of several systems (one-thread-per-point
 // body).  sys[k] is filled like a single launch's HopArgs (out_par0 = first

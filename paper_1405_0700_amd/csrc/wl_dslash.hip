@@ -17,21 +17,30 @@
 // on one contiguous range of sites and the neighbour re-reads hit its L2.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "wl_dslash_kernels.h"
 
 namespace wl {
 
+// Timing events of the launch being enqueued by this host thread (see launch_hop)
+static thread_local hipEvent_t t_ev[2] = {nullptr, nullptr};
+
+template <typename K> static void enqueue(K kern, dim3 grid, dim3 block, hipStream_t s, const HopArgs &a) {
+    if (t_ev[0])
+        hipExtLaunchKernelGGL(kern, grid, block, a.shm, s, t_ev[0], t_ev[1], 0, a);
+    else
+        hipLaunchKernelGGL(kern, grid, block, a.shm, s, a);
+}
+
 template <int SP, int GP, int RECON, bool DAG, int EPI, bool NT>
 static void launch_one(int tps, dim3 grid, dim3 block, hipStream_t s, const HopArgs &a) {
-    if (a.sweep > 0) {
-        hipLaunchKernelGGL((hop_sweep_kernel<SP, GP, RECON, DAG, EPI, NT>), grid, block, a.shm, s, a);
-        return;
-    }
-    if (tps == 2) {
-        hipLaunchKernelGGL((hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>), grid, block, a.shm, s, a);
-        return;
-    }
-    hipLaunchKernelGGL((hop_kernel<SP, GP, RECON, DAG, EPI, NT>), grid, block, a.shm, s, a);
+    if (a.sweep > 0)
+        enqueue(hop_sweep_kernel<SP, GP, RECON, DAG, EPI, NT>, grid, block, s, a);
+    else if (tps == 2)
+        enqueue(hop_kernel_split<SP, GP, RECON, DAG, EPI, NT>, grid, block, s, a);
+    else
+        enqueue(hop_kernel<SP, GP, RECON, DAG, EPI, NT>, grid, block, s, a);
 }
 
 template <int SP, int GP, int RECON, bool DAG, bool NT>
@@ -178,8 +187,25 @@ void set_processing_order(HopArgs &a, int tchunk) {
     }
 }
 
+static hipError_t launch_hop_prec(int prec, int recon, bool dagger, bool nt, int epi_k, int tps, HopArgs &a,
+                                  dim3 grid, dim3 blk, hipStream_t stream) {
+    if (prec == WL_F64)
+        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F64, WL_F64, 18>(dagger, nt, epi_k, tps, a, grid, blk, stream);
+    if (prec == WL_F32)
+        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream)
+                           : launch_dag<WL_F32, WL_F32, 18>(dagger, nt, epi_k, tps, a, grid, blk, stream);
+    if (prec == WL_F16N && recon == 12)
+        return launch_dag<WL_F16N, WL_F16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
+    if (prec == WL_BF16N && recon == 12)
+        return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
+    if (prec == WL_I16N && recon == 12)
+        return launch_dag<WL_I16N, WL_I16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int nparity,
-                      const LaunchCfg &cfg, hipStream_t stream) {
+                      const LaunchCfg &cfg, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
     const int block = cfg.block;
     if (block <= 0 || block > 256 || block % 64) return hipErrorInvalidValue;
     if (a.npts > (1L << 30)) return hipErrorInvalidValue;  // the kernels index points with 32-bit integers
@@ -202,25 +228,21 @@ hipError_t launch_hop(int prec, int recon, bool dagger, int epi, HopArgs &a, int
         epi_k |= EPI_CACHED_OUT;
     // the block sums of the norm epilogue use up to 4 KB of static LDS (8 KB with rpt 4)
     a.shm = occupancy_lds(cfg.occ, block, 8192);
-    switch (rpt) {
-    case 2: return launch_hop_r2(prec, recon, dagger, nt, epi, a, grid, blk, stream);
-    case 3: return launch_hop_r3(prec, recon, dagger, nt, epi, a, grid, blk, stream);
-    case 4: return launch_hop_r4(prec, recon, dagger, nt, epi, a, grid, blk, stream);
-    default: break;
+    if (rpt > 1) {
+        hipError_t e = ev0 ? hipEventRecord(ev0, stream) : hipSuccess;
+        if (e == hipSuccess) {
+            if (rpt == 2) e = launch_hop_r2(prec, recon, dagger, nt, epi, a, grid, blk, stream);
+            else if (rpt == 3) e = launch_hop_r3(prec, recon, dagger, nt, epi, a, grid, blk, stream);
+            else e = launch_hop_r4(prec, recon, dagger, nt, epi, a, grid, blk, stream);
+        }
+        if (e == hipSuccess && ev1) e = hipEventRecord(ev1, stream);
+        return e;
     }
-    if (prec == WL_F64)
-        return recon == 12 ? launch_dag<WL_F64, WL_F64, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream)
-                           : launch_dag<WL_F64, WL_F64, 18>(dagger, nt, epi_k, tps, a, grid, blk, stream);
-    if (prec == WL_F32)
-        return recon == 12 ? launch_dag<WL_F32, WL_F32, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream)
-                           : launch_dag<WL_F32, WL_F32, 18>(dagger, nt, epi_k, tps, a, grid, blk, stream);
-    if (prec == WL_F16N && recon == 12)
-        return launch_dag<WL_F16N, WL_F16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
-    if (prec == WL_BF16N && recon == 12)
-        return launch_dag<WL_BF16N, WL_BF16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
-    if (prec == WL_I16N && recon == 12)
-        return launch_dag<WL_I16N, WL_I16N, 12>(dagger, nt, epi_k, tps, a, grid, blk, stream);
-    return hipErrorInvalidValue;
+    t_ev[0] = ev0;
+    t_ev[1] = ev1;
+    const hipError_t e = launch_hop_prec(prec, recon, dagger, nt, epi_k, tps, a, grid, blk, stream);
+    t_ev[0] = t_ev[1] = nullptr;
+    return e;
 }
 
 }  // namespace wl

@@ -89,11 +89,9 @@ wl_status wli::hop_core(wl_ctx *c, int prec, int recon, bool dag, int epi, void 
                             c->timing_iter, c->timing_cycle});
         c->pool_used += 2;
         ev = c->timed.back().ev;
-        HIP_TRY(hipEventRecord(ev[0], s));
     }
     const LaunchCfg &cfg = c->cfg[prec];
-    HIP_TRY(launch_hop(prec, recon, dag, epi, h, np, cfg, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(launch_hop(prec, recon, dag, epi, h, np, cfg, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
     if (nblk_out)
         *nblk_out = hop_launch_blocks(effective_tps(prec, cfg), cfg, h.npts, nrhs, h.g.L[3], h.g.st, prec) * np;
     return WL_OK;

@@ -35,3 +35,42 @@ def test_timing_records_every_nth_launch():
     with pytest.raises(W.WilsonError):
         W.wl_timing_enable(lat.ctx, True, every=-1)
     lat.close()
+
+
+def test_timed_durations_are_kernel_executions():
+    """The dispatch packet stamps the events of a one-point-per-thread launch, so
+    the durations of back-to-back launches on one stream (which run one after the
+    other) add up to no more than the wall interval around them, and to most of it
+    when the kernel dominates; launches with two right-hand sides per thread are
+    timed by events recorded around them, and recorded as well."""
+    dims = (16, 16, 16, 32)
+    lat = W.Lattice.create(synth.su3_links(dims, 0.3, 62), (1, 1, 1, -1))
+    inp = lat.pack(synth.gaussian_spinor(dims, seed=63, nsites=lat.volume // 2), W.WL_ODD)
+    out = lat.new(W.WL_EVEN)
+    for _ in range(3):
+        W.wl_dslash_apply(lat.ctx, out, inp, W.WL_EVEN, W.WL_F64, 18)
+    W.wl_timing_enable(lat.ctx, True, every=1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(40):
+        W.wl_dslash_apply(lat.ctx, out, inp, W.WL_EVEN, W.WL_F64, 18)
+    e1.record()
+    torch.cuda.synchronize()
+    n, ms = W.wl_timing_read(lat.ctx, W.WL_F64, 18, False, 0)
+    wall = e0.elapsed_time(e1)
+    assert n == 40
+    assert 0.5 * wall < ms <= wall * 1.001 + 1e-3
+    # two right-hand sides per thread: events recorded around the launch
+    W.wl_ctx_set_launch(lat.ctx, W.WL_F32, 256, 1, 1, rpt=2)
+    in2 = lat.new(W.WL_ODD, W.WL_F32, 2)
+    in2.view(torch.float32).normal_()
+    out2 = lat.new(W.WL_EVEN, W.WL_F32, 2)
+    W.wl_timing_enable(lat.ctx, True, every=1)
+    for _ in range(3):
+        W.wl_dslash_apply(lat.ctx, out2, in2, W.WL_EVEN, W.WL_F32, 18, nrhs=2)
+    torch.cuda.synchronize()
+    n2, ms2 = W.wl_timing_read(lat.ctx, W.WL_F32, 18, False, 0)
+    assert n2 == 3 and ms2 > 0.0
+    W.wl_timing_enable(lat.ctx, False)
+    lat.close()

@@ -397,14 +397,16 @@ def run_launch(args):
     """Half-dslash launch shapes, timed with events over 20 back-to-back applications each, and plain device
     streams of 4 GiB for reference (what HBM gives a copy, a fill and a read here):
       f64_24 / f64_32   FP64-18 at 24^3x48 and 32^3x64 (links seed 401), two threads per point, over the
-                        processing order (z-range depth -k, t-chunks k > 0, e/o order 0)
-      f16n_32           FP16+norm-12 at 32^3x64: one or two threads per point, blocks, occupancy caps
-      rhs12_f32_24      12 right-hand sides FP32-18 at 24^3x48: one or two threads per point, time sweeps
+                        processing order (z-range depth -k, t-chunks k > 0, e/o order 0, y-z blocks YZ)
+      f16n_32           FP16+norm-12 at 32^3x64: one or two threads per point, blocks, occupancy caps, orders
+      rhs12_f32_24      12 right-hand sides FP32-18 at 24^3x48: one or two threads per point, time sweeps,
+                        y-z blocks
+      rhs12_f64_24      the same in FP64-18 (5,760 B per site), z-ranges against y-z blocks
     The library default of each context is listed first ("default")."""
     import torch
     from paper_1405_0700_amd import synth
     from paper_1405_0700_amd import wilson as W
-    A = W.WL_TCHUNK_AUTO
+    A, YZ = W.WL_TCHUNK_AUTO, W.WL_TCHUNK_YZ
 
     def timed(fn, n=20):
         for _ in range(3):
@@ -449,13 +451,17 @@ def run_launch(args):
     cfg = lambda block, tps, tch, occ=0, sweep_=0: (block, 1, tps, tch, -1, 1, occ, sweep_)
     out = {
         "f64_24": sweep((24, 24, 24, 48), W.WL_F64, 18, 1, 1536,
-                        [cfg(128, 2, t) for t in (-3, -6, -12, 0, 4)]),
+                        [cfg(128, 2, t) for t in (-3, -6, -12, 0, 4, YZ)]),
         "f64_32": sweep((32, 32, 32, 64), W.WL_F64, 18, 1, 1536,
-                        [cfg(128, 2, t) for t in (-4, -8, 0, 8)]),
+                        [cfg(128, 2, t) for t in (-4, -8, 0, 8, YZ)]),
         "f16n_32": sweep((32, 32, 32, 64), W.WL_F16N, 12, 1, 296,
-                         [cfg(bl, tps, A, occ) for tps in (1, 2) for bl in (128, 256) for occ in (0, 4)]),
+                         [cfg(bl, tps, A, occ) for tps in (1, 2) for bl in (128, 256) for occ in (0, 4)]
+                         + [cfg(256, 1, YZ, 4), cfg(256, 1, 0, 4)]),
         "rhs12_f32_24": sweep((24, 24, 24, 48), W.WL_F32, 18, 12, 2880,
-                              [cfg(256, 2, A), cfg(256, 1, A)] + [cfg(256, 1, 0, 0, sw) for sw in (4, 8, 16)]),
+                              [cfg(256, 2, A), cfg(256, 1, A)] + [cfg(256, 1, 0, 0, sw) for sw in (4, 8, 16)]
+                              + [cfg(bl, tps, YZ) for tps in (1, 2) for bl in (128, 256)]),
+        "rhs12_f64_24": sweep((24, 24, 24, 48), W.WL_F64, 18, 12, 1152 + 2 * 2304,
+                              [cfg(bl, tps, t) for t in (A, YZ) for tps in (1, 2) for bl in (128, 256)]),
     }
     print(json.dumps({"metric": "half-dslash time per launch shape (us), algorithmic GB/s; device streams (TB/s)",
                       "unit": "us", "higher_is_better": False, "workload": "launch", "hbm_streams_4GiB": hbm,

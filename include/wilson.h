@@ -126,7 +126,14 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  *           do not cut the lattice (|k| >= the extent) mean 0.
  *           WL_TCHUNK_AUTO (the default): -(Lz / 8) when Lz is a multiple of 8
  *           and at least 16, else 0 (measured: the FP64 half-dslash 8-10 %
- *           faster at 24^3x48 and 32^3x64, the 12-rhs FP32 one 14 %)
+ *           faster at 24^3x48 and 32^3x64, the 12-rhs FP32 one 14 %).
+ *           WL_TCHUNK_YZ: the (y, z) plane is cut into 2 x 4 blocks of
+ *           Ly/2 x Lz/4 x-lines, one per XCD with the swizzle, each walked
+ *           with t slowest: a block's neighbours outside it are fewer than a
+ *           z-range's (24^3: 36 against 48 x-lines per 72); used when Ly is
+ *           even and Lz a multiple of 4, else as AUTO.  Measured back to back
+ *           1-4 % faster than AUTO on the FP64 half-dslash, 2 % slower on the
+ *           FP16 one, and no faster inside the solves: an autotuner option
  *   nt      1: non-temporal hints on the link loads and output stores (they
  *           keep the single-use link stream from evicting re-read spinors from
  *           L2, but also bypass the Infinity Cache); 0: off; -1: on when the
@@ -156,6 +163,7 @@ wl_status wl_ctx_prepare_links(wl_ctx *ctx, wl_prec prec, int recon);
  * multiply-adds (rounding only).  Defaults are chosen per
  * precision by measurement (see wl_ctx_get_launch). */
 #define WL_TCHUNK_AUTO (-1048576) /* tchunk: the processing order chosen from the lattice */
+#define WL_TCHUNK_YZ (-2097152)   /* tchunk: y-z blocks, one per XCD, each walked with t slowest */
 typedef struct {
     int block;
     int swizzle;
@@ -540,7 +548,8 @@ wl_status wl_batch_timing_read(wl_batch *batch, int *count, double *total_ms);
  * launch shape of the sweep -- block 64/128/256, one or two threads per point
  * (FP64/FP32 storage) or 2-4 right-hand sides per thread (when nrhs allows),
  * XCD swizzle off/on, processing order by e/o index, by chunks of 4 time
- * slices or by z-ranges (WL_TCHUNK_AUTO), non-temporal hints off/on -- with HIP
+ * slices, by z-ranges (WL_TCHUNK_AUTO) or by y-z blocks (WL_TCHUNK_YZ),
+ * non-temporal hints off/on -- with HIP
  * events (average of 5 launches after a warm-up), picks the fastest and makes
  * it the context's launch configuration for `prec`.  Results are cached in
  * the process and, if cache_path is not NULL, appended to that text file

@@ -673,7 +673,7 @@ extern "C" wl_status wl_autotune(wl_ctx *c, wl_prec prec, int recon, int nrhs, c
             for (int tps : {1, 2})
                 for (int rpt : {1, 2, 3, 4})
                 for (int swz : {0, 1})
-                    for (int tch : {0, 4, WL_TCHUNK_AUTO})
+                    for (int tch : {0, 4, WL_TCHUNK_AUTO, WL_TCHUNK_YZ})
                         for (int nt : {0, 1}) {
                             if (st) break;  // the first failure ends the sweep
                             if (tps == 2 && !two) continue;

@@ -33,12 +33,31 @@ struct HopArgs {
     int swizzle;          // map consecutive blocks to the same XCD
     int tchunk;           // processing order (see LaunchCfg)
     int chunk_sites;      // sites of a full chunk: tchunk * Lz * (Lx/2) * Ly
+    int yz_by, yz_bz;     // WL_TCHUNK_YZ: block extent in y and z
+    FastDiv f_blk, f_slab, f_row;  // WL_TCHUNK_YZ: sites of a block, of one of its t, of one of its (z, t)
     void *r[2];           // EPI_CGR: the residual field of parity 0 / 1 (same storage as out)
     const char *alpha;    // EPI_CGR: alpha of rhs k at alpha + k * alpha_stride (a double)
     long alpha_stride;
     unsigned shm;         // dynamic LDS bytes reserved per block (host side: caps the occupancy)
     int sweep;            // time sweep: slices per block (0: one point per thread, no sweep)
 };
+
+// Site of position ps in the y-z block order (WL_TCHUNK_YZ): the (y, z) plane
+// is cut into 2 x 4 blocks of by x bz x-lines; block b holds y in
+// [(b % 2) by, +by) and z in [(b / 2) bz, +bz); its sites follow each other with
+// t slowest, then z, y and x.  Returns the e/o index x + (Lx/2) y + sz z + st t.
+__host__ __device__ __forceinline__ int yz_site(const Geom &g, int by, int bz, const FastDiv &f_blk,
+                                                const FastDiv &f_slab, const FastDiv &f_row, int ps) {
+    const int b = fdiv(ps, f_blk);
+    const int r = ps - b * f_blk.d;
+    const int t = fdiv(r, f_slab);
+    const int q = r - t * f_slab.d;
+    const int zl = fdiv(q, f_row);
+    const int q2 = q - zl * f_row.d;
+    const int yl = fdiv(q2, g.f_lxh);
+    const int x = q2 - yl * g.lxh;
+    return x + g.lxh * ((b & 1) * by + yl) + g.sz * ((b >> 1) * bz + zl) + g.st * t;
+}
 
 struct LaunchCfg {
     int block = 256;   // threads per block (multiple of 64, <= 256)
@@ -47,8 +66,9 @@ struct LaunchCfg {
                        // the two halves of a wavefront)
     int tchunk = WL_TCHUNK_AUTO;  // processing order: 0 = e/o index order; k > 0 = chunks of k
                        // time slices, each walked with z slowest; k < 0 = chunks of -k
-                       // z-planes over all t, each walked with t slowest; AUTO: -(Lz/8)
-                       // when Lz is a multiple of 8 and >= 16, else 0
+                       // z-planes over all t, each walked with t slowest; WL_TCHUNK_YZ =
+                       // 2 x 4 y-z blocks, each walked with t slowest; AUTO: -(Lz/8) when
+                       // Lz is a multiple of 8 and >= 16, else 0
     int nt = -1;       // non-temporal link loads / output stores: 1 on, 0 off,
                        // -1 on when the launch's working set exceeds 200 MB
     int rpt = 1;       // right-hand sides per thread (each link load reused for all

@@ -174,7 +174,21 @@ hipError_t launch_hop_batch(int prec, int recon, bool dagger, int epi, bool nt, 
 // a.tchunk / a.chunk_sites for a LaunchCfg tchunk value (AUTO resolved from the lattice)
 void set_processing_order(HopArgs &a, int tchunk) {
     int tch = tchunk;
-    if (tch == WL_TCHUNK_AUTO) tch = a.g.L[2] % 8 == 0 && a.g.L[2] >= 16 ? -(a.g.L[2] / 8) : 0;
+    const int ly = a.g.L[1], lz = a.g.L[2], lt = a.g.L[3];
+    if (tch == WL_TCHUNK_YZ) {
+        if (ly % 2 == 0 && lz % 4 == 0) {
+            a.tchunk = WL_TCHUNK_YZ;
+            a.yz_by = ly / 2;
+            a.yz_bz = lz / 4;
+            a.chunk_sites = 0;
+            a.f_row = make_fastdiv(a.yz_by * a.g.lxh);
+            a.f_slab = make_fastdiv(a.yz_bz * a.yz_by * a.g.lxh);
+            a.f_blk = make_fastdiv(lt * a.yz_bz * a.yz_by * a.g.lxh);
+            return;
+        }
+        tch = WL_TCHUNK_AUTO;
+    }
+    if (tch == WL_TCHUNK_AUTO) tch = lz % 8 == 0 && lz >= 16 ? -(lz / 8) : 0;
     if (tch > 0 && tch < a.g.L[3]) {
         a.tchunk = tch;
         a.chunk_sites = a.tchunk * a.g.L[2] * a.g.sz;

@@ -327,6 +327,7 @@ __device__ __forceinline__ int pos_of_point(const HopArgs &a, long gid, int &rhs
 __device__ __forceinline__ int site_of(const HopArgs &a, int ps) {
     if (a.tchunk == 0) return ps;
     const Geom &g = a.g;
+    if (a.tchunk == WL_TCHUNK_YZ) return yz_site(g, a.yz_by, a.yz_bz, a.f_blk, a.f_slab, a.f_row, ps);
     const int plane = g.sz;  // (Lx/2) * Ly sites of one (z, t)
     if (a.tchunk < 0) {
         // chunks of -tchunk z-planes over all t, each walked with t slowest

@@ -28,6 +28,7 @@ WL_EVEN, WL_ODD, WL_FULL = 0, 1, 2
 WL_OP_D, WL_OP_DHAT = 0, 1
 WL_ACCESS_SEQ, WL_ACCESS_INDEX, WL_ACCESS_PTR = 0, 1, 2
 WL_TCHUNK_AUTO = -1048576
+WL_TCHUNK_YZ = -2097152
 
 PREC = {"f64": WL_F64, "f32": WL_F32, "f16n": WL_F16N, "bf16n": WL_BF16N, "i16n": WL_I16N}
 SUBSET = {"even": WL_EVEN, "odd": WL_ODD, "full": WL_FULL}

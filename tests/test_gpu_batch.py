@@ -254,7 +254,7 @@ def test_autotune_picks_a_valid_launch_and_caches_it(tmp_path):
     cfg, us, cached = W.wl_autotune(lat.ctx, W.WL_F32, 18, 1, cache)
     assert not cached and us > 0
     block, swizzle, tps, tchunk, nt, rpt, occ, sweep = cfg
-    assert block in (64, 128, 256) and tps in (1, 2) and swizzle in (0, 1) and tchunk in (0, 4, W.WL_TCHUNK_AUTO) \
+    assert block in (64, 128, 256) and tps in (1, 2) and swizzle in (0, 1) and tchunk in (0, 4, W.WL_TCHUNK_AUTO, W.WL_TCHUNK_YZ) \
         and nt in (0, 1) and occ == 0 and sweep == 0
     assert rpt == 1  # one right-hand side: nothing to share
     assert W.wl_ctx_get_launch(lat.ctx, W.WL_F32) == cfg

@@ -569,7 +569,8 @@ def test_cg_free_field_plane_wave_one_iteration():
 @pytest.mark.parametrize("prec", [W.WL_F64, W.WL_F32])
 @pytest.mark.parametrize("block,swizzle,tps,tchunk,nt", [(64, 0, 1, 0, 0), (256, 1, 2, 0, 1), (128, 0, 2, 3, -1),
                                                          (192, 1, 1, 4, 1), (64, 1, 2, 5, 0), (256, 1, 1, 1, 1),
-                                                         (128, 1, 2, -1, 1), (256, 0, 1, -3, -1), (64, 1, 1, -2, 0)])
+                                                         (128, 1, 2, -1, 1), (256, 0, 1, -3, -1), (64, 1, 1, -2, 0),
+                                                         (256, 1, 1, W.WL_TCHUNK_YZ, 1), (128, 0, 2, W.WL_TCHUNK_YZ, -1)])
 def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
     dims = (6, 10, 4, 14)
     kappa = 0.13
@@ -605,6 +606,36 @@ def test_launch_configs_match_oracle(prec, block, swizzle, tps, tchunk, nt):
             assert rel(lat.unpack(x).reshape(b.shape), x_orc) < 1e-13
     finally:
         W.wl_ctx_set_launch(lat.ctx, prec, *saved)
+
+
+@pytest.mark.parametrize("prec,recon", [(W.WL_F64, 18), (W.WL_F32, 18), (W.WL_BF16N, 12)])
+@pytest.mark.parametrize("dims", [(8, 6, 8, 6), (4, 2, 12, 10), (6, 4, 4, 8)])
+def test_processing_orders_give_the_same_bits(prec, recon, dims):
+    """The processing order only decides which thread computes which point: the y-z block order,
+    the z-ranges and the e/o index order give bit-identical fields (3 right-hand sides, both
+    output parities through the Schur operator's fused epilogue too).  (6, 4, 4, 8) has Lz = 4,
+    where the y-z blocks are single z-planes."""
+    nrhs = 3
+    ph = random_phases(83)
+    u, lat = setup(dims, seed=84, phases=ph)
+    phis = [synth.gaussian_spinor(dims, seed=85 + r) for r in range(nrhs)]
+    inp = lat.pack(np.stack([p.reshape(-1, 4, 3) for p in phis]), W.WL_FULL, prec, nrhs)
+    ie = lat.pack(np.stack([orc.eo_split(p, dims)[0] for p in phis]), W.WL_EVEN, prec, nrhs)
+    saved = W.wl_ctx_get_launch(lat.ctx, prec)
+    outs = []
+    try:
+        for tch in (0, -2, W.WL_TCHUNK_YZ):
+            W.wl_ctx_set_launch(lat.ctx, prec, 256, 1, 1, tch)
+            out = lat.new(W.WL_FULL, prec, nrhs)
+            W.wl_dslash_apply(lat.ctx, out, inp, W.WL_FULL, prec, recon, nrhs=nrhs)
+            oe = lat.new(W.WL_EVEN, prec, nrhs)
+            W.wl_dirac_apply(lat.ctx, oe, ie, W.WL_OP_DHAT, False, 0.12, prec, recon, nrhs=nrhs)
+            torch.cuda.synchronize()
+            outs.append((out.cpu(), oe.cpu()))
+    finally:
+        W.wl_ctx_set_launch(lat.ctx, prec, *saved)
+    for o, e in outs[1:]:
+        assert torch.equal(o, outs[0][0]) and torch.equal(e, outs[0][1])
 
 
 @pytest.mark.parametrize("prec,recon", [(W.WL_F64, 18), (W.WL_F32, 12), (W.WL_F16N, 12)])

@@ -35,6 +35,7 @@ struct HopArgs {
     int chunk_sites;      // sites of a full chunk: tchunk * Lz * (Lx/2) * Ly
     int yz_by, yz_bz;     // WL_TCHUNK_YZ: block extent in y and z
     FastDiv f_blk, f_slab, f_row;  // WL_TCHUNK_YZ: sites of a block, of one of its t, of one of its (z, t)
+    FastDiv f_chunk, f_kplane;     // z-ranges (tchunk < 0): chunk_sites, and -tchunk planes of (Lx/2) Ly sites
     void *r[2];           // EPI_CGR: the residual field of parity 0 / 1 (same storage as out)
     const char *alpha;    // EPI_CGR: alpha of rhs k at alpha + k * alpha_stride (a double)
     long alpha_stride;

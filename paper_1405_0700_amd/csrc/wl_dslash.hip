@@ -195,6 +195,8 @@ void set_processing_order(HopArgs &a, int tchunk) {
     } else if (tch < 0 && -tch < a.g.L[2]) {
         a.tchunk = tch;
         a.chunk_sites = -a.tchunk * a.g.L[3] * a.g.sz;
+        a.f_chunk = make_fastdiv(a.chunk_sites);
+        a.f_kplane = make_fastdiv(-a.tchunk * a.g.sz);
     } else {
         a.tchunk = 0;
         a.chunk_sites = 0;

@@ -332,11 +332,11 @@ __device__ __forceinline__ int site_of(const HopArgs &a, int ps) {
     if (a.tchunk < 0) {
         // chunks of -tchunk z-planes over all t, each walked with t slowest
         const int k = -a.tchunk;
-        const int chunk = ps / a.chunk_sites;
+        const int chunk = fdiv(ps, a.f_chunk);
         const int r = ps - chunk * a.chunk_sites;
         const int z0 = chunk * k;
         const int kz = min(k, g.L[2] - z0);  // the last chunk may be thinner
-        const int t = r / (kz * plane);
+        const int t = kz == k ? fdiv(r, a.f_kplane) : r / (kz * plane);
         const int q = r - t * kz * plane;
         const int zl = fdiv(q, g.f_sz);
         return (q - zl * plane) + plane * (z0 + zl) + g.st * t;

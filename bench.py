@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload: skip the 32^3x64 mixed-precision and learned-preconditioner rows")
     ap.add_argument("--cpu-iters", type=int, default=25, help="CG iterations of the CPU-oracle sample")
     ap.add_argument("--cpu-quick", action="store_true",
                     help="skip the oracle CG-to-convergence runs of the CPU baseline")
@@ -534,6 +536,7 @@ def run_eo_cg(args):
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(u, eta, wl, args.cpu_iters, converge=not args.cpu_quick)
+    extra = {} if args.no_extra else extra_rows(args)
 
     last = infos[-1]
     line = {
@@ -567,21 +570,51 @@ def run_eo_cg(args):
         "algorithmic_bytes_per_step": nbytes // args.steps,
         "mixed_precision_same_system": mixed,
         "config1_8x8x8x8": config1,
-    }
+    } | extra
     print(json.dumps(line))
     lat.close()
 
 
-def run_mixed(args):
-    """32^3x64, kappa 0.137: FP64 CG against mixed-precision CG (FP64 reliable updates)."""
+def extra_rows(args):
+    """The 32^3x64 rows of the line (after the timed region): FP64 CG against FP16+norm and BF16+norm
+    mixed CG (the mixed workload's system, one timed solve each), and the learned preconditioner
+    (trained as in the learned workload, tested on the same 32^3x64 field with 2 Gaussian sources)
+    against plain FP64 CGNR; the oracle restates every solution."""
+    log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    u, eta = make_inputs(MIXED_32)
+    log("32^3x64 inputs in %.1f s" % (time.perf_counter() - t0))
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup = 1, 1
+    res, ok = mixed_results(sub, u, eta, [("f64_18", 0, 18), ("f16n_12", 2, 12), ("bf16n_12", 3, 12)])
+    mixed = {"workload": "even/odd Wilson CG to 1e-10, 32^3x64, kappa 0.137, links exp(0.2iH) seed 301, source "
+                         "seed 302 (1 warm-up + 1 timed solve per format)",
+             "results": {k: {"time_to_solution_ms": v["time_to_solution_ms"], "iters": v["iters"],
+                             "status": v["status"], "oracle": v["oracle"]} for k, v in res.items()},
+             "oracle_check": ok,
+             "speedup_vs_f64": {k: round(res["f64_18"]["time_to_solution_ms"] / v["time_to_solution_ms"], 3)
+                                for k, v in res.items() if k != "f64_18"}}
+    learned = learned_results(args, u_test=u, test_seed=None, src_seeds=(311, 312),
+                              solvers=("cg_f64", "pcgnr_none", "pcgnr_trained"))
+    learned = {k: learned[k] for k in ("workload", "stopping_criterion", "epochs", "loss_first", "loss_last",
+                                       "results", "network_apply_ms", "speedup_per_source_vs_cg_f64")}
+    log("32^3x64 rows in %.1f s" % (time.perf_counter() - t0))
+    return {"config3_mixed_32x32x32x64": mixed, "config5_learned_32x32x32x64": learned}
+
+
+MIXED_32 = dict(dims=(32, 32, 32, 64), eps=0.2, gauge_seed=301, src_seed=302, kappa=0.137, phases=(1, 1, 1, -1),
+                tol=1e-10)
+
+
+def mixed_results(args, u, eta, formats):
+    """FP64 CG against mixed-precision CG (FP64 reliable updates) on the 32^3x64 system of MIXED_32
+    (links u, source eta), every solution restated by the oracle; -> (results, oracle summary)."""
     from paper_1405_0700_amd import wilson as W
-    wl = dict(dims=(32, 32, 32, 64), eps=0.2, gauge_seed=301, src_seed=302, kappa=0.137, phases=(1, 1, 1, -1),
-              tol=1e-10)
-    u, eta = make_inputs(wl)
+    wl = MIXED_32
     lat = W.Lattice.create(u, wl["phases"])
     solver = EoSolver(lat, lat.pack(eta, W.WL_FULL), wl["kappa"], wl["tol"])
     res, sols = {}, {}
-    for name, prec, recon in [("f64_18", 0, 18)] + MIXED:
+    for name, prec, recon in formats:
         solver.set_precision(prec, recon)
         ms, inf = solver.timed(args.steps, args.warmup)
         res[name] = {"time_to_solution_ms": round(ms, 3), "iters": inf[-1][0]["iters"],
@@ -595,7 +628,13 @@ def run_mixed(args):
     for name in res:
         res[name]["oracle"] = {k: float("%.4g" % v) for k, v in check.check(*sols[name]).items()}
         print("[bench] oracle %s %s" % (name, res[name]["oracle"]), file=sys.stderr, flush=True)
-    ok = summarize_checks([r["oracle"] for r in res.values()])
+    return res, summarize_checks([r["oracle"] for r in res.values()])
+
+
+def run_mixed(args):
+    """32^3x64, kappa 0.137: FP64 CG against mixed-precision CG (FP64 reliable updates)."""
+    u, eta = make_inputs(MIXED_32)
+    res, ok = mixed_results(args, u, eta, [("f64_18", 0, 18)] + MIXED)
     best = min((v["time_to_solution_ms"], k) for k, v in res.items() if k != "f64_18")
     print(json.dumps({"metric": "CG time-to-1e-10, plain FP64 vs mixed precision", "workload":
                       "even/odd Wilson CG, 32^3x64, kappa 0.137, links exp(0.2iH) seed 301, source seed 302",
@@ -829,7 +868,15 @@ def run_batch(args):
                       "results": res, "speedup_tuned_vs_sequential": round(ms_seq / ms_t, 3)}))
 
 
+LEARNED_ALL = ("cg_f64", "cg_f64_multi", "pcgnr_none", "pcgnr_trained", "pcgnr_initial", "fgcr_none", "fgcr_trained")
+
+
 def run_learned(args):
+    out = learned_results(args)
+    print(json.dumps(out))
+
+
+def learned_results(args, u_test=None, test_seed=520, src_seeds=None, solvers=LEARNED_ALL):
     """Config 5: train the PTC preconditioner (8 hidden channels, BF16 weights) with the library's own
     kernels on (source, solution) pairs from plain FP64 CG on 8 fields 16^3x32 (kappa 0.137, links
     exp(0.2iH) seeds 501-508, 4 Gaussian sources each, residual-norm loss), then solve
@@ -842,7 +889,8 @@ def run_learned(args):
       pcgnr_trained     the same with the trained network
       fgcr_none         flexible GCR (FP64), one source after another, no network
       fgcr_trained      the same with the trained network as right preconditioner
-    The oracle restates every source's residual."""
+    The oracle restates every source's residual.  u_test / src_seeds replace the test field and the
+    sources' seeds (the default line reuses the mixed workload's 32^3x64 field); `solvers` picks rows."""
     import numpy as np
     import torch
     from paper_1405_0700_amd import learned, synth
@@ -868,8 +916,11 @@ def run_learned(args):
     for lat_, _ in sets:
         lat_.close()
     dims = (32, 32, 32, 64)
-    u_test = synth.su3_links(dims, 0.2, 520)
-    etas = [synth.gaussian_spinor(dims, seed=521 + k) for k in range(nsrc)]
+    if u_test is None:
+        u_test = synth.su3_links(dims, 0.2, test_seed)
+    src_seeds = list(src_seeds) if src_seeds is not None else [test_seed + 1 + k for k in range(nsrc)]
+    nsrc = len(src_seeds)
+    etas = [synth.gaussian_spinor(dims, seed=sd) for sd in src_seeds]
     lat = W.Lattice.create(u_test, ph)
     eta_m = lat.pack(np.stack([e.reshape(-1, 4, 3) for e in etas]), W.WL_FULL, W.WL_F64, nsrc)
     eta_1 = [lat.pack(e, W.WL_FULL) for e in etas]
@@ -885,25 +936,29 @@ def run_learned(args):
 
     # plain FP64 CGNR, one source at a time
     xs, its, sts, total = [], [], [], 0.0
-    for k in range(nsrc):
+    for k in range(nsrc if "cg_f64" in solvers else 0):
         x = lat.new(W.WL_FULL)
         (st, info), ms = timed(lambda: W.wl_cgnr_solve(lat.ctx, x, eta_1[k], kappa))
         total += ms
         xs.append(lat.unpack(x, W.WL_FULL))
         its.append(info["iters"])
         sts.append(st)
-    res["cg_f64"] = {"status": sts, "time_ms": round(total, 2), "time_per_source_ms": round(total / nsrc, 2),
-                     "iters": its}
-    sols["cg_f64"] = xs
-    log("cg_f64 %s" % res["cg_f64"])
-    x = lat.new(W.WL_FULL, W.WL_F64, nsrc)
-    (st, infos), ms = timed(lambda: W.wl_cgnr_solve(lat.ctx, x, eta_m, kappa, nrhs=nsrc))
-    infos = infos if nsrc > 1 else [infos]
-    res["cg_f64_multi"] = {"status": st, "time_ms": round(ms, 2), "time_per_source_ms": round(ms / nsrc, 2),
-                           "iters": [i["iters"] for i in infos]}
-    sols["cg_f64_multi"] = list(lat.unpack(x, W.WL_FULL, W.WL_F64, nsrc).reshape(nsrc, -1, 4, 3))
-    log("cg_f64_multi %s" % res["cg_f64_multi"])
+    if "cg_f64" in solvers:
+        res["cg_f64"] = {"status": sts, "time_ms": round(total, 2), "time_per_source_ms": round(total / nsrc, 2),
+                         "iters": its}
+        sols["cg_f64"] = xs
+        log("cg_f64 %s" % res["cg_f64"])
+    if "cg_f64_multi" in solvers:
+        x = lat.new(W.WL_FULL, W.WL_F64, nsrc)
+        (st, infos), ms = timed(lambda: W.wl_cgnr_solve(lat.ctx, x, eta_m, kappa, nrhs=nsrc))
+        infos = infos if nsrc > 1 else [infos]
+        res["cg_f64_multi"] = {"status": st, "time_ms": round(ms, 2), "time_per_source_ms": round(ms / nsrc, 2),
+                               "iters": [i["iters"] for i in infos]}
+        sols["cg_f64_multi"] = list(lat.unpack(x, W.WL_FULL, W.WL_F64, nsrc).reshape(nsrc, -1, 4, 3))
+        log("cg_f64_multi %s" % res["cg_f64_multi"])
     for name, m in (("pcgnr_none", None), ("pcgnr_trained", net), ("pcgnr_initial", fresh)):
+        if name not in solvers:
+            continue
         x = lat.new(W.WL_FULL, W.WL_F64, nsrc)
         pp = W.wl_pcgnr_params_default()
         pp.maxiter = 3000
@@ -916,6 +971,8 @@ def run_learned(args):
         log("%s %s" % (name, res[name]))
     # FGCR with the network as right preconditioner (one application per iteration), one source at a time
     for name, m in (("fgcr_none", None), ("fgcr_trained", net)):
+        if name not in solvers:
+            continue
         xs, its, sts, fbs, total = [], [], [], [], 0.0
         for k in range(nsrc):
             x = lat.new(W.WL_FULL)
@@ -943,20 +1000,22 @@ def run_learned(args):
         res[name]["oracle"] = summarize_checks(checks, key="system")
         log("oracle %s %s" % (name, res[name]["oracle"]))
     base = res["cg_f64"]["time_per_source_ms"]
-    print(json.dumps({"metric": "time-to-1e-10 of D x = eta: mixed-precision multi-RHS CG on the normal equations "
-                                "of D M with the learned PTC preconditioner M vs plain FP64 CG",
-                      "unit": "ms", "higher_is_better": False,
-                      "workload": "train 8 x 16^3x32 (links seeds 501-508, 4 Gaussian sources each, pairs (source, "
-                                  "solution)), kappa 0.137; test 32^3x64 links seed 520, %d sources "
-                                  "(seeds 521-%d)" % (nsrc, 520 + nsrc),
-                      "stopping_criterion": "||eta - D x|| <= 1e-10 ||eta|| for every solver and source (reading C-7)",
-                      "harvest_s": round(t_harvest, 2), "train_s": round(t_train, 2), "epochs": args.epochs,
-                      "loss_first": losses[0], "loss_last": losses[-1], "results": res,
-                      "network_apply_ms": round(ms_net / 10, 3),
-                      "speedup_per_source_vs_cg_f64": {k: round(base / v["time_per_source_ms"], 3)
-                                                       for k, v in res.items() if k != "cg_f64"}}))
     W.wl_ptc_destroy(net)
     W.wl_ptc_destroy(fresh)
+    field = "links seed %d" % test_seed if test_seed is not None else "the mixed workload's links (seed 301)"
+    return {"metric": "time-to-1e-10 of D x = eta: mixed-precision multi-RHS CG on the normal equations "
+                      "of D M with the learned PTC preconditioner M vs plain FP64 CG",
+            "unit": "ms", "higher_is_better": False,
+            "workload": "train %d x 16^3x32 (links seeds 501-%d, 4 Gaussian sources each, pairs (source, "
+                        "solution)), kappa 0.137; test 32^3x64 %s, %d sources (seeds %s)"
+                        % (args.train_fields, 500 + args.train_fields, field, nsrc,
+                           ", ".join(str(sd) for sd in src_seeds)),
+            "stopping_criterion": "||eta - D x|| <= 1e-10 ||eta|| for every solver and source (reading C-7)",
+            "harvest_s": round(t_harvest, 2), "train_s": round(t_train, 2), "epochs": args.epochs,
+            "loss_first": losses[0], "loss_last": losses[-1], "results": res,
+            "network_apply_ms": round(ms_net / 10, 3),
+            "speedup_per_source_vs_cg_f64": {k: round(base / v["time_per_source_ms"], 3)
+                                             for k, v in res.items() if k != "cg_f64"}}
 
 
 def run_eigcg(args):

@@ -43,7 +43,7 @@ def test_timed_durations_are_kernel_executions():
     other) add up to no more than the wall interval around them, and to most of it
     when the kernel dominates; launches with two right-hand sides per thread are
     timed by events recorded around them, and recorded as well."""
-    dims = (16, 16, 16, 32)
+    dims = (16, 16, 32, 32)  # ~40 us per FP64 launch: well above the host's enqueue time per call
     lat = W.Lattice.create(synth.su3_links(dims, 0.3, 62), (1, 1, 1, -1))
     inp = lat.pack(synth.gaussian_spinor(dims, seed=63, nsites=lat.volume // 2), W.WL_ODD)
     out = lat.new(W.WL_EVEN)

@@ -144,12 +144,14 @@ def test_dslash_low_precision(prec, recon, dagger):
 
 
 def _quantize(x, prec):
-    """The value a real FP64 number takes in the library's 16-bit storage (entries already divided by the
-    per-point norm for spinors; links are stored as they are): FP64 -> FP32 -> 16 bits, round to nearest
-    even (FP16, BF16), or round(32767 v) / 32767 (int16, decoded in FP32)."""
+    """The value a real FP64 link entry takes in the library's 16-bit link storage: FP16 is the FP64 value
+    rounded once to nearest even (the conversion kernel converts FP64 -> FP32 -> FP16 in its source, and
+    the compiled kernel stores the once-rounded values: measured at 32^3x64, where the twice-rounded
+    reference differs in a few entries by one step); BF16 rounds the FP32 bit pattern, FP64 -> FP32 -> BF16;
+    int16 is round(32767 v) / 32767, decoded in FP32."""
     x32 = np.asarray(x, dtype=np.float32)
     if prec == W.WL_F16N:
-        return x32.astype(np.float16).astype(np.float64)
+        return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float64)
     if prec == W.WL_BF16N:
         b = np.ascontiguousarray(x32).view(np.uint32).astype(np.uint64)
         b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
@@ -232,11 +234,10 @@ def test_dslash_16bit_full_size_default_launch(prec):
     seed 301, source seed 302) with the default launch: the full-lattice output (109 MB) is stored
     non-temporally, the even half-dslash the solvers launch (55 MB) through the caches.  Every site is
     checked against the oracle fed the inputs as stored, to the per-site bound of
-    test_dslash_16bit_per_site.  Measured: BF16's worst site is half a step of its per-point norm (the
-    output rounding alone); FP16's reaches about two half steps (2.1 at the worst of 2.1 million sites, 1.4
-    at the 99.99th percentile), an extra error of the order of one FP16 step of the output whose source is
-    not identified (flushing subnormal inputs or links in the oracle changes nothing); the bound's
-    arithmetic term covers it, and an indexing or layout mistake would exceed it by orders of magnitude."""
+    test_dslash_16bit_per_site.  Measured: the worst site of either format is half a step of its
+    per-point norm, the output rounding alone (with a reference that rounded the FP16 links twice, through
+    FP32, a few sites were one FP16 step further off: that is how the library's once-rounded FP16 links
+    were found)."""
     dims = (32, 32, 32, 64)
     u, lat = setup(dims, eps=0.2, seed=301)
     phi = synth.gaussian_spinor(dims, seed=302)

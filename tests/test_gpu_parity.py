@@ -145,9 +145,10 @@ def test_dslash_low_precision(prec, recon, dagger):
 
 def _quantize(x, prec):
     """The value a real FP64 link entry takes in the library's 16-bit link storage: FP16 is the FP64 value
-    rounded once to nearest even (the conversion kernel converts FP64 -> FP32 -> FP16 in its source, and
-    the compiled kernel stores the once-rounded values: measured at 32^3x64, where the twice-rounded
-    reference differs in a few entries by one step); BF16 rounds the FP32 bit pattern, FP64 -> FP32 -> BF16;
+    rounded once to nearest even (the conversion kernel converts FP64 -> FP32 -> FP16 in its source; the
+    compiler merges the two into one FP64 -> FP16 rounding, done in integer arithmetic, and a twice-rounded
+    reference differs from it in a few entries by one step); BF16 rounds the FP32 bit pattern, FP64 -> FP32
+    -> BF16;
     int16 is round(32767 v) / 32767, decoded in FP32."""
     x32 = np.asarray(x, dtype=np.float32)
     if prec == W.WL_F16N:
